@@ -1,0 +1,157 @@
+"""Seeded synthetic particle sets for the octree build.
+
+This module is shared by the tests, the benchmark, the oracle checks and the
+GPU path as the single source of input data. It holds none of the method's
+arithmetic (no keys, sorting or trees): it only draws particle coordinates.
+
+Every generator is deterministic in (seed, stream): numpy's Philox4x32-10
+counter-based bit generator keyed by the seed, with the stream number as the
+counter's starting block, so any set can be regenerated on its own.
+
+Recipes (shapes of the workloads the octree build is measured on):
+  * uniform cube: x, y, z i.i.d. uniform in [0, 1), each drawn as
+    (u64 >> 11) * 2^-53 so every value is an exact double;
+  * Plummer sphere (scale radius a, truncated at r_t): radius by inverting the
+    cumulative mass M(r) = r^3 / (a^2 + r^2)^(3/2) on X ~ U(0, M(r_t)), then an
+    isotropic direction (cos(theta) = 2u - 1, phi = 2 pi v);
+  * Gaussian displacement: every coordinate moved by N(0, sigma^2).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+UNIT_BOX = ((0.0, 0.0, 0.0), (1.0, 1.0, 1.0))
+PLUMMER_RT = 20.0
+PLUMMER_BOX = ((-PLUMMER_RT,) * 3, (PLUMMER_RT,) * 3)
+
+_STREAM_STRIDE = 1 << 40  # Philox blocks reserved per stream
+
+
+def _gen(seed: int, stream: int = 0) -> np.random.Generator:
+    bg = np.random.Philox(key=int(seed))
+    if stream:
+        bg = bg.advance(int(stream) * _STREAM_STRIDE)
+    return np.random.Generator(bg)
+
+
+def _unit_doubles(g: np.random.Generator, n: int) -> np.ndarray:
+    raw = g.bit_generator.random_raw(n)
+    return (raw >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+def uniform_cube(n: int, seed: int, stream: int = 0):
+    """n particles i.i.d. uniform in [0, 1)^3 (x, y, z float64 arrays)."""
+    g = _gen(seed, stream)
+    u = _unit_doubles(g, 3 * n)
+    return u[0::3].copy(), u[1::3].copy(), u[2::3].copy()
+
+
+def plummer_sphere(n: int, seed: int, stream: int = 0, a: float = 1.0, r_t: float = PLUMMER_RT):
+    """n particles from a Plummer sphere of scale radius a truncated at r_t."""
+    g = _gen(seed, stream)
+    u = _unit_doubles(g, 3 * n)
+    x_max = r_t ** 3 / (a * a + r_t * r_t) ** 1.5
+    X = (u[0::3] * x_max).clip(1e-300, None)
+    r = a / np.sqrt(X ** (-2.0 / 3.0) - 1.0)
+    cos_t = 2.0 * u[1::3] - 1.0
+    sin_t = np.sqrt(np.maximum(0.0, 1.0 - cos_t * cos_t))
+    phi = 2.0 * math.pi * u[2::3]
+    return r * sin_t * np.cos(phi), r * sin_t * np.sin(phi), r * cos_t
+
+
+def gaussian_displace(x, y, z, sigma: float, seed: int, stream: int):
+    """Copy of (x, y, z) with every coordinate moved by N(0, sigma^2)."""
+    g = _gen(seed, stream)
+    d = g.standard_normal(3 * x.size) * sigma
+    return x + d[0::3], y + d[1::3], z + d[2::3]
+
+
+@dataclass(frozen=True)
+class ParticleSet:
+    """One tree-build instance: particles, bounding box, curve, N_crit."""
+    x: np.ndarray
+    y: np.ndarray
+    z: np.ndarray
+    box: tuple
+    curve: int  # 0 Morton, 1 Hilbert
+    n_crit: int
+    kind: str
+
+    @property
+    def n(self) -> int:
+        return int(self.x.size)
+
+
+MORTON, HILBERT = 0, 1
+
+
+def make_set(kind: str, n: int, seed: int, stream: int, curve: int, n_crit: int) -> ParticleSet:
+    if kind == "uniform":
+        x, y, z = uniform_cube(n, seed, stream)
+        box = UNIT_BOX
+    elif kind == "plummer":
+        x, y, z = plummer_sphere(n, seed, stream)
+        box = PLUMMER_BOX
+    else:
+        raise ValueError(kind)
+    return ParticleSet(x, y, z, box, curve, n_crit, kind)
+
+
+# ---- The measured configurations ------------------------------------------
+
+def config_small(seed: int = 1) -> ParticleSet:
+    """65,536 uniform particles, Morton keys, N_crit = 64."""
+    return make_set("uniform", 1 << 16, seed, 0, MORTON, 64)
+
+
+def config_uniform_2_24(seed: int = 2, n: int = 1 << 24) -> ParticleSet:
+    """2^24 uniform particles, Hilbert keys, N_crit = 64 (the benchmarked build)."""
+    return make_set("uniform", n, seed, 0, HILBERT, 64)
+
+
+def config_plummer(seed: int = 3, n: int = 1 << 27) -> ParticleSet:
+    """2^27 Plummer particles (a = 1, r_t = 20), Hilbert keys, N_crit = 16."""
+    return make_set("plummer", n, seed, 0, HILBERT, 16)
+
+
+def plummer_rebuild_steps(s: ParticleSet, steps: int = 10, sigma: float = 1e-3, seed: int = 3):
+    """Cumulative Gaussian displacements of a Plummer set, one per rebuild."""
+    x, y, z = s.x, s.y, s.z
+    for k in range(1, steps + 1):
+        x, y, z = gaussian_displace(x, y, z, sigma, seed, k)
+        yield ParticleSet(x, y, z, s.box, s.curve, s.n_crit, s.kind)
+
+
+def batched_specs(count: int = 512, seed: int = 4, log2_min: float = 10.0, log2_max: float = 20.0):
+    """Per-instance (kind, n, curve, n_crit, stream) for the batched workload:
+    sizes floor(2^U), U ~ U[log2_min, log2_max]; uniform or Plummer and Morton or
+    Hilbert by coin flip; N_crit from {8, 16, 32, 64, 128}."""
+    g = _gen(seed, 0)
+    U = g.uniform(log2_min, log2_max, count)
+    kinds = g.integers(0, 2, count)
+    curves = g.integers(0, 2, count)
+    ncrits = np.array([8, 16, 32, 64, 128])[g.integers(0, 5, count)]
+    return [("plummer" if kinds[s] else "uniform", int(2.0 ** U[s]), int(curves[s]), int(ncrits[s]), s + 1)
+            for s in range(count)]
+
+
+def batched_sets(count: int = 512, seed: int = 4, **kw):
+    return [make_set(kind, n, seed, stream, curve, nc) for kind, n, curve, nc, stream in
+            batched_specs(count, seed, **kw)]
+
+
+def serving_specs(count: int = 10000, seed: int = 5, log2_min: float = 12.0, log2_max: float = 22.0):
+    """Per-request (kind, n, n_crit, stream, interarrival_unit) for the serving
+    workload: sizes floor(2^U), U ~ U[log2_min, log2_max]; uniform or Plummer;
+    Hilbert keys; N_crit in {16, 64}; unit-mean exponential inter-arrival gaps
+    (scaled by the caller to the chosen arrival rate)."""
+    g = _gen(seed, 0)
+    U = g.uniform(log2_min, log2_max, count)
+    kinds = g.integers(0, 2, count)
+    ncrits = np.array([16, 64])[g.integers(0, 2, count)]
+    gaps = g.exponential(1.0, count)
+    return [("plummer" if kinds[s] else "uniform", int(2.0 ** U[s]), int(ncrits[s]), s + 1, float(gaps[s]))
+            for s in range(count)]
