@@ -1,0 +1,197 @@
+/*
+ * cstone.h — C ABI of the MI355X (gfx950) Cornerstone octree build.
+ *
+ * Implements the single-GPU octree construction of Keller et al.,
+ * "Cornerstone: Octree Construction Algorithms for Scalable Particle
+ * Simulations" (PASC '23): SFC keys (Sec. 3), the sorted key array P with its
+ * particle permutation (Sec. 4, Table 1), leaf counts f (Eq. histogram), the
+ * iterated rebalance g = g3.g2.g1 (Eqs. g1-g3, rebalancecopy, rebalancesplit)
+ * and the fully linked octree NK / CO / LO (Sec. 5).
+ *
+ * Conventions shared by every call
+ *   - L = 21: keys are uint64 in [0, 8^21) = [0, 2^63); 8^21 = 2^63 closes every
+ *     cornerstone array (Eq. cstone). Counts, permutation, CO and LO are uint32,
+ *     so n < 2^32.
+ *   - All array pointers are DEVICE pointers owned by the caller unless marked
+ *     "host". The library keeps no pointer after a call returns and never
+ *     allocates device memory: scratch comes from the caller's workspace `ws`,
+ *     sized by the matching *_workspace_bytes() query (any 256-byte aligned
+ *     device buffer of at least that size; its contents on entry do not matter).
+ *   - Every call enqueues its work on `stream`. Calls that return results on the
+ *     host (cstone_rebalance, cstone_build) synchronise `stream` before
+ *     returning; the others are asynchronous.
+ *   - Functions return a cstone_status and never abort. Output arrays are
+ *     unspecified after an error unless stated otherwise.
+ *   - Overlapping calls that share one workspace race; give concurrent calls on
+ *     different streams their own workspaces.
+ */
+#ifndef CSTONE_H
+#define CSTONE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Every entry point below is exported from libcstone.so; nothing else is. */
+#define CSTONE_API __attribute__((visibility("default")))
+
+typedef enum cstone_status {
+    CSTONE_OK = 0,
+    CSTONE_ERR_INVALID_ARG = 1,   /* null pointer, n >= 2^32, n_crit == 0, bad box, short workspace */
+    CSTONE_ERR_NONFINITE = 2,     /* a coordinate is NaN or infinite */
+    CSTONE_ERR_CAPACITY = 3,      /* the next cornerstone array would exceed leaf_capacity */
+    CSTONE_ERR_NOT_CONVERGED = 4, /* max_iters rounds ran and some leaf still changed */
+    CSTONE_ERR_DEVICE = 5,        /* a HIP runtime error, or a device-side wait gave up */
+} cstone_status;
+
+typedef enum cstone_curve {
+    CSTONE_MORTON = 0,  /* Morton Z-curve; x is the most significant bit of each octal digit */
+    CSTONE_HILBERT = 1, /* Skilling's 3D Hilbert curve, x most significant; key 0 at the origin */
+} cstone_curve;
+
+/* Axis-aligned bounding box (host struct): lo[d] < hi[d], all finite. */
+typedef struct cstone_box {
+    double lo[3];
+    double hi[3];
+} cstone_box;
+
+/* Bit OR-ed into the optional device flag word of cstone_compute_keys. */
+#define CSTONE_FLAG_NONFINITE 1u
+
+/* Number of entries of the level-offset array LO (Sec. 5: L + 2). */
+#define CSTONE_LEVEL_OFFSETS 23
+
+/* Human-readable name of a status code (static string). */
+CSTONE_API const char* cstone_status_string(cstone_status status);
+
+/* ------------------------------------------------------------------------
+ * Keys (Sec. 3). For every particle p, the coordinates are mapped to the
+ * integer grid [0, 2^21)^3 by t = (c - lo) * (2^21 / (hi - lo)) in IEEE double
+ * (one rounding per operation, no contraction), clamped to [0, 2^21 - 1] and
+ * truncated; NaN maps to 0 and +Inf to 2^21 - 1. The grid point is encoded on
+ * the chosen curve into keys[p].
+ *   x, y, z   device, n doubles each (structure of arrays)
+ *   box       host, bounding box
+ *   keys      device, n uint64 (output)
+ *   flags     device, one uint32 or NULL; CSTONE_FLAG_NONFINITE is OR-ed in if
+ *             any coordinate is NaN or infinite (the word is not cleared).
+ * Asynchronous. Errors: INVALID_ARG, DEVICE.
+ */
+CSTONE_API cstone_status cstone_compute_keys(const double* x, const double* y, const double* z, size_t n,
+                                  const cstone_box* box, cstone_curve curve, uint64_t* keys,
+                                  uint32_t* flags, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Sort (Sec. 4, Table 1: radix sort_by_key with the identity permutation as
+ * values). Stable LSD radix sort: keys_out[i] = keys_in[perm_out[i]],
+ * keys_out non-decreasing, equal keys in ascending original index.
+ *   keys_in   device, n uint64 (not modified; may not alias the outputs)
+ *   keys_out  device, n uint64;  perm_out  device, n uint32
+ *   ws        device workspace of cstone_sort_workspace_bytes(n) bytes
+ * Asynchronous. Errors: INVALID_ARG, DEVICE.
+ */
+CSTONE_API size_t cstone_sort_workspace_bytes(size_t n);
+CSTONE_API cstone_status cstone_sort(const uint64_t* keys_in, uint64_t* keys_out, uint32_t* perm_out, size_t n,
+                          void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Leaf counts f (Eq. histogram): counts[i] = number of keys of the sorted array
+ * in [leaves[i], leaves[i+1]), as the difference of two binary-search
+ * positions.
+ *   sorted_keys  device, n uint64, non-decreasing
+ *   leaves       device, n_leaves + 1 uint64, a cornerstone array
+ *   counts       device, n_leaves uint32 (output)
+ * Asynchronous. Errors: INVALID_ARG, DEVICE.
+ */
+CSTONE_API cstone_status cstone_node_counts(const uint64_t* sorted_keys, size_t n, const uint64_t* leaves,
+                                 size_t n_leaves, uint32_t* counts, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Rebalance loop (Sec. 4): alternate f and g = g3.g2.g1 until no leaf is
+ * split or merged (O_i = 1 for all i), starting from the cornerstone array in
+ * `leaves`. A leaf splits if it holds more than n_crit particles and spans
+ * more than one key; 8 sibling leaves merge if their counts sum to at most
+ * n_crit; the root never merges. From the single root leaf {0, 8^21} the result
+ * is the unique balanced array (leaf counts <= n_crit, internal node counts >
+ * n_crit).
+ *   sorted_keys  device, n uint64, non-decreasing
+ *   leaves       device, leaf_capacity + 1 uint64; in: the start array (a
+ *                previous step's result; with *n_leaves == 1 the root array
+ *                {0, 2^63} is written here), out: the final array
+ *   n_leaves     host, in: leaves in the start array (>= 1), out: final count
+ *                (on CAPACITY: the count the next round needed)
+ *   counts       device, leaf_capacity uint32 (output: final leaf counts), or NULL
+ *   max_iters    rounds allowed (0 means 22 = L + 1)
+ *   iters_done   host, rounds run (a round is one f + one g), or NULL
+ *   ws           device workspace of cstone_rebalance_workspace_bytes() bytes
+ * Synchronises `stream`. Errors: INVALID_ARG; CAPACITY (leaves keep the last
+ * array that fitted, *n_leaves is the count the next round needed);
+ * NOT_CONVERGED (leaves hold the array after max_iters rounds, a valid
+ * cornerstone array); DEVICE.
+ */
+CSTONE_API size_t cstone_rebalance_workspace_bytes(size_t leaf_capacity);
+CSTONE_API cstone_status cstone_rebalance(const uint64_t* sorted_keys, size_t n, uint32_t n_crit, uint64_t* leaves,
+                               size_t* n_leaves, size_t leaf_capacity, uint32_t* counts,
+                               uint32_t max_iters, uint32_t* iters_done, void* ws, size_t ws_bytes,
+                               hipStream_t stream);
+
+/* Leaf capacity that a rebalance of n particles can never exceed: every round
+ * from the root only splits, and a balanced tree has at most
+ * floor(n / (n_crit + 1)) internal nodes per level, so 7 * 21 * that + 1;
+ * starting from an array of n_leaves_start leaves, one round adds at most 7 per
+ * over-full leaf on top of it. */
+CSTONE_API size_t cstone_leaf_capacity_bound(size_t n, uint32_t n_crit, size_t n_leaves_start);
+
+/* ------------------------------------------------------------------------
+ * Fully linked octree (Sec. 5). n = n_leaves + (n_leaves - 1) / 7 nodes.
+ *   node_keys      device, n uint64: every node in Warren-Salmon placeholder-bit
+ *                  form (a 1 bit followed by the node's level octal digits),
+ *                  ascending = breadth-first (level-major, SFC order within a level)
+ *   child          device, n uint32: index of the first of the node's 8
+ *                  contiguous children, 0 for a leaf (CO)
+ *   level_offsets  device, 23 uint32: index of the first node of each level
+ *                  0..21, then n (LO)
+ *   ws             device workspace of cstone_link_workspace_bytes(n_leaves) bytes
+ * Asynchronous. Errors: INVALID_ARG, DEVICE.
+ */
+CSTONE_API size_t cstone_node_count(size_t n_leaves);
+CSTONE_API size_t cstone_link_workspace_bytes(size_t n_leaves);
+CSTONE_API cstone_status cstone_link_octree(const uint64_t* leaves, size_t n_leaves, uint64_t* node_keys, uint32_t* child,
+                                 uint32_t* level_offsets, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Whole build: keys -> sort -> rebalance loop -> link, on one stream.
+ *   x, y, z, box, curve      as cstone_compute_keys
+ *   n_crit                   maximum particles per leaf (>= 1)
+ *   sorted_keys, perm        device, n each: P and the particle permutation
+ *   leaves, n_leaves, leaf_capacity, counts, max_iters, iters_done
+ *                            as cstone_rebalance; *n_leaves == 0 on entry means
+ *                            "start from the root leaf", otherwise `leaves`
+ *                            holds the previous cornerstone array to start from
+ *   node_keys, child         device, cstone_node_count(leaf_capacity) entries each,
+ *                            or both NULL to skip linking
+ *   level_offsets            device, 23 uint32 (ignored when node_keys is NULL)
+ *   ws                       device workspace, cstone_build_workspace_bytes(n, leaf_capacity)
+ *   stage_ms                 host, 4 floats or NULL: milliseconds spent in keys,
+ *                            sort, rebalance and link (measured with HIP events)
+ * Synchronises `stream`. Errors: those of the stages; NONFINITE if a
+ * coordinate is NaN or infinite (found at the first synchronisation, the
+ * outputs are then unspecified and no linking is done).
+ */
+CSTONE_API size_t cstone_build_workspace_bytes(size_t n, size_t leaf_capacity);
+CSTONE_API cstone_status cstone_build(const double* x, const double* y, const double* z, size_t n, const cstone_box* box,
+                           cstone_curve curve, uint32_t n_crit, uint64_t* sorted_keys, uint32_t* perm,
+                           uint64_t* leaves, size_t* n_leaves, size_t leaf_capacity, uint32_t* counts,
+                           uint64_t* node_keys, uint32_t* child, uint32_t* level_offsets, uint32_t max_iters,
+                           uint32_t* iters_done, void* ws, size_t ws_bytes, float* stage_ms, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CSTONE_H */

@@ -1,0 +1,297 @@
+"""Python binding of libcstone, the MI355X Cornerstone octree build.
+
+Thin ctypes marshalling over the C ABI declared in ``include/cstone.h``: every
+function here has the name of the C entry point without the ``cstone_``
+prefix, takes torch tensors that live on the GPU (PyTorch provides device
+memory and streams only) and passes their pointers straight through. All the
+work runs in the HIP kernels of ``libcstone.so``; if the library is missing
+the import of this module fails.
+
+Integer arrays are held in signed torch containers with the same bit
+patterns: uint64 keys in ``torch.int64``, uint32 counts / permutation / CO / LO
+in ``torch.int32``. :func:`to_numpy` returns them as unsigned numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcstone.so")
+
+L = 21
+KEY_END = 1 << 63
+MORTON, HILBERT = 0, 1
+LEVEL_OFFSETS = L + 2
+FLAG_NONFINITE = 1
+
+STATUS = {0: "OK", 1: "INVALID_ARG", 2: "NONFINITE", 3: "CAPACITY", 4: "NOT_CONVERGED", 5: "DEVICE"}
+
+
+class CstoneError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {STATUS.get(status, status)}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class Box(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3)]
+
+    @classmethod
+    def of(cls, box) -> "Box":
+        lo, hi = box
+        return cls((ctypes.c_double * 3)(*map(float, lo)), (ctypes.c_double * 3)(*map(float, hi)))
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2307_06345_amd.build.build() "
+                          "(the octree build has no fallback path)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, sz, u32, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint32, ctypes.c_int
+    pbox = ctypes.POINTER(Box)
+    psz = ctypes.POINTER(ctypes.c_size_t)
+    pu32 = ctypes.POINTER(ctypes.c_uint32)
+    sigs = {
+        "cstone_status_string": (ctypes.c_char_p, [i32]),
+        "cstone_compute_keys": (i32, [P, P, P, sz, pbox, i32, P, P, P]),
+        "cstone_sort_workspace_bytes": (sz, [sz]),
+        "cstone_sort": (i32, [P, P, P, sz, P, sz, P]),
+        "cstone_node_counts": (i32, [P, sz, P, sz, P, P]),
+        "cstone_rebalance_workspace_bytes": (sz, [sz]),
+        "cstone_rebalance": (i32, [P, sz, u32, P, psz, sz, P, u32, pu32, P, sz, P]),
+        "cstone_leaf_capacity_bound": (sz, [sz, u32, sz]),
+        "cstone_node_count": (sz, [sz]),
+        "cstone_link_workspace_bytes": (sz, [sz]),
+        "cstone_link_octree": (i32, [P, sz, P, P, P, P, sz, P]),
+        "cstone_build_workspace_bytes": (sz, [sz, sz]),
+        "cstone_build": (i32, [P, P, P, sz, pbox, i32, u32, P, P, P, psz, sz, P, P, P, P, u32, pu32, P, sz,
+                               ctypes.POINTER(ctypes.c_float), P]),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        raise CstoneError(status, what)
+
+
+def _dev(t: torch.Tensor, dtype) -> torch.Tensor:
+    assert t.is_cuda, "device tensors expected"
+    assert t.dtype == dtype and t.is_contiguous(), (t.dtype, dtype)
+    return t
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def to_numpy(t: torch.Tensor) -> np.ndarray:
+    a = t.detach().cpu().numpy()
+    if a.dtype == np.int64:
+        return a.view(np.uint64)
+    if a.dtype == np.int32:
+        return a.view(np.uint32)
+    return a
+
+
+def from_numpy(a: np.ndarray, device="cuda") -> torch.Tensor:
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.uint64:
+        a = a.view(np.int64)
+    elif a.dtype == np.uint32:
+        a = a.view(np.int32)
+    return torch.from_numpy(a).to(device)
+
+
+def status_string(status: int) -> str:
+    return _lib.cstone_status_string(status).decode()
+
+
+# ---- the six operations ------------------------------------------------------
+
+def compute_keys(x, y, z, box, curve=HILBERT, keys=None, flags=None, stream=None) -> torch.Tensor:
+    """SFC keys (int64 container of uint64) of FP64 device coordinates."""
+    n = x.numel()
+    for t in (x, y, z):
+        _dev(t, torch.float64)
+    if keys is None:
+        keys = torch.empty(n, dtype=torch.int64, device=x.device)
+    b = Box.of(box)
+    _check(_lib.cstone_compute_keys(_ptr(x), _ptr(y), _ptr(z), n, ctypes.byref(b), int(curve), _ptr(keys),
+                                    _ptr(flags), _stream(stream)), "cstone_compute_keys")
+    return keys
+
+
+def sort(keys, keys_out=None, perm_out=None, ws=None, stream=None):
+    """Stable radix sort: (sorted keys, perm) with sorted[i] = keys[perm[i]]."""
+    n = keys.numel()
+    _dev(keys, torch.int64)
+    if keys_out is None:
+        keys_out = torch.empty(n, dtype=torch.int64, device=keys.device)
+    if perm_out is None:
+        perm_out = torch.empty(n, dtype=torch.int32, device=keys.device)
+    need = _lib.cstone_sort_workspace_bytes(n)
+    if ws is None:
+        ws = _workspace(need, keys.device)
+    _check(_lib.cstone_sort(_ptr(keys), _ptr(keys_out), _ptr(perm_out), n, _ptr(ws), ws.numel(), _stream(stream)),
+           "cstone_sort")
+    return keys_out, perm_out
+
+
+def node_counts(sorted_keys, leaves, counts=None, stream=None) -> torch.Tensor:
+    nl = leaves.numel() - 1
+    if counts is None:
+        counts = torch.empty(max(nl, 1), dtype=torch.int32, device=leaves.device)
+    _check(_lib.cstone_node_counts(_ptr(sorted_keys), sorted_keys.numel(), _ptr(leaves), nl, _ptr(counts),
+                                   _stream(stream)), "cstone_node_counts")
+    return counts[:nl]
+
+
+def leaf_capacity_bound(n: int, n_crit: int, n_leaves_start: int = 1) -> int:
+    return int(_lib.cstone_leaf_capacity_bound(n, n_crit, n_leaves_start))
+
+
+def node_count(n_leaves: int) -> int:
+    return int(_lib.cstone_node_count(n_leaves))
+
+
+def rebalance(sorted_keys, n_crit: int, leaves=None, capacity=None, max_iters: int = 0, ws=None, stream=None):
+    """Iterate f and g from `leaves` (default: the root) to convergence.
+
+    Returns (K, counts, rounds). Raises CstoneError on CAPACITY/NOT_CONVERGED
+    (the error carries .leaves / .rounds of the last valid array)."""
+    n = sorted_keys.numel()
+    dev = sorted_keys.device
+    nl0 = 1 if leaves is None else leaves.numel() - 1
+    if capacity is None:
+        capacity = leaf_capacity_bound(n, n_crit, nl0)
+    buf = torch.empty(capacity + 1, dtype=torch.int64, device=dev)
+    if leaves is not None:
+        buf[: nl0 + 1].copy_(leaves)
+    counts = torch.empty(capacity, dtype=torch.int32, device=dev)
+    need = _lib.cstone_rebalance_workspace_bytes(capacity)
+    if ws is None:
+        ws = _workspace(need, dev)
+    nl = ctypes.c_size_t(nl0)
+    rounds = ctypes.c_uint32(0)
+    st = _lib.cstone_rebalance(_ptr(sorted_keys), n, int(n_crit), _ptr(buf), ctypes.byref(nl), capacity, _ptr(counts),
+                               int(max_iters), ctypes.byref(rounds), _ptr(ws), ws.numel(), _stream(stream))
+    if st != 0:
+        err = CstoneError(st, "cstone_rebalance")
+        err.n_leaves = nl.value
+        err.rounds = rounds.value
+        err.buffer = buf
+        err.counts = counts
+        raise err
+    return buf[: nl.value + 1], counts[: nl.value], int(rounds.value)
+
+
+def link_octree(leaves, node_keys=None, child=None, level_offsets=None, ws=None, stream=None):
+    """Fully linked octree of a cornerstone array: (NK, CO, LO)."""
+    nl = leaves.numel() - 1
+    n = node_count(nl)
+    dev = leaves.device
+    if node_keys is None:
+        node_keys = torch.empty(n, dtype=torch.int64, device=dev)
+    if child is None:
+        child = torch.empty(n, dtype=torch.int32, device=dev)
+    if level_offsets is None:
+        level_offsets = torch.empty(LEVEL_OFFSETS, dtype=torch.int32, device=dev)
+    need = _lib.cstone_link_workspace_bytes(nl)
+    if ws is None:
+        ws = _workspace(need, dev)
+    _check(_lib.cstone_link_octree(_ptr(leaves), nl, _ptr(node_keys), _ptr(child), _ptr(level_offsets), _ptr(ws),
+                                   ws.numel(), _stream(stream)), "cstone_link_octree")
+    return node_keys[:n], child[:n], level_offsets
+
+
+# ---- whole build with preallocated buffers ----------------------------------------
+
+@dataclass
+class BuildResult:
+    sorted_keys: torch.Tensor
+    perm: torch.Tensor
+    leaves: torch.Tensor
+    counts: torch.Tensor
+    node_keys: torch.Tensor | None
+    child: torch.Tensor | None
+    level_offsets: torch.Tensor | None
+    rounds: int
+    stage_ms: tuple
+
+
+class Builder:
+    """Holds every buffer of a build of up to `n_max` particles so repeated
+    builds allocate nothing (the library itself never allocates)."""
+
+    def __init__(self, n_max: int, n_crit_min: int = 1, leaf_capacity: int | None = None, device="cuda",
+                 link: bool = True):
+        self.device = torch.device(device)
+        self.n_max = int(n_max)
+        cap = leaf_capacity or leaf_capacity_bound(self.n_max, n_crit_min)
+        self.capacity = int(cap)
+        dev = self.device
+        self.sorted_keys = torch.empty(max(self.n_max, 1), dtype=torch.int64, device=dev)
+        self.perm = torch.empty(max(self.n_max, 1), dtype=torch.int32, device=dev)
+        self.leaves = torch.empty(self.capacity + 1, dtype=torch.int64, device=dev)
+        self.counts = torch.empty(self.capacity, dtype=torch.int32, device=dev)
+        self.link = link
+        nn = node_count(self.capacity)
+        self.node_keys = torch.empty(nn, dtype=torch.int64, device=dev) if link else None
+        self.child = torch.empty(nn, dtype=torch.int32, device=dev) if link else None
+        self.level_offsets = torch.empty(LEVEL_OFFSETS, dtype=torch.int32, device=dev) if link else None
+        self.ws = _workspace(_lib.cstone_build_workspace_bytes(self.n_max, self.capacity), dev)
+        self.n_leaves = 0
+
+    def build(self, x, y, z, box, curve, n_crit: int, incremental: bool = False, max_iters: int = 0,
+              timed: bool = False, stream=None) -> BuildResult:
+        n = x.numel()
+        assert n <= self.n_max
+        for t in (x, y, z):
+            _dev(t, torch.float64)
+        nl = ctypes.c_size_t(self.n_leaves if incremental else 0)
+        rounds = ctypes.c_uint32(0)
+        ms = (ctypes.c_float * 4)()
+        b = Box.of(box)
+        st = _lib.cstone_build(_ptr(x), _ptr(y), _ptr(z), n, ctypes.byref(b), int(curve), int(n_crit),
+                               _ptr(self.sorted_keys), _ptr(self.perm), _ptr(self.leaves), ctypes.byref(nl),
+                               self.capacity, _ptr(self.counts), _ptr(self.node_keys), _ptr(self.child),
+                               _ptr(self.level_offsets), int(max_iters), ctypes.byref(rounds), _ptr(self.ws),
+                               self.ws.numel(), ms if timed else None, _stream(stream))
+        if st != 0:
+            err = CstoneError(st, "cstone_build")
+            err.n_leaves = nl.value
+            raise err
+        self.n_leaves = nl.value
+        nlv = nl.value
+        nn = node_count(nlv)
+        return BuildResult(self.sorted_keys[:n], self.perm[:n], self.leaves[: nlv + 1], self.counts[:nlv],
+                           self.node_keys[:nn] if self.link else None, self.child[:nn] if self.link else None,
+                           self.level_offsets if self.link else None, int(rounds.value), tuple(ms) if timed else ())
+
+
+def build(x, y, z, box, curve=HILBERT, n_crit: int = 64, link: bool = True) -> BuildResult:
+    """One-shot build (allocates a Builder sized for this set)."""
+    return Builder(x.numel(), n_crit, device=x.device, link=link).build(x, y, z, box, curve, n_crit)

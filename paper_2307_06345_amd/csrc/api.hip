@@ -1,0 +1,162 @@
+// C ABI entry points of libcstone (declared and documented in cstone.h):
+// argument checks, workspace layout and the order of the stages on a stream.
+#include <algorithm>
+#include <cmath>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+using namespace cs;
+
+namespace {
+
+bool box_ok(const cstone_box* b) {
+    if (!b) return false;
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(b->lo[d]) || !std::isfinite(b->hi[d]) || !(b->lo[d] < b->hi[d])) return false;
+    return true;
+}
+
+constexpr size_t kMaxN = 0xffffffffull;  // counts, perm, CO and LO are uint32
+
+size_t nodes_of(size_t nl) { return nl + (nl ? (nl - 1) / 7 : 0); }
+
+__global__ void clear_word_kernel(uint32_t* w) { *w = 0; }
+
+}  // namespace
+
+extern "C" {
+
+const char* cstone_status_string(cstone_status s) {
+    switch (s) {
+        case CSTONE_OK: return "ok";
+        case CSTONE_ERR_INVALID_ARG: return "invalid argument";
+        case CSTONE_ERR_NONFINITE: return "non-finite coordinate";
+        case CSTONE_ERR_CAPACITY: return "leaf capacity exceeded";
+        case CSTONE_ERR_NOT_CONVERGED: return "rebalance did not converge within max_iters";
+        case CSTONE_ERR_DEVICE: return "device error";
+    }
+    return "unknown status";
+}
+
+cstone_status cstone_compute_keys(const double* x, const double* y, const double* z, size_t n, const cstone_box* box,
+                                  cstone_curve curve, uint64_t* keys, uint32_t* flags, hipStream_t stream) {
+    if (n > kMaxN || !box_ok(box) || (curve != CSTONE_MORTON && curve != CSTONE_HILBERT)) return CSTONE_ERR_INVALID_ARG;
+    if (n && (!x || !y || !z || !keys)) return CSTONE_ERR_INVALID_ARG;
+    return launch_keys(x, y, z, n, *box, curve, keys, flags, stream);
+}
+
+size_t cstone_sort_workspace_bytes(size_t n) { return sort_workspace_bytes(n, true); }
+
+cstone_status cstone_sort(const uint64_t* keys_in, uint64_t* keys_out, uint32_t* perm_out, size_t n, void* ws,
+                          size_t ws_bytes, hipStream_t stream) {
+    if (n > kMaxN) return CSTONE_ERR_INVALID_ARG;
+    if (n && (!keys_in || !keys_out || !perm_out || !ws)) return CSTONE_ERR_INVALID_ARG;
+    return launch_sort(keys_in, keys_out, perm_out, n, 63, ws, ws_bytes, stream);
+}
+
+cstone_status cstone_node_counts(const uint64_t* sorted_keys, size_t n, const uint64_t* leaves, size_t n_leaves,
+                                 uint32_t* counts, hipStream_t stream) {
+    if (n > kMaxN || n_leaves < 1 || !leaves || !counts || (n && !sorted_keys)) return CSTONE_ERR_INVALID_ARG;
+    return launch_node_counts(sorted_keys, n, leaves, n_leaves, counts, stream);
+}
+
+size_t cstone_rebalance_workspace_bytes(size_t leaf_capacity) { return rebalance_workspace_bytes(leaf_capacity); }
+
+size_t cstone_leaf_capacity_bound(size_t n, uint32_t n_crit, size_t n_leaves_start) {
+    const size_t full = n / (static_cast<size_t>(n_crit) + 1);
+    size_t bound = 7 * static_cast<size_t>(kL) * full + 1;
+    if (n_leaves_start > 1) bound = std::max(bound, n_leaves_start + 7 * full);
+    return bound;
+}
+
+cstone_status cstone_rebalance(const uint64_t* sorted_keys, size_t n, uint32_t n_crit, uint64_t* leaves,
+                               size_t* n_leaves, size_t leaf_capacity, uint32_t* counts, uint32_t max_iters,
+                               uint32_t* iters_done, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (n > kMaxN || n_crit == 0 || !leaves || !n_leaves || !ws || (n && !sorted_keys)) return CSTONE_ERR_INVALID_ARG;
+    if (*n_leaves < 1 || *n_leaves > leaf_capacity) return CSTONE_ERR_INVALID_ARG;
+    return run_rebalance(sorted_keys, n, n_crit, leaves, n_leaves, leaf_capacity, counts, max_iters, iters_done, ws,
+                         ws_bytes, stream);
+}
+
+size_t cstone_node_count(size_t n_leaves) { return nodes_of(n_leaves); }
+
+size_t cstone_link_workspace_bytes(size_t n_leaves) { return link_workspace_bytes(n_leaves); }
+
+cstone_status cstone_link_octree(const uint64_t* leaves, size_t n_leaves, uint64_t* node_keys, uint32_t* child,
+                                 uint32_t* level_offsets, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (n_leaves < 1 || n_leaves > kMaxN || (n_leaves - 1) % 7 != 0) return CSTONE_ERR_INVALID_ARG;
+    if (!leaves || !node_keys || !child || !level_offsets || !ws) return CSTONE_ERR_INVALID_ARG;
+    return launch_link(leaves, n_leaves, node_keys, child, level_offsets, ws, ws_bytes, stream);
+}
+
+size_t cstone_build_workspace_bytes(size_t n, size_t leaf_capacity) {
+    Carve c(nullptr);
+    c.take<uint64_t>(n);  // unsorted keys
+    c.take<uint32_t>(1);  // non-finite flag
+    size_t stage = std::max(sort_workspace_bytes(n, true),
+                            std::max(rebalance_workspace_bytes(leaf_capacity), link_workspace_bytes(leaf_capacity)));
+    return c.off + stage;
+}
+
+cstone_status cstone_build(const double* x, const double* y, const double* z, size_t n, const cstone_box* box,
+                           cstone_curve curve, uint32_t n_crit, uint64_t* sorted_keys, uint32_t* perm,
+                           uint64_t* leaves, size_t* n_leaves, size_t leaf_capacity, uint32_t* counts,
+                           uint64_t* node_keys, uint32_t* child, uint32_t* level_offsets, uint32_t max_iters,
+                           uint32_t* iters_done, void* ws, size_t ws_bytes, float* stage_ms, hipStream_t stream) {
+    if (n > kMaxN || n_crit == 0 || !box_ok(box) || !leaves || !n_leaves || !ws) return CSTONE_ERR_INVALID_ARG;
+    if (curve != CSTONE_MORTON && curve != CSTONE_HILBERT) return CSTONE_ERR_INVALID_ARG;
+    if (n && (!x || !y || !z || !sorted_keys || !perm)) return CSTONE_ERR_INVALID_ARG;
+    if ((node_keys == nullptr) != (child == nullptr) || (node_keys && !level_offsets)) return CSTONE_ERR_INVALID_ARG;
+    if (leaf_capacity < 1 || *n_leaves > leaf_capacity) return CSTONE_ERR_INVALID_ARG;
+    if (ws_bytes < cstone_build_workspace_bytes(n, leaf_capacity)) return CSTONE_ERR_INVALID_ARG;
+
+    Carve c(ws);
+    uint64_t* keys = c.take<uint64_t>(n);
+    uint32_t* flag = c.take<uint32_t>(1);
+    void* stage_ws = static_cast<char*>(ws) + c.off;
+    const size_t stage_bytes = ws_bytes - c.off;
+
+    hipEvent_t ev[5] = {};
+    const bool timed = stage_ms != nullptr;
+    if (timed)
+        for (auto& e : ev) CS_HIP(hipEventCreate(&e));
+    auto mark = [&](int i) -> hipError_t { return timed ? hipEventRecord(ev[i], stream) : hipSuccess; };
+    auto cleanup = [&]() {
+        if (timed)
+            for (auto& e : ev)
+                if (e) (void)hipEventDestroy(e);
+    };
+    cstone_status s = CSTONE_OK;
+    uint32_t host_flag = 0;
+    size_t nl = *n_leaves;
+    do {
+        if (mark(0) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
+        hipLaunchKernelGGL(clear_word_kernel, dim3(1), dim3(1), 0, stream, flag);
+        s = launch_keys(x, y, z, n, *box, curve, keys, flag, stream);
+        if (s != CSTONE_OK) break;
+        if (mark(1) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
+        s = launch_sort(keys, sorted_keys, perm, n, 63, stage_ws, stage_bytes, stream);
+        if (s != CSTONE_OK) break;
+        if (mark(2) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
+        if (nl == 0) nl = 1;  // start from the root leaf {0, 8^L}
+        s = run_rebalance(sorted_keys, n, n_crit, leaves, &nl, leaf_capacity, counts, max_iters, iters_done, stage_ws,
+                          stage_bytes, stream, flag, &host_flag);
+        *n_leaves = nl;
+        if (host_flag & CSTONE_FLAG_NONFINITE) { s = CSTONE_ERR_NONFINITE; break; }
+        if (s != CSTONE_OK) break;
+        if (mark(3) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
+        if (node_keys) {
+            s = launch_link(leaves, nl, node_keys, child, level_offsets, stage_ws, stage_bytes, stream);
+            if (s != CSTONE_OK) break;
+        }
+        if (mark(4) != hipSuccess || hipStreamSynchronize(stream) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
+        if (timed)
+            for (int i = 0; i < 4; ++i)
+                if (hipEventElapsedTime(&stage_ms[i], ev[i], ev[i + 1]) != hipSuccess) s = CSTONE_ERR_DEVICE;
+    } while (false);
+    cleanup();
+    return s;
+}
+
+}  // extern "C"

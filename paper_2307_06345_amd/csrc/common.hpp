@@ -1,0 +1,159 @@
+// Device and host helpers shared by the HIP kernels of the octree build.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "cstone.h"
+
+namespace cs {
+
+constexpr int kL = 21;
+constexpr uint64_t kKeyEnd = 1ull << 63;  // 8^21, closes every cornerstone array
+constexpr int kWave = 64;
+
+// Error word kept in workspaces: a device-side wait that gave up sets it.
+constexpr uint32_t kErrSpin = 1u;
+
+// Spin budget for look-back waits (each spin sleeps ~64 cycles); a wait that
+// exhausts it marks the error word and proceeds, so every wave terminates.
+constexpr uint32_t kSpinLimit = 1u << 20;
+
+#define CS_HIP(expr)                                     \
+    do {                                                 \
+        hipError_t cs_e_ = (expr);                       \
+        if (cs_e_ != hipSuccess) return CSTONE_ERR_DEVICE; \
+    } while (0)
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Bump allocator over a caller workspace (256-byte aligned slices).
+struct Carve {
+    char* base;
+    size_t off = 0;
+    explicit Carve(void* p) : base(static_cast<char*>(p)) {}
+    template <class T>
+    T* take(size_t count) {
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off = align_up(off + count * sizeof(T), 256);
+        return p;
+    }
+};
+
+// ---- wave64 primitives ---------------------------------------------------
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// Number of set bits of `mask` in lanes below this one.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
+}
+
+template <class T>
+__device__ __forceinline__ T wave_inclusive_sum(T v) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        T o = __shfl_up(v, d, kWave);
+        if (lane >= static_cast<uint32_t>(d)) v += o;
+    }
+    return v;
+}
+
+// Block-wide exclusive sum; `lds` holds one T per wave. Returns the exclusive
+// prefix of this thread and writes the block total to *total.
+template <class T, int BLOCK>
+__device__ __forceinline__ T block_exclusive_sum(T v, T* lds, T* total) {
+    constexpr int W = BLOCK / kWave;
+    const uint32_t lane = lane_id();
+    const uint32_t wave = threadIdx.x / kWave;
+    T inc = wave_inclusive_sum(v);
+    if (lane == kWave - 1) lds[wave] = inc;
+    __syncthreads();
+    T wave_prefix = 0, sum = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        T s = lds[w];
+        if (w < static_cast<int>(wave)) wave_prefix += s;
+        sum += s;
+    }
+    __syncthreads();
+    *total = sum;
+    return wave_prefix + inc - v;
+}
+
+// ---- agent-scope (cross-XCD) atomics for decoupled look-back ----------------
+
+__device__ __forceinline__ uint64_t ld_agent(const uint64_t* p) {
+    return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Look-back status word: [63:62] flag (0 empty, 1 tile aggregate, 2 inclusive
+// prefix), [61:48] epoch (which pass / round wrote it), [47:0] value.
+constexpr uint64_t kFlagAgg = 1ull << 62;
+constexpr uint64_t kFlagInc = 2ull << 62;
+constexpr uint64_t kValueMask = (1ull << 48) - 1;
+
+__device__ __forceinline__ uint64_t lb_word(uint64_t flag, uint32_t epoch, uint64_t value) {
+    return flag | (static_cast<uint64_t>(epoch & 0x3fffu) << 48) | (value & kValueMask);
+}
+
+// Exclusive prefix of tile `tile` for one counter: walk back over the
+// predecessors' words (stride `stride` between tiles) until an inclusive
+// prefix is found. Words of another epoch count as not yet written.
+__device__ __forceinline__ uint64_t lookback(const uint64_t* words, size_t stride, uint32_t tile,
+                                             uint32_t epoch, uint32_t* err) {
+    uint64_t excl = 0;
+    int64_t p = static_cast<int64_t>(tile) - 1;
+    uint32_t spins = 0;
+    while (p >= 0) {
+        uint64_t w = ld_agent(words + static_cast<size_t>(p) * stride);
+        uint64_t flag = w & (3ull << 62);
+        bool mine = ((w >> 48) & 0x3fffu) == (epoch & 0x3fffu);
+        if (flag == 0 || !mine) {
+            if (++spins > kSpinLimit) {
+                atomicOr(err, kErrSpin);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        excl += w & kValueMask;
+        if (flag == kFlagInc) break;
+        --p;
+    }
+    return excl;
+}
+
+// Dynamic tile index: blocks take tiles in launch order through an atomic
+// counter, so a block waiting on tile t-1 knows t-1 is already owned by a
+// running block (forward progress for the look-back).
+__device__ __forceinline__ uint32_t take_tile(uint32_t* counter, uint32_t* lds_slot) {
+    if (threadIdx.x == 0) *lds_slot = atomicAdd(counter, 1u);
+    __syncthreads();
+    uint32_t t = *lds_slot;
+    __syncthreads();
+    return t;
+}
+
+__device__ __forceinline__ int clz64(uint64_t v) { return v ? __clzll(static_cast<long long>(v)) : 64; }
+
+// First index in [lo, hi) whose key is >= k (hi if none).
+__device__ __forceinline__ uint64_t lower_bound_u64(const uint64_t* a, uint64_t lo, uint64_t hi, uint64_t k) {
+    while (lo < hi) {
+        uint64_t mid = lo + ((hi - lo) >> 1);
+        if (a[mid] < k)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+}  // namespace cs

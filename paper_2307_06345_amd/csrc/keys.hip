@@ -1,0 +1,195 @@
+// SFC keys from FP64 coordinates (Sec. 3): quantisation to the 2^21 grid,
+// Morton interleave, and Skilling's 3D Hilbert curve evaluated as a finite
+// state machine over bit planes with a 2-plane lookup table held in LDS.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace cs {
+namespace {
+
+// ---- Hilbert curve as a state machine -----------------------------------
+//
+// Skilling's transform (AIP Conf. Proc. 707, 2004) visits the bit planes from
+// the top. At each plane it either reflects the lower bits of word 0 or swaps
+// the lower bits of word 0 and word i, so everything it does to the lower planes
+// is an axis permutation plus reflection (a symmetry of the cube). Its Gray
+// stage is local to a plane, up to a running parity that complements every
+// later digit. The key digit of a plane is therefore a function of the plane's
+// raw octant and a state (axis permutation, reflection mask, parity); the
+// state reachable from the identity are enumerated here at compile time.
+
+struct HState {
+    uint8_t perm[3];  // transformed axis a reads raw axis perm[a]
+    uint8_t mask;     // reflection of transformed axis a in bit a
+    uint8_t parity;
+};
+
+constexpr bool same(const HState& a, const HState& b) {
+    return a.perm[0] == b.perm[0] && a.perm[1] == b.perm[1] && a.perm[2] == b.perm[2] && a.mask == b.mask &&
+           a.parity == b.parity;
+}
+
+// One bit plane: raw octant o = 4x + 2y + z -> key digit, next state.
+constexpr uint32_t plane_step(const HState& s, uint32_t o, HState& next) {
+    uint32_t raw[3] = {(o >> 2) & 1u, (o >> 1) & 1u, o & 1u};
+    uint32_t w[3] = {};
+    for (int a = 0; a < 3; ++a) w[a] = raw[s.perm[a]] ^ ((s.mask >> a) & 1u);
+    uint32_t g0 = w[0], g1 = w[1] ^ w[0], g2 = w[2] ^ w[1] ^ w[0];
+    uint32_t digit = (g0 << 2) | (g1 << 1) | g2;
+    if (s.parity) digit ^= 7u;
+    uint8_t p[3] = {s.perm[0], s.perm[1], s.perm[2]};
+    uint8_t m[3] = {static_cast<uint8_t>(s.mask & 1u), static_cast<uint8_t>((s.mask >> 1) & 1u),
+                    static_cast<uint8_t>((s.mask >> 2) & 1u)};
+    for (int i = 0; i < 3; ++i) {
+        if (w[i]) {
+            m[0] ^= 1u;
+        } else {
+            uint8_t tp = p[0];
+            p[0] = p[i];
+            p[i] = tp;
+            uint8_t tm = m[0];
+            m[0] = m[i];
+            m[i] = tm;
+        }
+    }
+    next = HState{{p[0], p[1], p[2]}, static_cast<uint8_t>(m[0] | (m[1] << 1) | (m[2] << 2)),
+                  static_cast<uint8_t>(s.parity ^ g2)};
+    return digit;
+}
+
+constexpr int kMaxStates = 96;
+constexpr int kStates = 48;  // reachable states (checked below)
+
+struct HilbertTables {
+    // one plane from the start state: digit | next << 3
+    uint16_t first[8];
+    // two planes: index = state * 64 + (octant_hi << 3 | octant_lo),
+    // entry = (digit_hi << 3 | digit_lo) | next << 6
+    uint16_t two[kStates * 64];
+    int count;
+};
+
+constexpr HilbertTables make_tables() {
+    HState st[kMaxStates] = {};
+    uint16_t one[kMaxStates][8] = {};
+    int count = 1;
+    st[0] = HState{{0, 1, 2}, 0, 0};
+    for (int s = 0; s < count; ++s) {
+        for (uint32_t o = 0; o < 8; ++o) {
+            HState nx{};
+            uint32_t d = plane_step(st[s], o, nx);
+            int idx = -1;
+            for (int k = 0; k < count; ++k)
+                if (same(st[k], nx)) idx = k;
+            if (idx < 0) {
+                idx = count;
+                st[count++] = nx;
+            }
+            one[s][o] = static_cast<uint16_t>(d | (idx << 3));
+        }
+    }
+    HilbertTables t{};
+    t.count = count;
+    for (int o = 0; o < 8; ++o) t.first[o] = one[0][o];
+    for (int s = 0; s < kStates && s < count; ++s)
+        for (uint32_t o = 0; o < 64; ++o) {
+            uint32_t e1 = one[s][o >> 3];
+            uint32_t e2 = one[e1 >> 3][o & 7u];
+            t.two[s * 64 + o] = static_cast<uint16_t>(((e1 & 7u) << 3) | (e2 & 7u) | ((e2 >> 3) << 6));
+        }
+    return t;
+}
+
+constexpr HilbertTables kHilbert = make_tables();
+static_assert(kHilbert.count == kStates, "unexpected number of Hilbert states");
+
+__device__ const HilbertTables d_hilbert = kHilbert;
+
+// ---- quantisation and Morton spread --------------------------------------
+
+__device__ __forceinline__ uint32_t quantize(double c, double lo, double s) {
+    double t = (c - lo) * s;  // two IEEE roundings; built with -ffp-contract=off
+    if (!(t >= 0.0)) return 0u;
+    if (t >= 2097152.0) return (1u << kL) - 1u;
+    return static_cast<uint32_t>(t);
+}
+
+// Spread the 21 low bits of v so bit b lands on bit 3b.
+__device__ __forceinline__ uint64_t spread3(uint32_t v) {
+    uint64_t x = v & 0x1fffffu;
+    x = (x | (x << 32)) & 0x1f00000000ffffull;
+    x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+    x = (x | (x << 8)) & 0x100f00f00f00f00full;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+__device__ __forceinline__ uint64_t morton_of(uint32_t ix, uint32_t iy, uint32_t iz) {
+    return (spread3(ix) << 2) | (spread3(iy) << 1) | spread3(iz);
+}
+
+// The Morton code's octal digits are the raw plane octants (x as the 4s bit),
+// so the Hilbert machine consumes it 6 bits (two planes) at a time.
+__device__ __forceinline__ uint64_t hilbert_from_morton(uint64_t m, const uint16_t* two, const uint16_t* first) {
+    uint32_t e = first[(m >> 60) & 7u];
+    uint64_t key = e & 7u;
+    uint32_t state = e >> 3;
+#pragma unroll
+    for (int pair = 9; pair >= 0; --pair) {
+        uint32_t o = static_cast<uint32_t>(m >> (6 * pair)) & 63u;
+        uint32_t t = two[state * 64 + o];
+        key = (key << 6) | (t & 63u);
+        state = t >> 6;
+    }
+    return key;
+}
+
+constexpr int kKeysBlock = 256;
+
+template <int CURVE>
+__global__ __launch_bounds__(kKeysBlock) void keys_kernel(const double* __restrict__ x,
+                                                          const double* __restrict__ y,
+                                                          const double* __restrict__ z, size_t n, double lo0,
+                                                          double lo1, double lo2, double s0, double s1, double s2,
+                                                          uint64_t* __restrict__ keys, uint32_t* flags) {
+    __shared__ uint16_t two[kStates * 64];
+    __shared__ uint16_t first[8];
+    if (CURVE == CSTONE_HILBERT) {
+        for (int i = threadIdx.x; i < kStates * 64; i += kKeysBlock) two[i] = d_hilbert.two[i];
+        if (threadIdx.x < 8) first[threadIdx.x] = d_hilbert.first[threadIdx.x];
+        __syncthreads();
+    }
+    bool bad = false;
+    const size_t stride = static_cast<size_t>(gridDim.x) * kKeysBlock;
+    for (size_t p = static_cast<size_t>(blockIdx.x) * kKeysBlock + threadIdx.x; p < n; p += stride) {
+        double cx = x[p], cy = y[p], cz = z[p];
+        bad |= !(__builtin_isfinite(cx) && __builtin_isfinite(cy) && __builtin_isfinite(cz));
+        uint64_t m = morton_of(quantize(cx, lo0, s0), quantize(cy, lo1, s1), quantize(cz, lo2, s2));
+        if (CURVE == CSTONE_HILBERT) m = hilbert_from_morton(m, two, first);
+        keys[p] = m;
+    }
+    if (flags && __ballot(bad) != 0ull && lane_id() == 0) atomicOr(flags, CSTONE_FLAG_NONFINITE);
+}
+
+}  // namespace
+
+cstone_status launch_keys(const double* x, const double* y, const double* z, size_t n, const cstone_box& box,
+                          cstone_curve curve, uint64_t* keys, uint32_t* flags, hipStream_t stream) {
+    if (n == 0) return CSTONE_OK;
+    double s[3];
+    for (int d = 0; d < 3; ++d) s[d] = 2097152.0 / (box.hi[d] - box.lo[d]);
+    size_t blocks = (n + kKeysBlock - 1) / kKeysBlock;
+    const size_t max_blocks = 256 * 16;  // grid-stride beyond 16 blocks per CU
+    if (blocks > max_blocks) blocks = max_blocks;
+    if (curve == CSTONE_HILBERT)
+        hipLaunchKernelGGL(keys_kernel<CSTONE_HILBERT>, dim3(blocks), dim3(kKeysBlock), 0, stream, x, y, z, n,
+                           box.lo[0], box.lo[1], box.lo[2], s[0], s[1], s[2], keys, flags);
+    else
+        hipLaunchKernelGGL(keys_kernel<CSTONE_MORTON>, dim3(blocks), dim3(kKeysBlock), 0, stream, x, y, z, n,
+                           box.lo[0], box.lo[1], box.lo[2], s[0], s[1], s[2], keys, flags);
+    CS_HIP(hipGetLastError());
+    return CSTONE_OK;
+}
+
+}  // namespace cs

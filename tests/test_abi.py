@@ -1,0 +1,66 @@
+"""The C-ABI library loads on the host and exports every entry point that
+include/cstone.h declares; host-only queries answer without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cstone.h")
+LIB = os.path.join(ROOT, "paper_2307_06345_amd", "libcstone.so")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"CSTONE_API\s+[\w\s\*]*?\b(cstone_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_six_operations():
+    names = declared_symbols()
+    for op in ("compute_keys", "sort", "node_counts", "rebalance", "link_octree", "build"):
+        assert f"cstone_{op}" in names
+
+
+def test_library_exports_every_declared_symbol():
+    assert os.path.exists(LIB), "run __graft_entry__.build() first"
+    lib = ctypes.CDLL(LIB)
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+
+
+def test_library_exports_nothing_else():
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True, check=True).stdout
+    exported = sorted(l.split()[-1] for l in out.splitlines() if " T " in l)
+    assert exported == declared_symbols()
+
+
+def test_host_queries():
+    import paper_2307_06345_amd as cs
+    assert cs.status_string(0) == "ok"
+    assert cs.node_count(1) == 1 and cs.node_count(15) == 17 and cs.node_count(64) == 73
+    # 7 * 21 * floor(n / (n_crit + 1)) + 1
+    assert cs.leaf_capacity_bound(1 << 16, 64) == 7 * 21 * ((1 << 16) // 65) + 1
+    assert cs.leaf_capacity_bound(10, 64) == 1
+    lib = cs._lib
+    assert lib.cstone_sort_workspace_bytes(1 << 20) >= 12 * (1 << 20)
+    assert lib.cstone_build_workspace_bytes(1000, 100) >= lib.cstone_sort_workspace_bytes(1000)
+
+
+def test_invalid_arguments_are_rejected_without_a_device():
+    import paper_2307_06345_amd as cs
+    lib = cs._lib
+    box = cs.Box.of(((0, 0, 0), (1, 1, 1)))
+    bad = cs.Box.of(((0, 0, 0), (1, 0, 1)))
+    # n > 0 with null pointers, a degenerate box, an unknown curve
+    assert lib.cstone_compute_keys(None, None, None, 5, ctypes.byref(box), 0, None, None, None) == 1
+    assert lib.cstone_compute_keys(None, None, None, 0, ctypes.byref(bad), 0, None, None, None) == 1
+    assert lib.cstone_compute_keys(None, None, None, 0, ctypes.byref(box), 7, None, None, None) == 1
+    # link: n_leaves - 1 must be a multiple of 7
+    assert lib.cstone_link_octree(ctypes.c_void_p(8), 5, ctypes.c_void_p(8), ctypes.c_void_p(8),
+                                  ctypes.c_void_p(8), ctypes.c_void_p(8), 1 << 20, None) == 1
+    # rebalance: n_crit == 0
+    nl = ctypes.c_size_t(1)
+    assert lib.cstone_rebalance(ctypes.c_void_p(8), 10, 0, ctypes.c_void_p(8), ctypes.byref(nl), 10, None, 0, None,
+                                ctypes.c_void_p(8), 1 << 20, None) == 1
