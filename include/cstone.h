@@ -128,13 +128,14 @@ CSTONE_API cstone_status cstone_node_counts(const uint64_t* sorted_keys, size_t 
  *   counts       device, leaf_capacity uint32 (output: final leaf counts), or NULL
  *   max_iters    rounds allowed (0 means 22 = L + 1)
  *   iters_done   host, rounds run (a round is one f + one g), or NULL
- *   ws           device workspace of cstone_rebalance_workspace_bytes() bytes
+ *   ws           device workspace of cstone_rebalance_workspace_bytes(n, n_crit,
+ *                leaf_capacity) bytes
  * Synchronises `stream`. Errors: INVALID_ARG; CAPACITY (leaves keep the last
  * array that fitted, *n_leaves is the count the next round needed);
  * NOT_CONVERGED (leaves hold the array after max_iters rounds, a valid
  * cornerstone array); DEVICE.
  */
-CSTONE_API size_t cstone_rebalance_workspace_bytes(size_t leaf_capacity);
+CSTONE_API size_t cstone_rebalance_workspace_bytes(size_t n, uint32_t n_crit, size_t leaf_capacity);
 CSTONE_API cstone_status cstone_rebalance(const uint64_t* sorted_keys, size_t n, uint32_t n_crit, uint64_t* leaves,
                                size_t* n_leaves, size_t leaf_capacity, uint32_t* counts,
                                uint32_t max_iters, uint32_t* iters_done, void* ws, size_t ws_bytes,
@@ -149,6 +150,9 @@ CSTONE_API size_t cstone_leaf_capacity_bound(size_t n, uint32_t n_crit, size_t n
 
 /* ------------------------------------------------------------------------
  * Fully linked octree (Sec. 5). n = n_leaves + (n_leaves - 1) / 7 nodes.
+ * Every node is started by one leaf (its first); the nodes of one level are
+ * in leaf order, so each node's breadth-first index is a per-level count over
+ * the leaves, found by one counting pass, a scan and one writing pass.
  *   node_keys      device, n uint64: every node in Warren-Salmon placeholder-bit
  *                  form (a 1 bit followed by the node's level octal digits),
  *                  ascending = breadth-first (level-major, SFC order within a level)
@@ -164,6 +168,15 @@ CSTONE_API size_t cstone_link_workspace_bytes(size_t n_leaves);
 CSTONE_API cstone_status cstone_link_octree(const uint64_t* leaves, size_t n_leaves, uint64_t* node_keys, uint32_t* child,
                                  uint32_t* level_offsets, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Same outputs as cstone_link_octree, computed by the five steps of Sec. 5 as
+ * written: leaf and internal node keys (internal nodes at the slot given by
+ * Eq. digitweight, with the digit weights' sign reversed so the slots are the
+ * integers 0..n_i-1), a radix sort of NK, LO and CO by binary search. Kept for
+ * comparison; cstone_link_octree reaches the breadth-first order directly. */
+CSTONE_API cstone_status cstone_link_octree_by_sort(const uint64_t* leaves, size_t n_leaves, uint64_t* node_keys,
+                                                    uint32_t* child, uint32_t* level_offsets, void* ws,
+                                                    size_t ws_bytes, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Whole build: keys -> sort -> rebalance loop -> link, on one stream.
  *   x, y, z, box, curve      as cstone_compute_keys
@@ -177,18 +190,26 @@ CSTONE_API cstone_status cstone_link_octree(const uint64_t* leaves, size_t n_lea
  *                            or both NULL to skip linking
  *   level_offsets            device, 23 uint32 (ignored when node_keys is NULL)
  *   ws                       device workspace, cstone_build_workspace_bytes(n, leaf_capacity)
- *   stage_ms                 host, 4 floats or NULL: milliseconds spent in keys,
- *                            sort, rebalance and link (measured with HIP events)
+ *   timings                  host, or NULL: HIP-event times of the stages and of
+ *                            every radix-sort pass of the particle keys (events
+ *                            are recorded on `stream` only when this is non-NULL)
  * Synchronises `stream`. Errors: those of the stages; NONFINITE if a
  * coordinate is NaN or infinite (found at the first synchronisation, the
  * outputs are then unspecified and no linking is done).
  */
+typedef struct cstone_timings {
+    float stage_ms[4];     /* keys, sort, rebalance loop, link */
+    float sort_pass_ms[8]; /* each digit pass of the particle-key sort */
+    uint32_t sort_passes;  /* entries of sort_pass_ms in use */
+} cstone_timings;
+
 CSTONE_API size_t cstone_build_workspace_bytes(size_t n, size_t leaf_capacity);
 CSTONE_API cstone_status cstone_build(const double* x, const double* y, const double* z, size_t n, const cstone_box* box,
                            cstone_curve curve, uint32_t n_crit, uint64_t* sorted_keys, uint32_t* perm,
                            uint64_t* leaves, size_t* n_leaves, size_t leaf_capacity, uint32_t* counts,
                            uint64_t* node_keys, uint32_t* child, uint32_t* level_offsets, uint32_t max_iters,
-                           uint32_t* iters_done, void* ws, size_t ws_bytes, float* stage_ms, hipStream_t stream);
+                           uint32_t* iters_done, void* ws, size_t ws_bytes, cstone_timings* timings,
+                           hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -39,6 +39,11 @@ class CstoneError(RuntimeError):
         self.name = STATUS.get(status, str(status))
 
 
+class Timings(ctypes.Structure):
+    _fields_ = [("stage_ms", ctypes.c_float * 4), ("sort_pass_ms", ctypes.c_float * 8),
+                ("sort_passes", ctypes.c_uint32)]
+
+
 class Box(ctypes.Structure):
     _fields_ = [("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3)]
 
@@ -63,15 +68,16 @@ def _load() -> ctypes.CDLL:
         "cstone_sort_workspace_bytes": (sz, [sz]),
         "cstone_sort": (i32, [P, P, P, sz, P, sz, P]),
         "cstone_node_counts": (i32, [P, sz, P, sz, P, P]),
-        "cstone_rebalance_workspace_bytes": (sz, [sz]),
+        "cstone_rebalance_workspace_bytes": (sz, [sz, u32, sz]),
         "cstone_rebalance": (i32, [P, sz, u32, P, psz, sz, P, u32, pu32, P, sz, P]),
         "cstone_leaf_capacity_bound": (sz, [sz, u32, sz]),
         "cstone_node_count": (sz, [sz]),
         "cstone_link_workspace_bytes": (sz, [sz]),
         "cstone_link_octree": (i32, [P, sz, P, P, P, P, sz, P]),
+        "cstone_link_octree_by_sort": (i32, [P, sz, P, P, P, P, sz, P]),
         "cstone_build_workspace_bytes": (sz, [sz, sz]),
         "cstone_build": (i32, [P, P, P, sz, pbox, i32, u32, P, P, P, psz, sz, P, P, P, P, u32, pu32, P, sz,
-                               ctypes.POINTER(ctypes.c_float), P]),
+                               ctypes.POINTER(Timings), P]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -191,7 +197,7 @@ def rebalance(sorted_keys, n_crit: int, leaves=None, capacity=None, max_iters: i
     if leaves is not None:
         buf[: nl0 + 1].copy_(leaves)
     counts = torch.empty(capacity, dtype=torch.int32, device=dev)
-    need = _lib.cstone_rebalance_workspace_bytes(capacity)
+    need = _lib.cstone_rebalance_workspace_bytes(n, int(n_crit), capacity)
     if ws is None:
         ws = _workspace(need, dev)
     nl = ctypes.c_size_t(nl0)
@@ -208,8 +214,9 @@ def rebalance(sorted_keys, n_crit: int, leaves=None, capacity=None, max_iters: i
     return buf[: nl.value + 1], counts[: nl.value], int(rounds.value)
 
 
-def link_octree(leaves, node_keys=None, child=None, level_offsets=None, ws=None, stream=None):
-    """Fully linked octree of a cornerstone array: (NK, CO, LO)."""
+def link_octree(leaves, node_keys=None, child=None, level_offsets=None, ws=None, stream=None, by_sort=False):
+    """Fully linked octree of a cornerstone array: (NK, CO, LO). With
+    by_sort=True the paper's literal five steps are used (same outputs)."""
     nl = leaves.numel() - 1
     n = node_count(nl)
     dev = leaves.device
@@ -222,8 +229,9 @@ def link_octree(leaves, node_keys=None, child=None, level_offsets=None, ws=None,
     need = _lib.cstone_link_workspace_bytes(nl)
     if ws is None:
         ws = _workspace(need, dev)
-    _check(_lib.cstone_link_octree(_ptr(leaves), nl, _ptr(node_keys), _ptr(child), _ptr(level_offsets), _ptr(ws),
-                                   ws.numel(), _stream(stream)), "cstone_link_octree")
+    fn = _lib.cstone_link_octree_by_sort if by_sort else _lib.cstone_link_octree
+    _check(fn(_ptr(leaves), nl, _ptr(node_keys), _ptr(child), _ptr(level_offsets), _ptr(ws), ws.numel(),
+              _stream(stream)), "cstone_link_octree")
     return node_keys[:n], child[:n], level_offsets
 
 
@@ -239,7 +247,8 @@ class BuildResult:
     child: torch.Tensor | None
     level_offsets: torch.Tensor | None
     rounds: int
-    stage_ms: tuple
+    stage_ms: tuple      # keys, sort, rebalance, link (timed builds only)
+    sort_pass_ms: tuple  # every digit pass of the particle sort (timed builds only)
 
 
 class Builder:
@@ -273,13 +282,13 @@ class Builder:
             _dev(t, torch.float64)
         nl = ctypes.c_size_t(self.n_leaves if incremental else 0)
         rounds = ctypes.c_uint32(0)
-        ms = (ctypes.c_float * 4)()
+        tm = Timings()
         b = Box.of(box)
         st = _lib.cstone_build(_ptr(x), _ptr(y), _ptr(z), n, ctypes.byref(b), int(curve), int(n_crit),
                                _ptr(self.sorted_keys), _ptr(self.perm), _ptr(self.leaves), ctypes.byref(nl),
                                self.capacity, _ptr(self.counts), _ptr(self.node_keys), _ptr(self.child),
                                _ptr(self.level_offsets), int(max_iters), ctypes.byref(rounds), _ptr(self.ws),
-                               self.ws.numel(), ms if timed else None, _stream(stream))
+                               self.ws.numel(), ctypes.byref(tm) if timed else None, _stream(stream))
         if st != 0:
             err = CstoneError(st, "cstone_build")
             err.n_leaves = nl.value
@@ -289,7 +298,9 @@ class Builder:
         nn = node_count(nlv)
         return BuildResult(self.sorted_keys[:n], self.perm[:n], self.leaves[: nlv + 1], self.counts[:nlv],
                            self.node_keys[:nn] if self.link else None, self.child[:nn] if self.link else None,
-                           self.level_offsets if self.link else None, int(rounds.value), tuple(ms) if timed else ())
+                           self.level_offsets if self.link else None, int(rounds.value),
+                           tuple(tm.stage_ms) if timed else (),
+                           tuple(tm.sort_pass_ms[: tm.sort_passes]) if timed else ())
 
 
 def build(x, y, z, box, curve=HILBERT, n_crit: int = 64, link: bool = True) -> BuildResult:

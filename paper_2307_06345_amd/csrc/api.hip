@@ -61,7 +61,9 @@ cstone_status cstone_node_counts(const uint64_t* sorted_keys, size_t n, const ui
     return launch_node_counts(sorted_keys, n, leaves, n_leaves, counts, stream);
 }
 
-size_t cstone_rebalance_workspace_bytes(size_t leaf_capacity) { return rebalance_workspace_bytes(leaf_capacity); }
+size_t cstone_rebalance_workspace_bytes(size_t n, uint32_t n_crit, size_t leaf_capacity) {
+    return rebalance_workspace_bytes(n, n_crit, leaf_capacity);
+}
 
 size_t cstone_leaf_capacity_bound(size_t n, uint32_t n_crit, size_t n_leaves_start) {
     const size_t full = n / (static_cast<size_t>(n_crit) + 1);
@@ -87,15 +89,25 @@ cstone_status cstone_link_octree(const uint64_t* leaves, size_t n_leaves, uint64
                                  uint32_t* level_offsets, void* ws, size_t ws_bytes, hipStream_t stream) {
     if (n_leaves < 1 || n_leaves > kMaxN || (n_leaves - 1) % 7 != 0) return CSTONE_ERR_INVALID_ARG;
     if (!leaves || !node_keys || !child || !level_offsets || !ws) return CSTONE_ERR_INVALID_ARG;
-    return launch_link(leaves, n_leaves, node_keys, child, level_offsets, ws, ws_bytes, stream);
+    return launch_link(leaves, n_leaves, nullptr, node_keys, child, level_offsets, ws, ws_bytes, stream);
+}
+
+cstone_status cstone_link_octree_by_sort(const uint64_t* leaves, size_t n_leaves, uint64_t* node_keys, uint32_t* child,
+                                         uint32_t* level_offsets, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (n_leaves < 1 || n_leaves > kMaxN || (n_leaves - 1) % 7 != 0) return CSTONE_ERR_INVALID_ARG;
+    if (!leaves || !node_keys || !child || !level_offsets || !ws) return CSTONE_ERR_INVALID_ARG;
+    return launch_link_by_sort(leaves, n_leaves, node_keys, child, level_offsets, ws, ws_bytes, stream);
 }
 
 size_t cstone_build_workspace_bytes(size_t n, size_t leaf_capacity) {
     Carve c(nullptr);
     c.take<uint64_t>(n);  // unsorted keys
     c.take<uint32_t>(1);  // non-finite flag
+    // the sort runs before the loop; the loop and the link share the stream
+    // without a host check in between, so they get separate parts (the split
+    // list of the loop is largest for n_crit = 1)
     size_t stage = std::max(sort_workspace_bytes(n, true),
-                            std::max(rebalance_workspace_bytes(leaf_capacity), link_workspace_bytes(leaf_capacity)));
+                            rebalance_workspace_bytes(n, 1, leaf_capacity) + link_workspace_bytes(leaf_capacity));
     return c.off + stage;
 }
 
@@ -103,7 +115,8 @@ cstone_status cstone_build(const double* x, const double* y, const double* z, si
                            cstone_curve curve, uint32_t n_crit, uint64_t* sorted_keys, uint32_t* perm,
                            uint64_t* leaves, size_t* n_leaves, size_t leaf_capacity, uint32_t* counts,
                            uint64_t* node_keys, uint32_t* child, uint32_t* level_offsets, uint32_t max_iters,
-                           uint32_t* iters_done, void* ws, size_t ws_bytes, float* stage_ms, hipStream_t stream) {
+                           uint32_t* iters_done, void* ws, size_t ws_bytes, cstone_timings* timings,
+                           hipStream_t stream) {
     if (n > kMaxN || n_crit == 0 || !box_ok(box) || !leaves || !n_leaves || !ws) return CSTONE_ERR_INVALID_ARG;
     if (curve != CSTONE_MORTON && curve != CSTONE_HILBERT) return CSTONE_ERR_INVALID_ARG;
     if (n && (!x || !y || !z || !sorted_keys || !perm)) return CSTONE_ERR_INVALID_ARG;
@@ -118,15 +131,22 @@ cstone_status cstone_build(const double* x, const double* y, const double* z, si
     const size_t stage_bytes = ws_bytes - c.off;
 
     hipEvent_t ev[5] = {};
-    const bool timed = stage_ms != nullptr;
-    if (timed)
-        for (auto& e : ev) CS_HIP(hipEventCreate(&e));
-    auto mark = [&](int i) -> hipError_t { return timed ? hipEventRecord(ev[i], stream) : hipSuccess; };
+    hipEvent_t pass_ev[9] = {};
+    const int passes = sort_passes(63);
+    const bool timed = timings != nullptr;
     auto cleanup = [&]() {
-        if (timed)
-            for (auto& e : ev)
-                if (e) (void)hipEventDestroy(e);
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+        for (auto& e : pass_ev)
+            if (e) (void)hipEventDestroy(e);
     };
+    if (timed) {
+        for (auto& e : ev)
+            if (hipEventCreate(&e) != hipSuccess) { cleanup(); return CSTONE_ERR_DEVICE; }
+        for (int i = 0; i <= passes; ++i)
+            if (hipEventCreate(&pass_ev[i]) != hipSuccess) { cleanup(); return CSTONE_ERR_DEVICE; }
+    }
+    auto mark = [&](int i) -> hipError_t { return timed ? hipEventRecord(ev[i], stream) : hipSuccess; };
     cstone_status s = CSTONE_OK;
     uint32_t host_flag = 0;
     size_t nl = *n_leaves;
@@ -136,24 +156,47 @@ cstone_status cstone_build(const double* x, const double* y, const double* z, si
         s = launch_keys(x, y, z, n, *box, curve, keys, flag, stream);
         if (s != CSTONE_OK) break;
         if (mark(1) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
-        s = launch_sort(keys, sorted_keys, perm, n, 63, stage_ws, stage_bytes, stream);
+        s = launch_sort(keys, sorted_keys, perm, n, 63, stage_ws, stage_bytes, stream,
+                        timed && n ? pass_ev : nullptr);
         if (s != CSTONE_OK) break;
         if (mark(2) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
         if (nl == 0) nl = 1;  // start from the root leaf {0, 8^L}
-        s = run_rebalance(sorted_keys, n, n_crit, leaves, &nl, leaf_capacity, counts, max_iters, iters_done, stage_ws,
-                          stage_bytes, stream, flag, &host_flag);
-        *n_leaves = nl;
-        if (host_flag & CSTONE_FLAG_NONFINITE) { s = CSTONE_ERR_NONFINITE; break; }
+        // the loop and the link are enqueued together; the host looks once,
+        // after the link, and only goes round again if the loop needs more rounds
+        const size_t reb_bytes = rebalance_workspace_bytes(n, n_crit, leaf_capacity);
+        void* link_ws = static_cast<char*>(stage_ws) + reb_bytes;
+        const size_t link_bytes = stage_bytes - reb_bytes;
+        RebalanceLoop loop;
+        s = loop.begin(sorted_keys, n, n_crit, leaves, nl, leaf_capacity, counts, max_iters, stage_ws, reb_bytes,
+                       stream, flag);
         if (s != CSTONE_OK) break;
-        if (mark(3) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
-        if (node_keys) {
-            s = launch_link(leaves, nl, node_keys, child, level_offsets, stage_ws, stage_bytes, stream);
-            if (s != CSTONE_OK) break;
+        bool finished = false;
+        for (uint32_t batch = 0; !finished; batch = 2) {
+            if ((s = loop.enqueue(batch)) != CSTONE_OK) break;
+            if (mark(3) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
+            if (node_keys) {
+                s = launch_link(leaves, leaf_capacity, loop.device_leaf_count(), node_keys, child, level_offsets,
+                                link_ws, link_bytes, stream);
+                if (s != CSTONE_OK) break;
+            }
+            if (mark(4) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
+            loop.wait(&finished);
         }
-        if (mark(4) != hipSuccess || hipStreamSynchronize(stream) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
-        if (timed)
+        if (s != CSTONE_OK) break;
+        *n_leaves = loop.n_leaves;
+        if (iters_done) *iters_done = loop.rounds;
+        host_flag = loop.input_flags;
+        if (host_flag & CSTONE_FLAG_NONFINITE) { s = CSTONE_ERR_NONFINITE; break; }
+        if ((s = loop.status) != CSTONE_OK) break;
+        if (timed) {
             for (int i = 0; i < 4; ++i)
-                if (hipEventElapsedTime(&stage_ms[i], ev[i], ev[i + 1]) != hipSuccess) s = CSTONE_ERR_DEVICE;
+                if (hipEventElapsedTime(&timings->stage_ms[i], ev[i], ev[i + 1]) != hipSuccess) s = CSTONE_ERR_DEVICE;
+            timings->sort_passes = n ? static_cast<uint32_t>(passes) : 0u;
+            for (int p = 0; p < 8; ++p) timings->sort_pass_ms[p] = 0.f;
+            for (int p = 0; n && p < passes; ++p)
+                if (hipEventElapsedTime(&timings->sort_pass_ms[p], pass_ev[p], pass_ev[p + 1]) != hipSuccess)
+                    s = CSTONE_ERR_DEVICE;
+        }
     } while (false);
     cleanup();
     return s;

@@ -131,6 +131,72 @@ __device__ __forceinline__ uint64_t lookback(const uint64_t* words, size_t strid
     return excl;
 }
 
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+// Exclusive prefix of `tile` over one counter (words[p] for tile p), resolved
+// by a whole wave: each step reads the 64 nearest unresolved predecessors at
+// once, so a long run of aggregates costs one round trip per 64 tiles. Every
+// lane returns the same value; all 64 lanes must call it together.
+__device__ __forceinline__ uint64_t lookback_wave(const uint64_t* words, uint32_t tile, uint32_t epoch,
+                                                  uint32_t* err) {
+    const uint32_t lane = lane_id();
+    uint64_t excl = 0;
+    int64_t top = static_cast<int64_t>(tile) - 1;
+    uint32_t spins = 0;
+    while (top >= 0) {
+        const int64_t p = top - lane;
+        const bool valid = p >= 0;
+        const uint64_t w = valid ? ld_agent(words + p) : 0ull;
+        const uint64_t flag = w & (3ull << 62);
+        const bool mine = ((w >> 48) & 0x3fffu) == (epoch & 0x3fffu);
+        const bool ready = !valid || (flag != 0 && mine);
+        const uint64_t inc = __ballot(valid && ready && flag == kFlagInc);
+        const uint64_t pending = __ballot(!ready);
+        // lanes up to and including the nearest inclusive prefix (all if none)
+        const uint64_t upto = inc ? ((inc & (~inc + 1)) << 1) - 1 : ~0ull;
+        if (pending & upto) {
+            if (++spins > kSpinLimit) {
+                if (lane == 0) atomicOr(err, kErrSpin);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        excl += wave_sum<uint64_t>((valid && ((upto >> lane) & 1ull)) ? (w & kValueMask) : 0ull);
+        if (inc) break;
+        top -= kWave;
+    }
+    return excl;
+}
+
+// First index in [lo, hi) of a sorted array whose key is >= k, searched by a
+// whole wave with 63 probes per step (log64 dependent loads instead of log2).
+// lo, hi and k must be the same in every lane; all 64 lanes must call it.
+__device__ __forceinline__ uint32_t wave_lower_bound(const uint64_t* a, uint32_t lo, uint32_t hi, uint64_t k) {
+    const uint32_t lane = lane_id();
+    while (hi - lo > kWave) {
+        const uint32_t len = hi - lo;
+        bool below = false;
+        if (lane < kWave - 1) {
+            const uint32_t s = lo + static_cast<uint32_t>((static_cast<uint64_t>(len) * (lane + 1)) >> 6);
+            below = a[s] < k;
+        }
+        const uint32_t c = static_cast<uint32_t>(__popcll(__ballot(below)));  // probes below k form a prefix
+        const uint32_t new_lo = c ? lo + static_cast<uint32_t>((static_cast<uint64_t>(len) * c) >> 6) + 1 : lo;
+        const uint32_t new_hi =
+            c < kWave - 1 ? lo + static_cast<uint32_t>((static_cast<uint64_t>(len) * (c + 1)) >> 6) : hi;
+        lo = new_lo;
+        hi = new_hi;
+    }
+    const bool below = lane < hi - lo && a[lo + lane] < k;
+    return lo + static_cast<uint32_t>(__popcll(__ballot(below)));
+}
+
 // Dynamic tile index: blocks take tiles in launch order through an atomic
 // counter, so a block waiting on tile t-1 knows t-1 is already owned by a
 // running block (forward progress for the look-back).

@@ -1,6 +1,9 @@
 // Fully linked octree (Sec. 5): node keys NK in placeholder-bit form,
 // breadth-first order, child offsets CO and level offsets LO.
 //
+// Two paths with identical outputs. launch_link places every node at its
+// breadth-first index directly (see "breadth-first placement" below).
+// launch_link_by_sort follows the five steps of Sec. 5:
 //   step 1+2  one thread per leaf i writes the leaf's node key at n_i + i and,
 //             if the common prefix d of K_i and K_{i+1} is a whole number of
 //             octal digits, the internal node with that prefix (the boundary
@@ -76,17 +79,184 @@ __global__ __launch_bounds__(kLinkBlock) void child_offsets_kernel(const uint64_
     co[p] = c;
 }
 
+// ---- breadth-first placement without sorting ---------------------------------
+//
+// Every node starts at exactly one leaf: its first one. Leaf j starts the
+// nodes of levels a_j + 1 .. lambda_j, where lambda_j is its own level and a_j
+// the level of its deepest common ancestor with leaf j - 1 (a_0 = -1), and in
+// breadth-first order the nodes of one level are in leaf order. So node (l, j)
+// sits at LO[l] + #{j' < j : a_j' < l <= lambda_j'}, and its first child is
+// node (l + 1, j), started by the same leaf. One counting pass, a scan per
+// level over the tiles, and one writing pass replace steps 3-5.
+
+constexpr int kLevels = kL + 1;
+constexpr int kBfBlock = 256;
+constexpr int kBfItems = 4;
+constexpr int kBfTile = kBfBlock * kBfItems;
+constexpr int kBfWaves = kBfBlock / kWave;
+
+struct LeafLevels {
+    int a[kBfItems];
+    int lam[kBfItems];
+};
+
+__device__ __forceinline__ LeafLevels leaf_levels(const uint64_t* __restrict__ K, size_t nl, size_t first) {
+    LeafLevels r;
+#pragma unroll
+    for (int it = 0; it < kBfItems; ++it) {
+        const size_t j = first + it;
+        r.a[it] = 0;
+        r.lam[it] = -1;  // no levels for padding items
+        if (j < nl) {
+            const uint64_t kj = K[j];
+            r.lam[it] = span_level(K[j + 1] - kj);
+            r.a[it] = j ? (clz64(K[j - 1] ^ kj) - 1) / 3 : -1;
+        }
+    }
+    return r;
+}
+
+__device__ __forceinline__ uint32_t level_count(const LeafLevels& r, int l) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int it = 0; it < kBfItems; ++it) c += (r.a[it] < l && l <= r.lam[it]) ? 1u : 0u;
+    return c;
+}
+
+// Per tile and level: number of nodes the tile's leaves start (level-major,
+// row stride `stride` tiles). The leaf count comes from nl_dev if set.
+__global__ __launch_bounds__(kBfBlock) void bf_count_kernel(const uint64_t* __restrict__ K, const uint64_t* nl_dev,
+                                                            size_t nl_host, uint32_t* __restrict__ tile_counts,
+                                                            uint32_t stride) {
+    __shared__ uint32_t wtot[kLevels][kBfWaves];
+    const size_t nl = nl_dev ? *nl_dev : nl_host;
+    const uint32_t tiles = static_cast<uint32_t>((nl + kBfTile - 1) / kBfTile);
+    const uint32_t wave = threadIdx.x / kWave;
+    for (uint32_t tile = blockIdx.x; tile < tiles && tile < stride; tile += gridDim.x) {
+        const LeafLevels r = leaf_levels(K, nl, static_cast<size_t>(tile) * kBfTile + threadIdx.x * kBfItems);
+#pragma unroll
+        for (int l = 0; l < kLevels; ++l) {
+            const uint32_t s = wave_sum<uint32_t>(level_count(r, l));
+            if (lane_id() == 0) wtot[l][wave] = s;
+        }
+        __syncthreads();
+        if (threadIdx.x < kLevels) {
+            uint32_t s = 0;
+#pragma unroll
+            for (int w = 0; w < kBfWaves; ++w) s += wtot[threadIdx.x][w];
+            tile_counts[static_cast<size_t>(threadIdx.x) * stride + tile] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// One block per level: exclusive scan over the tiles, in place; level totals.
+__global__ __launch_bounds__(kBfBlock) void bf_scan_kernel(uint32_t* __restrict__ tile_counts, const uint64_t* nl_dev,
+                                                           size_t nl_host, uint32_t stride,
+                                                           uint32_t* __restrict__ totals) {
+    __shared__ uint32_t tmp[kBfWaves];
+    const size_t nl = nl_dev ? *nl_dev : nl_host;
+    const uint32_t tiles = min(static_cast<uint32_t>((nl + kBfTile - 1) / kBfTile), stride);
+    uint32_t* row = tile_counts + static_cast<size_t>(blockIdx.x) * stride;
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < tiles; base += kBfBlock) {
+        const uint32_t t = base + threadIdx.x;
+        const uint32_t v = t < tiles ? row[t] : 0u;
+        uint32_t sum;
+        const uint32_t ex = block_exclusive_sum<uint32_t, kBfBlock>(v, tmp, &sum);
+        if (t < tiles) row[t] = carry + ex;
+        carry += sum;
+    }
+    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
+}
+
+__global__ __launch_bounds__(kBfBlock) void bf_write_kernel(const uint64_t* __restrict__ K, const uint64_t* nl_dev,
+                                                            size_t nl_host, const uint32_t* __restrict__ tile_offsets,
+                                                            uint32_t stride, const uint32_t* __restrict__ totals,
+                                                            uint64_t* __restrict__ nk, uint32_t* __restrict__ co,
+                                                            uint32_t* __restrict__ lo_out) {
+    __shared__ uint32_t lo[kLevels + 1];
+    __shared__ uint32_t wtot[kLevels][kBfWaves];
+    __shared__ uint32_t run[kLevels][kBfBlock];  // next index per level for each thread
+    const size_t nl = nl_dev ? *nl_dev : nl_host;
+    const size_t n = nl + (nl - 1) / 7;
+    const uint32_t tiles = static_cast<uint32_t>((nl + kBfTile - 1) / kBfTile);
+    const uint32_t tid = threadIdx.x;
+    const uint32_t wave = tid / kWave;
+    if (tid < kWave) {  // LO: exclusive scan of the level totals
+        const uint32_t v = tid < kLevels ? totals[tid] : 0u;
+        const uint32_t inc = wave_inclusive_sum(v);
+        if (tid <= kLevels) lo[tid] = inc - v;
+        if (blockIdx.x == 0 && tid <= kLevels) lo_out[tid] = tid < kLevels ? inc - v : static_cast<uint32_t>(n);
+    }
+    for (uint32_t tile = blockIdx.x; tile < tiles && tile < stride; tile += gridDim.x) {
+        const size_t first = static_cast<size_t>(tile) * kBfTile + tid * kBfItems;
+        const LeafLevels r = leaf_levels(K, nl, first);
+        uint32_t c[kLevels], inc[kLevels];
+#pragma unroll
+        for (int l = 0; l < kLevels; ++l) {
+            c[l] = level_count(r, l);
+            inc[l] = wave_inclusive_sum(c[l]);
+            if (lane_id() == kWave - 1) wtot[l][wave] = inc[l];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int l = 0; l < kLevels; ++l) {
+            uint32_t before = 0;
+#pragma unroll
+            for (int w = 0; w < kBfWaves; ++w) before += w < static_cast<int>(wave) ? wtot[l][w] : 0u;
+            run[l][tid] = lo[l] + tile_offsets[static_cast<size_t>(l) * stride + tile] + before + inc[l] - c[l];
+        }
+        // each thread only touches its own column of run[][]
+#pragma unroll
+        for (int it = 0; it < kBfItems; ++it) {
+            const size_t j = first + it;
+            if (j >= nl) continue;
+            const uint64_t kj = K[j];
+            for (int l = r.a[it] + 1; l <= r.lam[it]; ++l) {
+                const uint32_t p = run[l][tid]++;
+                if (p >= n) continue;  // always in range for a cornerstone array; guards memory
+                nk[p] = (1ull << (3 * l)) | (kj >> (3 * (kL - l)));
+                co[p] = l < r.lam[it] ? run[l + 1][tid] : 0u;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
 size_t link_workspace_bytes(size_t n_leaves) {
     const size_t n = n_leaves + (n_leaves ? (n_leaves - 1) / 7 : 0);
     Carve c(nullptr);
     c.take<uint64_t>(n);
-    return c.off + sort_workspace_bytes(n, false);
+    const size_t by_sort = c.off + sort_workspace_bytes(n, false);
+    Carve b(nullptr);
+    b.take<uint32_t>(static_cast<size_t>(kLevels) * ((n_leaves + kBfTile - 1) / kBfTile));
+    b.take<uint32_t>(kLevels);
+    return std::max(by_sort, b.off);
 }
 
-cstone_status launch_link(const uint64_t* leaves, size_t nl, uint64_t* node_keys, uint32_t* child,
-                          uint32_t* level_offsets, void* ws, size_t ws_bytes, hipStream_t stream) {
+cstone_status launch_link(const uint64_t* leaves, size_t nl, const uint64_t* nl_dev, uint64_t* node_keys,
+                          uint32_t* child, uint32_t* level_offsets, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (ws_bytes < link_workspace_bytes(nl)) return CSTONE_ERR_INVALID_ARG;
+    const uint32_t stride = static_cast<uint32_t>((nl + kBfTile - 1) / kBfTile);  // tiles of the largest array
+    Carve c(ws);
+    uint32_t* tile_counts = c.take<uint32_t>(static_cast<size_t>(kLevels) * stride);
+    uint32_t* totals = c.take<uint32_t>(kLevels);
+    const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(stride, 2048));
+    hipLaunchKernelGGL(bf_count_kernel, dim3(grid), dim3(kBfBlock), 0, stream, leaves, nl_dev, nl, tile_counts,
+                       stride);
+    hipLaunchKernelGGL(bf_scan_kernel, dim3(kLevels), dim3(kBfBlock), 0, stream, tile_counts, nl_dev, nl, stride,
+                       totals);
+    hipLaunchKernelGGL(bf_write_kernel, dim3(grid), dim3(kBfBlock), 0, stream, leaves, nl_dev, nl, tile_counts, stride,
+                       totals, node_keys, child, level_offsets);
+    CS_HIP(hipGetLastError());
+    return CSTONE_OK;
+}
+
+cstone_status launch_link_by_sort(const uint64_t* leaves, size_t nl, uint64_t* node_keys, uint32_t* child,
+                                  uint32_t* level_offsets, void* ws, size_t ws_bytes, hipStream_t stream) {
     if (ws_bytes < link_workspace_bytes(nl)) return CSTONE_ERR_INVALID_ARG;
     const size_t n = nl + (nl - 1) / 7;
     Carve c(ws);

@@ -3,13 +3,20 @@
 // The loop keeps, next to the cornerstone array K, the position of every key
 // of K in the sorted particle keys P (the lower bound that f computes). A
 // leaf's count is the difference of two adjacent positions, and the combined
-// count of 8 sibling leaves is the difference of the positions around them, so
-// one kernel per round does g1 (decision), g2 (exclusive scan of O, single
-// pass with decoupled look-back) and g3 (writing K'), and hands f of the next
-// round the positions of K': copied leaves keep theirs, and only the 7 inner
-// boundaries of a split leaf are searched, inside that leaf's own range of P.
+// count of 8 sibling leaves is the difference of the positions around them.
+// Each round is two kernels:
+//   round_kernel   g1 (decision), g2 (exclusive scan of O in one pass with a
+//                  wave-wide decoupled look-back) and g3 (writing K'); copied
+//                  leaves and the first child of a split keep their position,
+//                  and every split leaf is appended to a list;
+//   split_search   f for the next round: the 7 inner boundaries of every split
+//                  leaf, searched inside that leaf's own range of P, spread
+//                  over the whole GPU (one lane per search, or one wave with
+//                  63 probes per step when the range is long).
 // Rounds are enqueued ahead of the host's convergence check; a round that
-// starts after convergence (or after a capacity overflow) exits at once.
+// starts after convergence (or after a capacity overflow) exits at once, and a
+// finalize kernel leaves the last complete round's array in place with its
+// counts and its leaf count in device memory.
 #include <algorithm>
 #include <cstring>
 
@@ -24,16 +31,26 @@ constexpr int kCountBlock = 256;
 constexpr int kRBlock = 256;
 constexpr int kRItems = 4;
 constexpr int kRTile = kRBlock * kRItems;
-constexpr uint32_t kMaxRoundGrid = 2048;
+constexpr uint32_t kMaxGrid = 2048;
+constexpr uint32_t kSearchBlock = 256;
+constexpr uint32_t kWaveSearchMin = 1024;  // ranges at least this long use a whole wave
+
+}  // namespace
 
 // Device-side loop state.
 struct LoopState {
     uint64_t nl[kMaxRounds + 1];    // leaves entering round r
     uint32_t changed[kMaxRounds];   // some O_i != 1 in round r
     uint32_t counters[kMaxRounds];  // dynamic tile counter of round r
+    uint32_t nsplit[kMaxRounds];    // split leaves listed in round r
     uint32_t err;
-    uint32_t input_flags;           // copy of the caller's key-stage flag word
+    uint32_t input_flags;  // copy of the caller's key-stage flag word
+    uint64_t final_nl;     // set by finalize_kernel: leaves of the result array
+    uint32_t final_last;   // rounds behind it
+    uint32_t final_code;   // 0 running, 1 converged, 2 capacity exceeded
 };
+
+namespace {
 
 // ---- f as a standalone operation -----------------------------------------
 
@@ -60,14 +77,6 @@ __global__ __launch_bounds__(kCountBlock) void positions_kernel(const uint64_t* 
     if (i <= nl) pos[i] = static_cast<uint32_t>(lower_bound_u64(P, 0, n, K[i]));
 }
 
-// Leaf counts from positions.
-__global__ __launch_bounds__(kCountBlock) void counts_from_positions_kernel(const uint32_t* __restrict__ pos,
-                                                                             size_t nl,
-                                                                             uint32_t* __restrict__ counts) {
-    const size_t i = static_cast<size_t>(blockIdx.x) * kCountBlock + threadIdx.x;
-    if (i < nl) counts[i] = pos[i + 1] - pos[i];
-}
-
 __global__ __launch_bounds__(256) void loop_init_kernel(LoopState* st, uint64_t nl0, uint64_t* lb, size_t lb_words,
                                                         uint32_t* pos, uint32_t n, int root, uint64_t* K,
                                                         const uint32_t* input_flags) {
@@ -77,6 +86,7 @@ __global__ __launch_bounds__(256) void loop_init_kernel(LoopState* st, uint64_t 
     if (t < kMaxRounds) {
         st->changed[t] = 0;
         st->counters[t] = 0;
+        st->nsplit[t] = 0;
     }
     if (t <= kMaxRounds) st->nl[t] = t == 0 ? nl0 : 0;
     if (t == 0) {
@@ -91,19 +101,17 @@ __global__ __launch_bounds__(256) void loop_init_kernel(LoopState* st, uint64_t 
     }
 }
 
-// ---- one round: g1 + g2 + g3, and the positions of K' ----------------------
+// ---- one round: g1 + g2 + g3 -------------------------------------------------
 
-__global__ __launch_bounds__(kRBlock) void round_kernel(const uint64_t* __restrict__ P, uint32_t n, uint32_t n_crit,
-                                                         const uint64_t* __restrict__ K,
+__global__ __launch_bounds__(kRBlock) void round_kernel(uint32_t n, uint32_t n_crit, const uint64_t* __restrict__ K,
                                                          const uint32_t* __restrict__ pos,
                                                          uint64_t* __restrict__ K_out, uint32_t* __restrict__ pos_out,
+                                                         uint64_t* __restrict__ splits, uint32_t split_capacity,
                                                          LoopState* st, int round, uint64_t capacity, uint64_t* lb) {
     __shared__ uint32_t slot;
     __shared__ uint64_t scan_tmp[kRBlock / kWave];
     __shared__ uint64_t tile_prefix;
-    __shared__ uint32_t nsplit;
-    __shared__ uint16_t split_leaf[kRTile];
-    __shared__ uint32_t split_off[kRTile];
+    __shared__ uint32_t split_base;
     __shared__ uint32_t any_change;
 
     if (round > 0 && st->changed[round - 1] == 0) return;  // converged in an earlier round
@@ -117,13 +125,11 @@ __global__ __launch_bounds__(kRBlock) void round_kernel(const uint64_t* __restri
     for (;;) {
         const uint32_t tile = take_tile(&st->counters[round], &slot);
         if (tile >= tiles) break;
-        if (tid == 0) nsplit = 0;
-        const uint64_t tile_first = static_cast<uint64_t>(tile) * kRTile;
-        const uint64_t first = tile_first + static_cast<uint64_t>(tid) * kRItems;
+        const uint64_t first = static_cast<uint64_t>(tile) * kRTile + static_cast<uint64_t>(tid) * kRItems;
 
         // g1: decision O_i for this thread's leaves
         uint32_t op[kRItems];
-        uint64_t sum = 0;
+        uint32_t osum = 0, nsplit = 0;
         bool changed = false;
 #pragma unroll
         for (int j = 0; j < kRItems; ++j) {
@@ -137,7 +143,8 @@ __global__ __launch_bounds__(kRBlock) void round_kernel(const uint64_t* __restri
                 if (cnt > n_crit && delta > 1) {
                     o = 8;  // subdivide
                 } else if (delta < kKeyEnd) {  // the root never merges
-                    const uint64_t js = (ki % (8 * delta)) / delta;  // place among its siblings
+                    // place among its siblings, (K_i mod 8 delta) / delta; delta is a power of 8
+                    const uint64_t js = (ki >> (63 - clz64(delta))) & 7u;
                     if (js >= 1 && i >= js && i - js + 8 <= nl && K[i - js] + 8 * delta == K[i - js + 8] &&
                         pos[i - js + 8] - pos[i - js] <= n_crit)
                         o = 0;  // 8 sibling leaves with at most n_crit particles: merge
@@ -145,30 +152,38 @@ __global__ __launch_bounds__(kRBlock) void round_kernel(const uint64_t* __restri
                 changed |= (o != 1);
             }
             op[j] = o;
-            sum += o;
+            osum += o;
+            nsplit += o == 8;
         }
 
-        // g2: exclusive scan of O, in the block and then across tiles
+        // g2: exclusive scan of O (low word) and of the split count (high word)
         uint64_t block_total;
-        const uint64_t excl_thread = block_exclusive_sum<uint64_t, kRBlock>(sum, scan_tmp, &block_total);
-        if (tid == 0) {
+        const uint64_t excl = block_exclusive_sum<uint64_t, kRBlock>(
+            (static_cast<uint64_t>(nsplit) << 32) | osum, scan_tmp, &block_total);
+        if (tid < kWave) {
+            uint64_t prefix = 0;
             uint64_t* w = lb + tile;
+            const uint64_t agg = block_total & 0xffffffffull;
             if (tile == 0) {
-                st_agent(w, lb_word(kFlagInc, epoch, block_total));
-                tile_prefix = 0;
+                if (tid == 0) st_agent(w, lb_word(kFlagInc, epoch, agg));
             } else {
-                st_agent(w, lb_word(kFlagAgg, epoch, block_total));
-                const uint64_t ex = lookback(lb, 1, tile, epoch, &st->err);
-                st_agent(w, lb_word(kFlagInc, epoch, ex + block_total));
-                tile_prefix = ex;
+                if (tid == 0) st_agent(w, lb_word(kFlagAgg, epoch, agg));
+                prefix = lookback_wave(lb, tile, epoch, &st->err);
+                if (tid == 0) st_agent(w, lb_word(kFlagInc, epoch, prefix + agg));
+            }
+            if (tid == 0) {
+                tile_prefix = prefix;
+                const uint32_t s = static_cast<uint32_t>(block_total >> 32);
+                split_base = s ? atomicAdd(&st->nsplit[round], s) : 0u;
             }
         }
         if (changed) any_change = 1;
         __syncthreads();
         const uint64_t tp = tile_prefix;
 
-        // g3: K' (Eqs. rebalancecopy / rebalancesplit) and the positions of K'
-        uint64_t o_prime = tp + excl_thread;
+        // g3: K' (Eqs. rebalancecopy / rebalancesplit) and the known positions of K'
+        uint64_t o_prime = tp + (excl & 0xffffffffull);
+        uint32_t s_at = split_base + static_cast<uint32_t>(excl >> 32);
 #pragma unroll
         for (int j = 0; j < kRItems; ++j) {
             const uint64_t i = first + j;
@@ -185,10 +200,9 @@ __global__ __launch_bounds__(kRBlock) void round_kernel(const uint64_t* __restri
 #pragma unroll
                         for (int c = 0; c < 8; ++c) K_out[o_prime + c] = ki + c * child;
                         pos_out[o_prime] = pos[i];
-                        const uint32_t s = atomicAdd(&nsplit, 1u);
-                        split_leaf[s] = static_cast<uint16_t>(i - tile_first);
-                        split_off[s] = static_cast<uint32_t>(o_prime - tp);
+                        if (s_at < split_capacity) splits[s_at] = i | (o_prime << 32);
                     }
+                    ++s_at;
                 }
             }
             o_prime += op[j];
@@ -202,38 +216,119 @@ __global__ __launch_bounds__(kRBlock) void round_kernel(const uint64_t* __restri
             }
         }
         __syncthreads();
-
-        // f for the next round: the 7 inner child boundaries of each split leaf,
-        // one (leaf, child) pair per thread, searched in the parent's range of P
-        const uint32_t work = nsplit * 7u;
-        for (uint32_t w = tid; w < work; w += kRBlock) {
-            const uint32_t s = w / 7u;
-            const uint32_t c = w % 7u + 1u;
-            const uint64_t i = tile_first + split_leaf[s];
-            const uint64_t ki = K[i];
-            const uint64_t key = ki + c * ((K[i + 1] - ki) >> 3);
-            pos_out[tp + split_off[s] + c] = static_cast<uint32_t>(lower_bound_u64(P, pos[i], pos[i + 1], key));
-        }
-        __syncthreads();
     }
     if (tid == 0 && any_change) atomicOr(&st->changed[round], 1u);
+}
+
+// ---- f for the next round: positions of the inner child boundaries ----------
+
+__global__ __launch_bounds__(kSearchBlock) void split_search_kernel(const uint64_t* __restrict__ P,
+                                                                     const uint64_t* __restrict__ K,
+                                                                     const uint32_t* __restrict__ pos,
+                                                                     uint32_t* __restrict__ pos_out,
+                                                                     const uint64_t* __restrict__ splits,
+                                                                     uint32_t split_capacity, const LoopState* st,
+                                                                     int round, uint64_t capacity) {
+    const uint64_t nl = st->nl[round];
+    if (st->nl[round + 1] > capacity || nl > capacity) return;  // overflowed round: K' is discarded
+    const uint32_t listed = min(st->nsplit[round], split_capacity);
+    const uint32_t work = listed * 7u;
+    const uint32_t lane = lane_id();
+    const uint32_t waves = gridDim.x * (kSearchBlock / kWave);
+    const uint32_t wave = blockIdx.x * (kSearchBlock / kWave) + threadIdx.x / kWave;
+    // few searches (early rounds, long ranges): one per wave; many: 64 per wave
+    const uint32_t chunk = max(1u, min(static_cast<uint32_t>(kWave), (work + waves - 1) / waves));
+    for (uint32_t base = wave * chunk; base < work; base += waves * chunk) {
+        const uint32_t w = base + lane;
+        bool valid = lane < chunk && w < work;
+        uint32_t lo = 0, hi = 0, dst = 0;
+        uint64_t key = 0;
+        if (valid) {
+            const uint64_t e = splits[w / 7u];
+            const uint64_t i = e & 0xffffffffull;
+            const uint32_t c = w % 7u + 1u;
+            const uint64_t ki = K[i];
+            key = ki + c * ((K[i + 1] - ki) >> 3);
+            lo = pos[i];
+            hi = pos[i + 1];
+            dst = static_cast<uint32_t>(e >> 32) + c;
+        }
+        valid = valid && dst <= capacity;  // always true for a listed split; guards memory
+        const bool wide = valid && hi - lo >= kWaveSearchMin;
+        if (valid && !wide) pos_out[dst] = static_cast<uint32_t>(lower_bound_u64(P, lo, hi, key));
+        uint64_t todo = __ballot(wide);
+        while (todo) {
+            const int l = __ffsll(static_cast<long long>(todo)) - 1;
+            todo &= todo - 1;
+            const uint32_t l_lo = __shfl(lo, l, kWave);
+            const uint32_t l_hi = __shfl(hi, l, kWave);
+            const uint64_t l_key = __shfl(key, l, kWave);
+            const uint32_t at = wave_lower_bound(P, l_lo, l_hi, l_key);
+            if (static_cast<int>(lane) == l) pos_out[dst] = at;
+        }
+    }
+}
+
+// ---- pick the array of the last complete round --------------------------------
+
+struct Outcome {
+    uint32_t last;     // rounds completed (the array after them is the result)
+    uint32_t code;     // 0 running, 1 converged, 2 capacity exceeded
+    uint64_t nl;       // leaves of that array
+};
+
+__device__ __forceinline__ Outcome loop_outcome(const LoopState* st, uint32_t enqueued, uint64_t capacity) {
+    for (uint32_t q = 0; q < enqueued; ++q) {
+        if (st->nl[q + 1] > capacity) return {q, 2u, st->nl[q]};
+        if (st->changed[q] == 0) return {q + 1, 1u, st->nl[q + 1]};  // round q copied every leaf
+    }
+    return {enqueued, 0u, st->nl[enqueued]};
+}
+
+// Leaves the result array in K[0] (copied from K[1] when an odd number of
+// rounds completed), writes its counts, and publishes its leaf count.
+__global__ __launch_bounds__(256) void finalize_kernel(LoopState* st, uint32_t enqueued, uint64_t capacity,
+                                                       uint64_t* __restrict__ K0, const uint64_t* __restrict__ K1,
+                                                       const uint32_t* __restrict__ pos0,
+                                                       const uint32_t* __restrict__ pos1,
+                                                       uint32_t* __restrict__ counts) {
+    const Outcome o = loop_outcome(st, enqueued, capacity);
+    const uint64_t nl = o.nl <= capacity ? o.nl : 0;
+    const bool odd = o.last & 1u;
+    const uint32_t* pos = odd ? pos1 : pos0;
+    const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+    for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i <= nl; i += stride) {
+        if (odd) K0[i] = K1[i];
+        if (counts && i < nl) counts[i] = pos[i + 1] - pos[i];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->final_nl = nl;
+        st->final_last = o.last;
+        st->final_code = o.code;
+    }
 }
 
 struct RebalanceWs {
     uint64_t* K_alt;
     uint32_t* pos[2];
+    uint64_t* splits;
+    uint32_t split_capacity;
     LoopState* st;
     uint64_t* lb;
     size_t lb_words;
     size_t bytes;
 };
 
-RebalanceWs carve_rebalance(void* ws, size_t cap) {
+RebalanceWs carve_rebalance(void* ws, size_t n, uint32_t n_crit, size_t cap) {
     Carve c(ws);
     RebalanceWs r{};
     r.K_alt = c.take<uint64_t>(cap + 1);
     r.pos[0] = c.take<uint32_t>(cap + 1);
     r.pos[1] = c.take<uint32_t>(cap + 1);
+    // leaves that split in one round hold > n_crit particles each and are disjoint
+    const size_t max_splits = std::min<size_t>(cap, n / (static_cast<size_t>(n_crit) + 1)) + 1;
+    r.split_capacity = static_cast<uint32_t>(max_splits);
+    r.splits = c.take<uint64_t>(max_splits);
     r.st = c.take<LoopState>(1);
     r.lb_words = (cap + kRTile - 1) / kRTile + 1;
     r.lb = c.take<uint64_t>(r.lb_words);
@@ -242,6 +337,10 @@ RebalanceWs carve_rebalance(void* ws, size_t cap) {
 }
 
 uint32_t grid_1d(size_t items, int block) { return static_cast<uint32_t>((items + block - 1) / block); }
+
+uint32_t clamp_grid(size_t blocks) {
+    return static_cast<uint32_t>(std::max<size_t>(1, std::min<size_t>(blocks, kMaxGrid)));
+}
 
 }  // namespace
 
@@ -254,112 +353,123 @@ cstone_status launch_node_counts(const uint64_t* sorted_keys, size_t n, const ui
     return CSTONE_OK;
 }
 
-size_t rebalance_workspace_bytes(size_t leaf_capacity) { return carve_rebalance(nullptr, leaf_capacity).bytes; }
+size_t rebalance_workspace_bytes(size_t n, uint32_t n_crit, size_t leaf_capacity) {
+    return carve_rebalance(nullptr, n, n_crit ? n_crit : 1, leaf_capacity).bytes;
+}
 
-cstone_status run_rebalance(const uint64_t* P, size_t n, uint32_t n_crit, uint64_t* leaves, size_t* n_leaves,
-                            size_t cap, uint32_t* counts, uint32_t max_iters, uint32_t* iters_done, void* ws,
-                            size_t ws_bytes, hipStream_t stream, const uint32_t* input_flags,
-                            uint32_t* input_flags_out) {
-    RebalanceWs w = carve_rebalance(ws, cap);
+cstone_status RebalanceLoop::begin(const uint64_t* P, size_t n, uint32_t n_crit, uint64_t* leaves, size_t nl0,
+                                   size_t cap, uint32_t* counts, uint32_t max_iters, void* ws, size_t ws_bytes,
+                                   hipStream_t stream, const uint32_t* input_flags) {
+    RebalanceWs w = carve_rebalance(ws, n, n_crit, cap);
     if (ws_bytes < w.bytes) return CSTONE_ERR_INVALID_ARG;
-    const size_t nl0 = *n_leaves;
-    if (nl0 < 1 || nl0 > cap) return CSTONE_ERR_INVALID_ARG;
-    if (max_iters == 0) max_iters = kL + 1;
-    if (max_iters > kMaxRounds) max_iters = kMaxRounds;
-
-    uint64_t* bufK[2] = {leaves, w.K_alt};
-    const int root = nl0 == 1;
-    uint32_t init_grid = grid_1d(std::max<size_t>(w.lb_words, kMaxRounds + 1), 256);
-    if (init_grid > 1024) init_grid = 1024;
-    hipLaunchKernelGGL(loop_init_kernel, dim3(init_grid), dim3(256), 0, stream, w.st, static_cast<uint64_t>(nl0),
-                       w.lb, w.lb_words, w.pos[0], static_cast<uint32_t>(n), root, leaves, input_flags);
-    if (!root)
+    if (nl0 < 1 || nl0 > cap || cap >= 0xffffffffull) return CSTONE_ERR_INVALID_ARG;
+    P_ = P;
+    n_ = n;
+    n_crit_ = n_crit;
+    leaves_ = leaves;
+    nl0_ = nl0;
+    cap_ = cap;
+    counts_ = counts;
+    max_iters_ = std::min<uint32_t>(max_iters ? max_iters : kL + 1, kMaxRounds);
+    enqueued_ = 0;
+    stream_ = stream;
+    ws_ = ws;
+    st_ = w.st;
+    root_ = nl0 == 1;
+    hipLaunchKernelGGL(loop_init_kernel, dim3(clamp_grid(grid_1d(std::max<size_t>(w.lb_words, kMaxRounds + 1), 256))),
+                       dim3(256), 0, stream, w.st, static_cast<uint64_t>(nl0), w.lb, w.lb_words, w.pos[0],
+                       static_cast<uint32_t>(n), root_ ? 1 : 0, leaves, input_flags);
+    if (!root_)
         hipLaunchKernelGGL(positions_kernel, dim3(grid_1d(nl0 + 1, kCountBlock)), dim3(kCountBlock), 0, stream, P, n,
                            leaves, nl0, w.pos[0]);
     CS_HIP(hipGetLastError());
+    return CSTONE_OK;
+}
 
-    // rounds expected from the root: about log8(n / (n_crit + 1)) + 2
-    uint32_t batch = 2;
-    if (root) {
-        double ratio = static_cast<double>(n) / (static_cast<double>(n_crit) + 1.0);
-        uint32_t est = 2;
-        while (ratio > 1.0) {
-            ratio /= 8.0;
-            ++est;
+cstone_status RebalanceLoop::enqueue(uint32_t rounds) {
+    RebalanceWs w = carve_rebalance(ws_, n_, n_crit_, cap_);
+    if (rounds == 0) {
+        rounds = 2;
+        if (root_) {  // from the root: about log8(n / (n_crit + 1)) + 2 rounds
+            double ratio = static_cast<double>(n_) / (static_cast<double>(n_crit_) + 1.0);
+            while (ratio > 1.0) {
+                ratio /= 8.0;
+                ++rounds;
+            }
         }
-        batch = est;
     }
-    LoopState host{};
-    uint32_t done = 0;
-    int outcome = 0;  // 1 converged, 2 capacity, 3 not converged
-    uint32_t final_round = 0;
-    while (outcome == 0) {
-        const uint32_t b = std::min(batch, max_iters - done);
-        for (uint32_t q = done; q < done + b; ++q) {
-            double bound = static_cast<double>(nl0);
-            for (uint32_t e = 0; e < q && bound < static_cast<double>(cap); ++e) bound *= 8.0;
-            const size_t rows = std::min<double>(bound, static_cast<double>(cap));
-            uint32_t grid = grid_1d(rows, kRTile);
-            if (grid > kMaxRoundGrid) grid = kMaxRoundGrid;
-            if (grid < 1) grid = 1;
-            hipLaunchKernelGGL(round_kernel, dim3(grid), dim3(kRBlock), 0, stream, P, static_cast<uint32_t>(n),
-                               n_crit, bufK[q & 1], w.pos[q & 1], bufK[(q + 1) & 1], w.pos[(q + 1) & 1], w.st,
-                               static_cast<int>(q), static_cast<uint64_t>(cap), w.lb);
-        }
-        CS_HIP(hipGetLastError());
-        done += b;
-        CS_HIP(hipMemcpyAsync(&host, w.st, sizeof(LoopState), hipMemcpyDeviceToHost, stream));
-        CS_HIP(hipStreamSynchronize(stream));
-        if (input_flags_out) *input_flags_out = host.input_flags;
-        if (host.err) return CSTONE_ERR_DEVICE;
-        for (uint32_t q = 0; q < done; ++q) {
-            if (host.nl[q + 1] > cap) {
-                outcome = 2;
-                final_round = q;
-                break;
-            }
-            if (host.changed[q] == 0) {
-                outcome = 1;
-                final_round = q;
-                break;
-            }
-        }
-        if (outcome == 0 && done >= max_iters) {
-            outcome = 3;
-            final_round = max_iters;
-        }
+    rounds = std::min(rounds, max_iters_ - enqueued_);
+    uint64_t* bufK[2] = {leaves_, w.K_alt};
+    for (uint32_t q = enqueued_; q < enqueued_ + rounds; ++q) {
+        // leaves entering round q: at most nl0 * 8^q and the capacity
+        double bound = static_cast<double>(nl0_);
+        for (uint32_t e = 0; e < q && bound < static_cast<double>(cap_); ++e) bound *= 8.0;
+        const size_t rows = static_cast<size_t>(std::min<double>(bound, static_cast<double>(cap_)));
+        hipLaunchKernelGGL(round_kernel, dim3(clamp_grid(grid_1d(rows, kRTile))), dim3(kRBlock), 0, stream_,
+                           static_cast<uint32_t>(n_), n_crit_, bufK[q & 1], w.pos[q & 1], bufK[(q + 1) & 1],
+                           w.pos[(q + 1) & 1], w.splits, w.split_capacity, w.st, static_cast<int>(q),
+                           static_cast<uint64_t>(cap_), w.lb);
+        // one wave per search while searches are few
+        const size_t searches = 7 * std::min<size_t>(rows, w.split_capacity);
+        hipLaunchKernelGGL(split_search_kernel, dim3(clamp_grid(grid_1d(searches, kSearchBlock / kWave))),
+                           dim3(kSearchBlock), 0, stream_, P_, bufK[q & 1], w.pos[q & 1], w.pos[(q + 1) & 1],
+                           w.splits, w.split_capacity, w.st, static_cast<int>(q), static_cast<uint64_t>(cap_));
+    }
+    enqueued_ += rounds;
+    hipLaunchKernelGGL(finalize_kernel, dim3(clamp_grid(grid_1d(cap_ + 1, 256))), dim3(256), 0, stream_, w.st,
+                       enqueued_, static_cast<uint64_t>(cap_), leaves_, w.K_alt, w.pos[0], w.pos[1], counts_);
+    CS_HIP(hipGetLastError());
+    return CSTONE_OK;
+}
+
+const uint64_t* RebalanceLoop::device_leaf_count() const { return &st_->final_nl; }
+
+cstone_status RebalanceLoop::wait(bool* finished) {
+    LoopState host;
+    CS_HIP(hipMemcpyAsync(&host, st_, sizeof(LoopState), hipMemcpyDeviceToHost, stream_));
+    CS_HIP(hipStreamSynchronize(stream_));
+    input_flags = host.input_flags;
+    rounds = host.final_last;
+    *finished = true;
+    if (host.err) {
+        status = CSTONE_ERR_DEVICE;
+        return status;
+    }
+    if (host.final_code == 2) {
+        n_leaves = host.nl[host.final_last + 1];  // what the failing round needed
+        status = CSTONE_ERR_CAPACITY;
+        return status;
+    }
+    n_leaves = host.final_nl;
+    if (host.final_code == 1) {
+        status = CSTONE_OK;
+    } else if (enqueued_ >= max_iters_) {
+        status = CSTONE_ERR_NOT_CONVERGED;
+    } else {
+        status = CSTONE_OK;
+        *finished = false;
+    }
+    return status;
+}
+
+cstone_status run_rebalance(const uint64_t* P, size_t n, uint32_t n_crit, uint64_t* leaves, size_t* n_leaves,
+                            size_t cap, uint32_t* counts, uint32_t max_iters, uint32_t* iters_done, void* ws,
+                            size_t ws_bytes, hipStream_t stream) {
+    RebalanceLoop loop;
+    cstone_status s = loop.begin(P, n, n_crit, leaves, *n_leaves, cap, counts, max_iters, ws, ws_bytes, stream,
+                                 nullptr);
+    if (s != CSTONE_OK) return s;
+    bool finished = false;
+    uint32_t batch = 0;
+    while (!finished) {
+        if ((s = loop.enqueue(batch)) != CSTONE_OK) return s;
+        loop.wait(&finished);
         batch = 2;
     }
-
-    // array after the last complete round lives in buffer (round + 1) & 1 for
-    // a converged loop, round & 1 otherwise
-    uint32_t buf;
-    size_t nl_final;
-    if (outcome == 1) {
-        buf = (final_round + 1) & 1;
-        nl_final = host.nl[final_round + 1];
-    } else if (outcome == 2) {
-        buf = final_round & 1;
-        nl_final = host.nl[final_round];
-    } else {
-        buf = final_round & 1;
-        nl_final = host.nl[final_round];
-    }
-    if (buf == 1) CS_HIP(hipMemcpyAsync(leaves, w.K_alt, (nl_final + 1) * sizeof(uint64_t),
-                                        hipMemcpyDeviceToDevice, stream));
-    if (counts)
-        hipLaunchKernelGGL(counts_from_positions_kernel, dim3(grid_1d(nl_final, kCountBlock)), dim3(kCountBlock), 0,
-                           stream, w.pos[buf], nl_final, counts);
-    CS_HIP(hipGetLastError());
-    CS_HIP(hipStreamSynchronize(stream));
-
-    if (iters_done) *iters_done = outcome == 1 ? final_round + 1 : final_round;
-    if (outcome == 2) {
-        *n_leaves = host.nl[final_round + 1];
-        return CSTONE_ERR_CAPACITY;
-    }
-    *n_leaves = nl_final;
-    return outcome == 3 ? CSTONE_ERR_NOT_CONVERGED : CSTONE_OK;
+    if (loop.status == CSTONE_ERR_DEVICE) return loop.status;
+    *n_leaves = loop.n_leaves;
+    if (iters_done) *iters_done = loop.rounds;
+    return loop.status;
 }
 
 }  // namespace cs

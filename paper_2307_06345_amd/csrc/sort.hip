@@ -207,13 +207,15 @@ SortWs carve_sort(void* ws, size_t n, bool with_perm) {
 
 size_t sort_workspace_bytes(size_t n, bool with_perm) { return carve_sort(nullptr, n, with_perm).bytes; }
 
+int sort_passes(int sig_bits) { return (sig_bits + kBits - 1) / kBits; }
+
 cstone_status launch_sort(const uint64_t* keys_in, uint64_t* keys_out, uint32_t* perm_out, size_t n,
-                          int sig_bits, void* ws, size_t ws_bytes, hipStream_t stream) {
+                          int sig_bits, void* ws, size_t ws_bytes, hipStream_t stream, hipEvent_t* pass_events) {
     const bool with_perm = perm_out != nullptr;
     SortWs s = carve_sort(ws, n, with_perm);
     if (ws_bytes < s.bytes) return CSTONE_ERR_INVALID_ARG;
     if (n == 0) return CSTONE_OK;
-    const int passes = (sig_bits + kBits - 1) / kBits;
+    const int passes = sort_passes(sig_bits);
     if (passes < 1 || passes > kMaxPasses) return CSTONE_ERR_INVALID_ARG;
 
     hipLaunchKernelGGL(sort_init_kernel, dim3(1), dim3(256), 0, stream, s.ghist, s.counters, s.err);
@@ -224,6 +226,7 @@ cstone_status launch_sort(const uint64_t* keys_in, uint64_t* keys_out, uint32_t*
                        s.lb, s.lb_words);
 
     const uint32_t tiles = static_cast<uint32_t>((n + kTile - 1) / kTile);
+    if (pass_events) CS_HIP(hipEventRecord(pass_events[0], stream));
     const uint64_t* src_k = keys_in;
     const uint32_t* src_v = nullptr;
     for (int p = 0; p < passes; ++p) {
@@ -245,6 +248,7 @@ cstone_status launch_sort(const uint64_t* keys_in, uint64_t* keys_out, uint32_t*
         }
         src_k = dk;
         src_v = dv;
+        if (pass_events) CS_HIP(hipEventRecord(pass_events[p + 1], stream));
     }
     CS_HIP(hipGetLastError());
     return CSTONE_OK;

@@ -221,24 +221,27 @@ def test_rebalance_capacity_error():
 
 # ---- link ------------------------------------------------------------------
 
+@pytest.mark.parametrize("by_sort", [False, True])
 @pytest.mark.parametrize("kind,n,n_crit", [("uniform", 0, 64), ("uniform", 65536, 64), ("plummer", 300000, 16),
-                                           ("plummer", 20000, 1), ("uniform", 200000, 3)])
-def test_link_parity(kind, n, n_crit):
+                                           ("plummer", 20000, 1), ("uniform", 200000, 3),
+                                           ("uniform", 3000000, 64)])
+def test_link_parity(kind, n, n_crit, by_sort):
     P = _sorted_particle_keys(kind, n, n_crit, 16)
     K = oracle.build_leaves(P, n_crit)
-    say("link", kind, n, n_crit, "leaves", K.size - 1)
-    NK, CO, LO = cs.link_octree(dev(K))
+    say("link", kind, n, n_crit, "leaves", K.size - 1, "by_sort", by_sort)
+    NK, CO, LO = cs.link_octree(dev(K), by_sort=by_sort)
     rNK, rCO, rLO = oracle.link_octree(K)
     eq(host(NK), rNK, "NK")
     eq(host(CO), rCO, "CO")
     eq(host(LO), rLO, "LO")
 
 
-def test_link_paper_example(golden_fig):
+@pytest.mark.parametrize("by_sort", [False, True])
+def test_link_paper_example(golden_fig, by_sort):
     K = np.array([int(p, 8) << (3 * (21 - len(p))) for p in golden_fig["fig1_bottom_octal_prefixes"]] + [END],
                  np.uint64)
-    say("link Fig. 2")
-    NK, CO, LO = cs.link_octree(dev(K))
+    say("link Fig. 2", "by_sort", by_sort)
+    NK, CO, LO = cs.link_octree(dev(K), by_sort=by_sort)
     assert list(host(LO)) == golden_fig["fig2_LO_prefix"] + [golden_fig["fig2_LO_tail_value"]] * 20
     assert [int(v) for v in host(NK)] == [int(s, 8) for s in golden_fig["fig2_NK_octal"]]
     assert list(host(CO)) == golden_fig["fig2_CO"]
