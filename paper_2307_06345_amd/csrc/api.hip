@@ -153,11 +153,15 @@ cstone_status cstone_build(const double* x, const double* y, const double* z, si
     do {
         if (mark(0) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
         hipLaunchKernelGGL(clear_word_kernel, dim3(1), dim3(1), 0, stream, flag);
-        s = launch_keys(x, y, z, n, *box, curve, keys, flag, stream);
+        // the key kernel counts the sort's first digit as it writes the keys
+        if (n && (s = sort_prepare(stage_ws, n, true, stream)) != CSTONE_OK) break;
+        uint32_t hist_mask = 0;
+        uint32_t* hist0 = n ? sort_first_histogram(stage_ws, n, true, &hist_mask) : nullptr;
+        s = launch_keys(x, y, z, n, *box, curve, keys, flag, stream, hist0, hist_mask);
         if (s != CSTONE_OK) break;
         if (mark(1) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
         s = launch_sort(keys, sorted_keys, perm, n, 63, stage_ws, stage_bytes, stream,
-                        timed && n ? pass_ev : nullptr);
+                        timed && n ? pass_ev : nullptr, /*prepared=*/true);
         if (s != CSTONE_OK) break;
         if (mark(2) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
         if (nl == 0) nl = 1;  // start from the root leaf {0, 8^L}

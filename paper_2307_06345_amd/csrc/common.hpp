@@ -139,9 +139,11 @@ __device__ __forceinline__ T wave_sum(T v) {
 }
 
 // Exclusive prefix of `tile` over one counter (words[p] for tile p), resolved
-// by a whole wave: each step reads the 64 nearest unresolved predecessors at
-// once, so a long run of aggregates costs one round trip per 64 tiles. Every
+// by a whole wave: each step reads the 64 * R nearest unresolved predecessors
+// at once (R independent loads per lane, lane l holding tiles top - l - 64 r),
+// so a long run of aggregates costs one round trip per 64 * R tiles. Every
 // lane returns the same value; all 64 lanes must call it together.
+template <int R = 4>
 __device__ __forceinline__ uint64_t lookback_wave(const uint64_t* words, uint32_t tile, uint32_t epoch,
                                                   uint32_t* err) {
     const uint32_t lane = lane_id();
@@ -149,17 +151,37 @@ __device__ __forceinline__ uint64_t lookback_wave(const uint64_t* words, uint32_
     int64_t top = static_cast<int64_t>(tile) - 1;
     uint32_t spins = 0;
     while (top >= 0) {
-        const int64_t p = top - lane;
-        const bool valid = p >= 0;
-        const uint64_t w = valid ? ld_agent(words + p) : 0ull;
-        const uint64_t flag = w & (3ull << 62);
-        const bool mine = ((w >> 48) & 0x3fffu) == (epoch & 0x3fffu);
-        const bool ready = !valid || (flag != 0 && mine);
-        const uint64_t inc = __ballot(valid && ready && flag == kFlagInc);
-        const uint64_t pending = __ballot(!ready);
-        // lanes up to and including the nearest inclusive prefix (all if none)
-        const uint64_t upto = inc ? ((inc & (~inc + 1)) << 1) - 1 : ~0ull;
-        if (pending & upto) {
+        uint64_t w[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t p = top - lane - static_cast<int64_t>(r) * kWave;
+            w[r] = p >= 0 ? ld_agent(words + p) : 0ull;
+        }
+        bool found = false, wait = false;
+        uint64_t part = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {  // sub-windows, nearest first
+            if (found || wait) continue;
+            const int64_t p = top - lane - static_cast<int64_t>(r) * kWave;
+            const bool valid = p >= 0;
+            const uint64_t flag = w[r] & (3ull << 62);
+            const bool mine = ((w[r] >> 48) & 0x3fffu) == (epoch & 0x3fffu);
+            const bool ready = !valid || (flag != 0 && mine);
+            const uint64_t inc = __ballot(valid && ready && flag == kFlagInc);
+            const uint64_t pending = __ballot(!ready);
+            // lanes up to and including the nearest inclusive prefix (all if none)
+            const uint64_t upto = inc ? ((inc & (~inc + 1)) << 1) - 1 : ~0ull;
+            if (pending & upto) {
+                wait = true;  // resume from this sub-window
+                top -= static_cast<int64_t>(r) * kWave;
+                continue;
+            }
+            part += (valid && ((upto >> lane) & 1ull)) ? (w[r] & kValueMask) : 0ull;
+            if (inc) found = true;
+        }
+        excl += wave_sum<uint64_t>(part);
+        if (found) break;
+        if (wait) {
             if (++spins > kSpinLimit) {
                 if (lane == 0) atomicOr(err, kErrSpin);
                 break;
@@ -167,9 +189,7 @@ __device__ __forceinline__ uint64_t lookback_wave(const uint64_t* words, uint32_
             __builtin_amdgcn_s_sleep(1);
             continue;
         }
-        excl += wave_sum<uint64_t>((valid && ((upto >> lane) & 1ull)) ? (w & kValueMask) : 0ull);
-        if (inc) break;
-        top -= kWave;
+        top -= static_cast<int64_t>(R) * kWave;
     }
     return excl;
 }

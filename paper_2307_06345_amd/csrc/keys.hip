@@ -148,46 +148,116 @@ __device__ __forceinline__ uint64_t hilbert_from_morton(uint64_t m, const uint16
 constexpr int kKeysBlock = 256;
 
 template <int CURVE>
+__device__ __forceinline__ uint64_t key_of(double cx, double cy, double cz, double lo0, double lo1, double lo2,
+                                           double s0, double s1, double s2, const uint16_t* two,
+                                           const uint16_t* first) {
+    const uint64_t m = morton_of(quantize(cx, lo0, s0), quantize(cy, lo1, s1), quantize(cz, lo2, s2));
+    return CURVE == CSTONE_HILBERT ? hilbert_from_morton(m, two, first) : m;
+}
+
+__device__ __forceinline__ bool finite3(double a, double b, double c) {
+    return __builtin_isfinite(a) && __builtin_isfinite(b) && __builtin_isfinite(c);
+}
+
+// PAIRED: every thread encodes two neighbouring particles with 16-byte loads
+// and stores (all four arrays 16-byte aligned); the odd last particle, if any,
+// is done by thread 0 of block 0.
+template <int CURVE, bool PAIRED>
 __global__ __launch_bounds__(kKeysBlock) void keys_kernel(const double* __restrict__ x,
                                                           const double* __restrict__ y,
                                                           const double* __restrict__ z, size_t n, double lo0,
                                                           double lo1, double lo2, double s0, double s1, double s2,
-                                                          uint64_t* __restrict__ keys, uint32_t* flags) {
+                                                          uint64_t* __restrict__ keys, uint32_t* flags,
+                                                          uint32_t* hist0, uint32_t hmask) {
     __shared__ uint16_t two[kStates * 64];
     __shared__ uint16_t first[8];
+    __shared__ uint32_t h[512];
     if (CURVE == CSTONE_HILBERT) {
         for (int i = threadIdx.x; i < kStates * 64; i += kKeysBlock) two[i] = d_hilbert.two[i];
         if (threadIdx.x < 8) first[threadIdx.x] = d_hilbert.first[threadIdx.x];
-        __syncthreads();
     }
+    if (hist0)
+        for (int i = threadIdx.x; i < 512; i += kKeysBlock) h[i] = 0;
+    __syncthreads();
     bool bad = false;
     const size_t stride = static_cast<size_t>(gridDim.x) * kKeysBlock;
-    for (size_t p = static_cast<size_t>(blockIdx.x) * kKeysBlock + threadIdx.x; p < n; p += stride) {
-        double cx = x[p], cy = y[p], cz = z[p];
-        bad |= !(__builtin_isfinite(cx) && __builtin_isfinite(cy) && __builtin_isfinite(cz));
-        uint64_t m = morton_of(quantize(cx, lo0, s0), quantize(cy, lo1, s1), quantize(cz, lo2, s2));
-        if (CURVE == CSTONE_HILBERT) m = hilbert_from_morton(m, two, first);
-        keys[p] = m;
+    const size_t t0 = static_cast<size_t>(blockIdx.x) * kKeysBlock + threadIdx.x;
+    if (PAIRED) {
+        const size_t pairs = n / 2;
+        const double2* x2 = reinterpret_cast<const double2*>(x);
+        const double2* y2 = reinterpret_cast<const double2*>(y);
+        const double2* z2 = reinterpret_cast<const double2*>(z);
+        ulonglong2* k2 = reinterpret_cast<ulonglong2*>(keys);
+        for (size_t p = t0; p < pairs; p += stride) {
+            const double2 cx = x2[p], cy = y2[p], cz = z2[p];
+            bad |= !(finite3(cx.x, cy.x, cz.x) && finite3(cx.y, cy.y, cz.y));
+            ulonglong2 k;
+            k.x = key_of<CURVE>(cx.x, cy.x, cz.x, lo0, lo1, lo2, s0, s1, s2, two, first);
+            k.y = key_of<CURVE>(cx.y, cy.y, cz.y, lo0, lo1, lo2, s0, s1, s2, two, first);
+            k2[p] = k;
+            if (hist0) {
+                atomicAdd(&h[k.x & hmask], 1u);
+                atomicAdd(&h[k.y & hmask], 1u);
+            }
+        }
+        if ((n & 1) && t0 == 0) {
+            const size_t p = n - 1;
+            bad |= !finite3(x[p], y[p], z[p]);
+            const uint64_t k = key_of<CURVE>(x[p], y[p], z[p], lo0, lo1, lo2, s0, s1, s2, two, first);
+            keys[p] = k;
+            if (hist0) atomicAdd(&h[k & hmask], 1u);
+        }
+    } else {
+        for (size_t p = t0; p < n; p += stride) {
+            const double cx = x[p], cy = y[p], cz = z[p];
+            bad |= !finite3(cx, cy, cz);
+            const uint64_t k = key_of<CURVE>(cx, cy, cz, lo0, lo1, lo2, s0, s1, s2, two, first);
+            keys[p] = k;
+            if (hist0) atomicAdd(&h[k & hmask], 1u);
+        }
     }
     if (flags && __ballot(bad) != 0ull && lane_id() == 0) atomicOr(flags, CSTONE_FLAG_NONFINITE);
+    if (hist0) {
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i <= hmask; i += kKeysBlock)
+            if (h[i]) atomicAdd(&hist0[i], h[i]);
+    }
+}
+
+template <int CURVE, bool PAIRED>
+void launch_keys_t(size_t blocks, hipStream_t stream, const double* x, const double* y, const double* z, size_t n,
+                   const cstone_box& box, const double* s, uint64_t* keys, uint32_t* flags, uint32_t* hist0,
+                   uint32_t hmask) {
+    hipLaunchKernelGGL((keys_kernel<CURVE, PAIRED>), dim3(blocks), dim3(kKeysBlock), 0, stream, x, y, z, n,
+                       box.lo[0], box.lo[1], box.lo[2], s[0], s[1], s[2], keys, flags, hist0, hmask);
 }
 
 }  // namespace
 
 cstone_status launch_keys(const double* x, const double* y, const double* z, size_t n, const cstone_box& box,
-                          cstone_curve curve, uint64_t* keys, uint32_t* flags, hipStream_t stream) {
+                          cstone_curve curve, uint64_t* keys, uint32_t* flags, hipStream_t stream, uint32_t* hist0,
+                          uint32_t hist_mask) {
     if (n == 0) return CSTONE_OK;
+    if (hist0 && hist_mask >= 512) return CSTONE_ERR_INVALID_ARG;
     double s[3];
     for (int d = 0; d < 3; ++d) s[d] = 2097152.0 / (box.hi[d] - box.lo[d]);
-    size_t blocks = (n + kKeysBlock - 1) / kKeysBlock;
-    const size_t max_blocks = 256 * 16;  // grid-stride beyond 16 blocks per CU
+    auto aligned = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; };
+    const bool paired = aligned(x) && aligned(y) && aligned(z) && aligned(keys);
+    const size_t per_thread = paired ? 2 : 1;
+    size_t blocks = (n + kKeysBlock * per_thread - 1) / (kKeysBlock * per_thread);
+    const size_t max_blocks = 256 * 8;  // grid-stride beyond 8 blocks per CU
     if (blocks > max_blocks) blocks = max_blocks;
-    if (curve == CSTONE_HILBERT)
-        hipLaunchKernelGGL(keys_kernel<CSTONE_HILBERT>, dim3(blocks), dim3(kKeysBlock), 0, stream, x, y, z, n,
-                           box.lo[0], box.lo[1], box.lo[2], s[0], s[1], s[2], keys, flags);
-    else
-        hipLaunchKernelGGL(keys_kernel<CSTONE_MORTON>, dim3(blocks), dim3(kKeysBlock), 0, stream, x, y, z, n,
-                           box.lo[0], box.lo[1], box.lo[2], s[0], s[1], s[2], keys, flags);
+    if (curve == CSTONE_HILBERT) {
+        if (paired)
+            launch_keys_t<CSTONE_HILBERT, true>(blocks, stream, x, y, z, n, box, s, keys, flags, hist0, hist_mask);
+        else
+            launch_keys_t<CSTONE_HILBERT, false>(blocks, stream, x, y, z, n, box, s, keys, flags, hist0, hist_mask);
+    } else {
+        if (paired)
+            launch_keys_t<CSTONE_MORTON, true>(blocks, stream, x, y, z, n, box, s, keys, flags, hist0, hist_mask);
+        else
+            launch_keys_t<CSTONE_MORTON, false>(blocks, stream, x, y, z, n, box, s, keys, flags, hist0, hist_mask);
+    }
     CS_HIP(hipGetLastError());
     return CSTONE_OK;
 }

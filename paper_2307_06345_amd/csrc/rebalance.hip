@@ -29,7 +29,7 @@ namespace {
 constexpr int kMaxRounds = 64;
 constexpr int kCountBlock = 256;
 constexpr int kRBlock = 256;
-constexpr int kRItems = 4;
+constexpr int kRItems = 8;
 constexpr int kRTile = kRBlock * kRItems;
 constexpr uint32_t kMaxGrid = 2048;
 constexpr uint32_t kSearchBlock = 256;
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(kRBlock) void round_kernel(uint32_t n, uint32_t n_c
                 if (tid == 0) st_agent(w, lb_word(kFlagInc, epoch, agg));
             } else {
                 if (tid == 0) st_agent(w, lb_word(kFlagAgg, epoch, agg));
-                prefix = lookback_wave(lb, tile, epoch, &st->err);
+                prefix = lookback_wave<4>(lb, tile, epoch, &st->err);
                 if (tid == 0) st_agent(w, lb_word(kFlagInc, epoch, prefix + agg));
             }
             if (tid == 0) {
