@@ -141,6 +141,12 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid) {
 // One tile of a pass: `base` .. `base + count` of the keys, in the segment
 // whose first tile is `first` and whose particles start at `seg_base`
 // (segment-relative permutation values; the plain sort is one segment).
+// Minimum waves per SIMD (the second launch bound): room for two blocks of up
+// to 512 threads per CU (4 SIMDs), so that one block's waits overlap the
+// other's work; a block's LDS stays below half of the CU's 160 KB.
+template <int BLOCK>
+constexpr int kMinBlocks = BLOCK <= 512 ? 2 * BLOCK / (4 * kWave) : BLOCK / (4 * kWave);
+
 struct TileDesc {
     uint32_t tile, base, count, first, seg_base;
 };
@@ -151,8 +157,8 @@ __device__ __forceinline__ void onesweep_tile(const TileDesc td, const uint64_t*
                                               uint32_t* __restrict__ vals_out, uint32_t n, uint32_t shift,
                                               const uint32_t* __restrict__ ghist, uint32_t* __restrict__ ghist_next,
                                               uint32_t shift_next, typename LB::word* lb, uint32_t epoch,
-                                              uint32_t* err, uint64_t* stage, uint32_t (*whist)[1 << BITS],
-                                              uint32_t* nhist, uint64_t* ddelta, uint32_t* scan_tmp) {
+                                              uint32_t* err, uint64_t* stage, uint16_t (*whist)[1 << BITS],
+                                              uint32_t* nhist, uint32_t* ddelta, uint64_t* scan_tmp) {
     constexpr int RADIX = 1 << BITS;
     constexpr int W = BLOCK / kWave;
     constexpr int TILE = BLOCK * ITEMS;
@@ -166,6 +172,8 @@ __device__ __forceinline__ void onesweep_tile(const TileDesc td, const uint64_t*
     const uint32_t end = tile_base + tile_count;  // keys at or past `end` belong to others
     const uint32_t wave_base = tile_base + wave * ITEMS * kWave;
 
+    // this pass's digit counts of the whole set, for the global digit offsets
+    const uint32_t gcount = tid < RADIX ? ghist[tid] : 0u;
     uint64_t k[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
@@ -185,7 +193,7 @@ __device__ __forceinline__ void onesweep_tile(const TileDesc td, const uint64_t*
         const uint64_t peers = match_digit<BITS>(d, FULL ? ~0ull : __ballot(ok));
         const uint32_t below = lanes_below(peers);
         const uint32_t base = whist[wave][d];
-        if (ok && below == 0) whist[wave][d] = base + static_cast<uint32_t>(__popcll(peers));
+        if (ok && below == 0) whist[wave][d] = static_cast<uint16_t>(base + static_cast<uint32_t>(__popcll(peers)));
         rank[i] = base + below;
     }
     __syncthreads();
@@ -196,16 +204,20 @@ __device__ __forceinline__ void onesweep_tile(const TileDesc td, const uint64_t*
 #pragma unroll
         for (int w = 0; w < W; ++w) {
             const uint32_t c = whist[w][tid];
-            whist[w][tid] = total;
+            whist[w][tid] = static_cast<uint16_t>(total);
             total += c;
         }
         LB::store(lb + static_cast<size_t>(tile) * RADIX + tid, LB::make(tile == td.first ? 2u : 1u, epoch, total));
     }
-    uint32_t dummy;
-    const uint32_t lst = block_exclusive_sum<uint32_t, BLOCK>(total, scan_tmp, &dummy);
+    // one scan for both: high word global start of the digit, low word its tile-local start
+    uint64_t dummy;
+    const uint64_t both = block_exclusive_sum<uint64_t, BLOCK>((static_cast<uint64_t>(gcount) << 32) | total,
+                                                               scan_tmp, &dummy);
+    const uint32_t lst = static_cast<uint32_t>(both);
+    const uint32_t gbase = static_cast<uint32_t>(both >> 32);
     if (tid < RADIX) {
 #pragma unroll
-        for (int w = 0; w < W; ++w) whist[w][tid] += lst;  // tile-local start of (digit, wave)
+        for (int w = 0; w < W; ++w) whist[w][tid] += static_cast<uint16_t>(lst);  // tile-local start of (digit, wave)
     }
     __syncthreads();
 
@@ -218,6 +230,8 @@ __device__ __forceinline__ void onesweep_tile(const TileDesc td, const uint64_t*
         if (FULL || idx < end) stage[lpos[i]] = k[i];
     }
     // the permutation values are only needed for the scatter: start loading them
+    // (not earlier: the keys must be dead by then to keep the registers in budget)
+    __builtin_amdgcn_sched_barrier(0);
     uint32_t v[ITEMS];
     if (WITH_VALUES) {
 #pragma unroll
@@ -226,31 +240,32 @@ __device__ __forceinline__ void onesweep_tile(const TileDesc td, const uint64_t*
             v[i] = FIRST ? idx - td.seg_base : ((FULL || idx < end) ? vals_in[idx] : 0u);
         }
     }
-    const uint32_t gbase = block_exclusive_sum<uint32_t, BLOCK>(tid < RADIX ? ghist[tid] : 0u, scan_tmp, &dummy);
     if (tid < RADIX) {
         uint64_t excl = 0;
         if (tile != td.first) {
             excl = digit_lookback<LB, WIN>(lb + tid, RADIX, tile, td.first, epoch, err);
             LB::store(lb + static_cast<size_t>(tile) * RADIX + tid, LB::make(2u, epoch, excl + total));
         }
-        ddelta[tid] = static_cast<uint64_t>(td.seg_base) + gbase + excl - lst;
+        // destination of tile-local position j is j + ddelta (mod 2^32; every index is below 2^32)
+        ddelta[tid] = td.seg_base + gbase + static_cast<uint32_t>(excl) - lst;
         if (ghist_next && nhist[tid]) atomicAdd(&ghist_next[tid], nhist[tid]);
     }
     __syncthreads();
 
-    // store each digit run contiguously
-    uint32_t dst[ITEMS];
+    // store each digit run contiguously; keep the digits (two per register)
+    // for the values, which follow the keys through the same LDS buffer
+    uint32_t dpk[(ITEMS + 1) / 2];
+#pragma unroll
+    for (int i = 0; i < (ITEMS + 1) / 2; ++i) dpk[i] = 0;
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t j = static_cast<uint32_t>(i) * BLOCK + tid;
-        dst[i] = 0xffffffffu;
         if (FULL || j < tile_count) {
             const uint64_t key = stage[j];
-            const uint64_t to = j + ddelta[digit_of<BITS>(key, shift)];
-            if (to < n) {  // always true; guards memory against a logic error
-                dst[i] = static_cast<uint32_t>(to);
-                keys_out[to] = key;
-            }
+            const uint32_t d = digit_of<BITS>(key, shift);
+            dpk[i / 2] |= d << ((i & 1) * 16);
+            const uint32_t to = j + ddelta[d];
+            if (to < n) keys_out[to] = key;  // always true; guards memory against a logic error
         }
     }
     if (WITH_VALUES) {
@@ -264,13 +279,16 @@ __device__ __forceinline__ void onesweep_tile(const TileDesc td, const uint64_t*
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             const uint32_t j = static_cast<uint32_t>(i) * BLOCK + tid;
-            if ((FULL || j < tile_count) && dst[i] != 0xffffffffu) vals_out[dst[i]] = stage32[j];
+            if (FULL || j < tile_count) {
+                const uint32_t to = j + ddelta[(dpk[i / 2] >> ((i & 1) * 16)) & 0xffffu];
+                if (to < n) vals_out[to] = stage32[j];
+            }
         }
     }
 }
 
 template <int BITS, int BLOCK, int ITEMS, int WIN, bool FIRST, bool WITH_VALUES, class LB>
-__global__ __launch_bounds__(BLOCK) void onesweep_kernel(const uint64_t* __restrict__ keys_in,
+__global__ __launch_bounds__(BLOCK, kMinBlocks<BLOCK>) void onesweep_kernel(const uint64_t* __restrict__ keys_in,
                                                           const uint32_t* __restrict__ vals_in,
                                                           uint64_t* __restrict__ keys_out,
                                                           uint32_t* __restrict__ vals_out, uint32_t n, uint32_t shift,
@@ -284,10 +302,10 @@ __global__ __launch_bounds__(BLOCK) void onesweep_kernel(const uint64_t* __restr
     static_assert(BLOCK >= RADIX, "one digit per thread in the digit loops");
     // the tile reordered by digit (keys, then values)
     __shared__ uint64_t stage[TILE];
-    __shared__ uint32_t whist[W][RADIX];
+    __shared__ uint16_t whist[W][RADIX];
     __shared__ uint32_t nhist[RADIX];
-    __shared__ uint64_t ddelta[RADIX];
-    __shared__ uint32_t scan_tmp[W];
+    __shared__ uint32_t ddelta[RADIX];
+    __shared__ uint64_t scan_tmp[W];
     const uint32_t tid = threadIdx.x;
     // tiles follow the block index: the dispatcher starts lower blocks first,
     // so every tile a block waits for is running or done
@@ -312,7 +330,7 @@ __global__ __launch_bounds__(BLOCK) void onesweep_kernel(const uint64_t* __restr
 // set has its own digit histograms (ghist + set * hist_stride) and its own
 // look-back chain, and its permutation values count from the set's start.
 template <int BITS, int BLOCK, int ITEMS, int WIN, bool FIRST, bool WITH_VALUES, class LB>
-__global__ __launch_bounds__(BLOCK) void onesweep_seg_kernel(const uint64_t* __restrict__ keys_in,
+__global__ __launch_bounds__(BLOCK, kMinBlocks<BLOCK>) void onesweep_seg_kernel(const uint64_t* __restrict__ keys_in,
                                                               const uint32_t* __restrict__ vals_in,
                                                               uint64_t* __restrict__ keys_out,
                                                               uint32_t* __restrict__ vals_out, uint32_t n,
@@ -327,10 +345,10 @@ __global__ __launch_bounds__(BLOCK) void onesweep_seg_kernel(const uint64_t* __r
     constexpr int TILE = BLOCK * ITEMS;
     static_assert(BLOCK >= RADIX, "one digit per thread in the digit loops");
     __shared__ uint64_t stage[TILE];
-    __shared__ uint32_t whist[W][RADIX];
+    __shared__ uint16_t whist[W][RADIX];
     __shared__ uint32_t nhist[RADIX];
-    __shared__ uint64_t ddelta[RADIX];
-    __shared__ uint32_t scan_tmp[W];
+    __shared__ uint32_t ddelta[RADIX];
+    __shared__ uint64_t scan_tmp[W];
     const uint32_t tid = threadIdx.x;
     const uint32_t tile = blockIdx.x;
     if (lb_clear && tid < RADIX) lb_clear[static_cast<size_t>(tile) * RADIX + tid] = 0;
