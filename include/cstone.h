@@ -211,6 +211,103 @@ CSTONE_API cstone_status cstone_build(const double* x, const double* y, const do
                            uint32_t* iters_done, void* ws, size_t ws_bytes, cstone_timings* timings,
                            hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Sort tile shapes. The radix sort has a few compiled shapes (digit width,
+ * block size, keys per thread); the autotuner times them and the fastest is
+ * used from then on by every sort of the process (the only process-wide
+ * state of the library).
+ *   cstone_sort_autotune  sorts keys_in (device, n, < 2^63) with every shape,
+ *                         reps times each, writes the mean times (host, one
+ *                         per shape, or NULL) and the index chosen, and makes
+ *                         it the default. ws: cstone_sort_workspace_bytes(n).
+ *                         Synchronises `stream`.
+ */
+CSTONE_API int cstone_sort_variant_count(void);
+CSTONE_API cstone_status cstone_sort_variant_info(int variant, int* digit_bits, int* block, int* items);
+CSTONE_API cstone_status cstone_sort_autotune(const uint64_t* keys_in, size_t n, uint64_t* keys_out, uint32_t* perm_out,
+                                   void* ws, size_t ws_bytes, int reps, float* ms_per_variant, int* chosen,
+                                   hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Batched builds: many independent particle sets (Sec. 4-5 for each), of
+ * uneven sizes and N_crit, built from their root leaves by one sequence of
+ * launches with no host synchronisation (every stage is a single launch over
+ * all sets: per-tile set tables for the keys and the segmented sort, the sets'
+ * cornerstone arrays kept back to back through the rebalance rounds with one
+ * scan per round and per-set convergence flags, one linking pass). The
+ * sequence can be captured once into a hipGraph and replayed.
+ *
+ * Layout. Particles of set s occupy [particle_offsets[s], particle_offsets[s+1])
+ * of x, y, z, sorted_keys and perm (perm values count from the set's first
+ * particle). Its cornerstone array goes to leaves[leaf_offsets[s] ...] (n_leaves
+ * + 1 keys, at most leaf_capacity + 1), its counts to counts[leaf_offsets[s] ...],
+ * its nodes to node_keys / child[node_offsets[s] ...] (child indices relative
+ * to the set), and its 23 level offsets to level_offsets[23 s ...].
+ * results[s] receives leaf and node counts, rounds and a cstone_status (OK,
+ * NONFINITE, CAPACITY, NOT_CONVERGED) for the set.
+ */
+typedef struct cstone_set {
+    uint64_t n;             /* particles, 0 allowed */
+    cstone_box box;
+    int32_t curve;          /* cstone_curve */
+    uint32_t n_crit;        /* >= 1 */
+    uint64_t leaf_capacity; /* 0: cstone_leaf_capacity_bound(n, n_crit, 1) */
+} cstone_set;
+
+typedef struct cstone_set_result {
+    uint32_t n_leaves, n_nodes, rounds, status;
+} cstone_set_result;
+
+typedef struct cstone_batch_layout {
+    uint64_t n_sets;
+    uint64_t n_particles;     /* sum of n */
+    uint64_t leaf_slots;      /* entries of leaves and counts */
+    uint64_t node_slots;      /* entries of node_keys and child */
+    uint64_t workspace_bytes; /* for any sort shape */
+    uint64_t n_tiles;         /* sort tiles of the current shape */
+    int32_t sort_variant;
+    uint32_t rounds;          /* rebalance rounds enqueued (rounds after convergence exit at once) */
+} cstone_batch_layout;
+
+typedef struct cstone_batch cstone_batch; /* host-side plan */
+
+/* Plan a batch: offsets, capacities and tile tables (host memory only).
+ * Errors: INVALID_ARG (n_crit 0, a bad box or curve, more than 2^32 - 1
+ * particles or entries in total). */
+CSTONE_API cstone_status cstone_batch_create(const cstone_set* sets, uint32_t n_sets, cstone_batch** plan);
+CSTONE_API void cstone_batch_destroy(cstone_batch* plan);
+/* Any of the offset arrays (host, n_sets + 1 entries) may be NULL. */
+CSTONE_API cstone_status cstone_batch_get_layout(const cstone_batch* plan, cstone_batch_layout* layout,
+                                      uint64_t* particle_offsets, uint64_t* leaf_offsets, uint64_t* node_offsets);
+/* Sort shape of this plan (cstone_sort_variant_count() shapes); call
+ * cstone_batch_upload again afterwards. */
+CSTONE_API cstone_status cstone_batch_set_variant(cstone_batch* plan, int variant);
+/* Copy the plan's tables into the workspace (device, layout.workspace_bytes).
+ * Synchronises `stream`; needed once before building with that workspace. */
+CSTONE_API cstone_status cstone_batch_upload(const cstone_batch* plan, void* ws, size_t ws_bytes, hipStream_t stream);
+/* Enqueue the whole batched build on `stream`; no host synchronisation, no
+ * allocation, so it may be captured. Device arrays as in the layout above. */
+CSTONE_API cstone_status cstone_batch_build(const cstone_batch* plan, const double* x, const double* y, const double* z,
+                                 uint64_t* sorted_keys, uint32_t* perm, uint64_t* leaves, uint32_t* counts,
+                                 uint64_t* node_keys, uint32_t* child, uint32_t* level_offsets,
+                                 cstone_set_result* results, void* ws, size_t ws_bytes, hipStream_t stream);
+/* Capture cstone_batch_build with these arrays into a hipGraph kept by the
+ * plan (replacing an earlier one). `stream` must not be the null stream. */
+CSTONE_API cstone_status cstone_batch_capture(cstone_batch* plan, const double* x, const double* y, const double* z,
+                                   uint64_t* sorted_keys, uint32_t* perm, uint64_t* leaves, uint32_t* counts,
+                                   uint64_t* node_keys, uint32_t* child, uint32_t* level_offsets,
+                                   cstone_set_result* results, void* ws, size_t ws_bytes, hipStream_t stream);
+/* Launch the captured graph on `stream` (asynchronous). */
+CSTONE_API cstone_status cstone_batch_launch(cstone_batch* plan, hipStream_t stream);
+/* Build with every sort shape (reps timed builds each, after one warm-up),
+ * keep the fastest in the plan and upload it. Times per shape (host, or NULL).
+ * Drops a captured graph. Synchronises `stream`. */
+CSTONE_API cstone_status cstone_batch_autotune(cstone_batch* plan, const double* x, const double* y, const double* z,
+                                    uint64_t* sorted_keys, uint32_t* perm, uint64_t* leaves, uint32_t* counts,
+                                    uint64_t* node_keys, uint32_t* child, uint32_t* level_offsets,
+                                    cstone_set_result* results, void* ws, size_t ws_bytes, int reps,
+                                    float* ms_per_variant, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -53,6 +53,17 @@ class Box(ctypes.Structure):
         return cls((ctypes.c_double * 3)(*map(float, lo)), (ctypes.c_double * 3)(*map(float, hi)))
 
 
+class CSet(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("box", Box), ("curve", ctypes.c_int32), ("n_crit", ctypes.c_uint32),
+                ("leaf_capacity", ctypes.c_uint64)]
+
+
+class BatchLayout(ctypes.Structure):
+    _fields_ = [("n_sets", ctypes.c_uint64), ("n_particles", ctypes.c_uint64), ("leaf_slots", ctypes.c_uint64),
+                ("node_slots", ctypes.c_uint64), ("workspace_bytes", ctypes.c_uint64), ("n_tiles", ctypes.c_uint64),
+                ("sort_variant", ctypes.c_int32), ("rounds", ctypes.c_uint32)]
+
+
 def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2307_06345_amd.build.build() "
@@ -75,6 +86,19 @@ def _load() -> ctypes.CDLL:
         "cstone_link_workspace_bytes": (sz, [sz]),
         "cstone_link_octree": (i32, [P, sz, P, P, P, P, sz, P]),
         "cstone_link_octree_by_sort": (i32, [P, sz, P, P, P, P, sz, P]),
+        "cstone_sort_variant_count": (i32, []),
+        "cstone_sort_variant_info": (i32, [i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "cstone_sort_autotune": (i32, [P, sz, P, P, P, sz, i32, ctypes.POINTER(ctypes.c_float),
+                                       ctypes.POINTER(i32), P]),
+        "cstone_batch_create": (i32, [ctypes.POINTER(CSet), u32, ctypes.POINTER(P)]),
+        "cstone_batch_destroy": (None, [P]),
+        "cstone_batch_get_layout": (i32, [P, ctypes.POINTER(BatchLayout), P, P, P]),
+        "cstone_batch_set_variant": (i32, [P, i32]),
+        "cstone_batch_upload": (i32, [P, P, sz, P]),
+        "cstone_batch_build": (i32, [P] + [P] * 11 + [P, sz, P]),
+        "cstone_batch_capture": (i32, [P] + [P] * 11 + [P, sz, P]),
+        "cstone_batch_launch": (i32, [P, P]),
+        "cstone_batch_autotune": (i32, [P] + [P] * 11 + [P, sz, i32, ctypes.POINTER(ctypes.c_float), P]),
         "cstone_build_workspace_bytes": (sz, [sz, sz]),
         "cstone_build": (i32, [P, P, P, sz, pbox, i32, u32, P, P, P, psz, sz, P, P, P, P, u32, pu32, P, sz,
                                ctypes.POINTER(Timings), P]),
@@ -306,3 +330,153 @@ class Builder:
 def build(x, y, z, box, curve=HILBERT, n_crit: int = 64, link: bool = True) -> BuildResult:
     """One-shot build (allocates a Builder sized for this set)."""
     return Builder(x.numel(), n_crit, device=x.device, link=link).build(x, y, z, box, curve, n_crit)
+
+
+# ---- sort shapes and their autotuner ------------------------------------------------
+
+def sort_variants() -> list:
+    """(digit bits, block, items per thread) of every compiled sort shape."""
+    out = []
+    for v in range(_lib.cstone_sort_variant_count()):
+        b, bl, it = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(_lib.cstone_sort_variant_info(v, ctypes.byref(b), ctypes.byref(bl), ctypes.byref(it)),
+               "cstone_sort_variant_info")
+        out.append((b.value, bl.value, it.value))
+    return out
+
+
+def sort_autotune(keys, reps: int = 3, stream=None):
+    """Time every sort shape on `keys` and make the fastest the default.
+    Returns (chosen index, ms per shape)."""
+    n = keys.numel()
+    _dev(keys, torch.int64)
+    out = torch.empty_like(keys)
+    perm = torch.empty(n, dtype=torch.int32, device=keys.device)
+    ws = _workspace(_lib.cstone_sort_workspace_bytes(n), keys.device)
+    nv = _lib.cstone_sort_variant_count()
+    ms = (ctypes.c_float * nv)()
+    chosen = ctypes.c_int(-1)
+    _check(_lib.cstone_sort_autotune(_ptr(keys), n, _ptr(out), _ptr(perm), _ptr(ws), ws.numel(), int(reps), ms,
+                                     ctypes.byref(chosen), _stream(stream)), "cstone_sort_autotune")
+    return chosen.value, list(ms)
+
+
+# ---- batched builds -------------------------------------------------------------------
+
+SET_RESULT_FIELDS = ("n_leaves", "n_nodes", "rounds", "status")
+
+
+class Batch:
+    """A planned batch of independent particle sets and every device buffer
+    its build needs (allocated once here; building allocates nothing).
+
+    `sets` is a sequence of (n, box, curve, n_crit) or (n, box, curve, n_crit,
+    leaf_capacity). Particles of set s are x[po[s]:po[s+1]] (po =
+    self.particle_offsets); build() enqueues the whole batch, capture() records
+    it into a hipGraph that launch() replays."""
+
+    def __init__(self, sets, device="cuda"):
+        self.device = torch.device(device)
+        arr = (CSet * max(len(sets), 1))()
+        for i, spec in enumerate(sets):
+            n, box, curve, n_crit = spec[:4]
+            cap = spec[4] if len(spec) > 4 else 0
+            arr[i] = CSet(int(n), Box.of(box), int(curve), int(n_crit), int(cap))
+        self.n_sets = len(sets)
+        plan = ctypes.c_void_p()
+        _check(_lib.cstone_batch_create(arr, self.n_sets, ctypes.byref(plan)), "cstone_batch_create")
+        self._plan = plan
+        self._refresh_layout()
+        lay = self.layout
+        dev = self.device
+        n = max(int(lay.n_particles), 1)
+        self.sorted_keys = torch.empty(n, dtype=torch.int64, device=dev)
+        self.perm = torch.empty(n, dtype=torch.int32, device=dev)
+        self.leaves = torch.empty(max(int(lay.leaf_slots), 1), dtype=torch.int64, device=dev)
+        self.counts = torch.empty(max(int(lay.leaf_slots), 1), dtype=torch.int32, device=dev)
+        self.node_keys = torch.empty(max(int(lay.node_slots), 1), dtype=torch.int64, device=dev)
+        self.child = torch.empty(max(int(lay.node_slots), 1), dtype=torch.int32, device=dev)
+        self.level_offsets = torch.empty(max(self.n_sets, 1) * LEVEL_OFFSETS, dtype=torch.int32, device=dev)
+        self.results = torch.zeros(max(self.n_sets, 1) * 4, dtype=torch.int32, device=dev)
+        self.ws = _workspace(lay.workspace_bytes, dev)
+        self.upload()
+
+    def _refresh_layout(self):
+        lay = BatchLayout()
+        k = self.n_sets + 1
+        po, lo, no = (ctypes.c_uint64 * k)(), (ctypes.c_uint64 * k)(), (ctypes.c_uint64 * k)()
+        _check(_lib.cstone_batch_get_layout(self._plan, ctypes.byref(lay), po, lo, no), "cstone_batch_get_layout")
+        self.layout = lay
+        self.particle_offsets = np.frombuffer(po, dtype=np.uint64).astype(np.int64)
+        self.leaf_offsets = np.frombuffer(lo, dtype=np.uint64).astype(np.int64)
+        self.node_offsets = np.frombuffer(no, dtype=np.uint64).astype(np.int64)
+
+    def __del__(self):
+        plan = getattr(self, "_plan", None)
+        if plan is not None and plan.value:
+            _lib.cstone_batch_destroy(plan)
+            self._plan = None
+
+    @property
+    def n_particles(self) -> int:
+        return int(self.layout.n_particles)
+
+    @property
+    def sort_variant(self) -> int:
+        return int(self.layout.sort_variant)
+
+    def set_variant(self, variant: int, stream=None):
+        _check(_lib.cstone_batch_set_variant(self._plan, int(variant)), "cstone_batch_set_variant")
+        self._refresh_layout()
+        self.upload(stream)
+
+    def upload(self, stream=None):
+        _check(_lib.cstone_batch_upload(self._plan, _ptr(self.ws), self.ws.numel(), _stream(stream)),
+               "cstone_batch_upload")
+
+    def _args(self, x, y, z):
+        for t in (x, y, z):
+            _dev(t, torch.float64)
+            assert t.numel() >= self.n_particles
+        return [_ptr(x), _ptr(y), _ptr(z), _ptr(self.sorted_keys), _ptr(self.perm), _ptr(self.leaves),
+                _ptr(self.counts), _ptr(self.node_keys), _ptr(self.child), _ptr(self.level_offsets),
+                _ptr(self.results), _ptr(self.ws), self.ws.numel()]
+
+    def build(self, x, y, z, stream=None):
+        """Enqueue the batched build (asynchronous)."""
+        _check(_lib.cstone_batch_build(self._plan, *self._args(x, y, z), _stream(stream)), "cstone_batch_build")
+
+    def capture(self, x, y, z, stream):
+        """Record the build with these inputs into a hipGraph (stream: a torch.cuda.Stream)."""
+        _check(_lib.cstone_batch_capture(self._plan, *self._args(x, y, z), _stream(stream)), "cstone_batch_capture")
+
+    def launch(self, stream=None):
+        _check(_lib.cstone_batch_launch(self._plan, _stream(stream)), "cstone_batch_launch")
+
+    def autotune(self, x, y, z, reps: int = 3, stream=None):
+        """Time every sort shape on this batch and keep the fastest; returns ms per shape."""
+        nv = _lib.cstone_sort_variant_count()
+        ms = (ctypes.c_float * nv)()
+        _check(_lib.cstone_batch_autotune(self._plan, *self._args(x, y, z), int(reps), ms, _stream(stream)),
+               "cstone_batch_autotune")
+        self._refresh_layout()
+        return list(ms)
+
+    def set_results(self) -> np.ndarray:
+        """(n_sets, 4) uint32: n_leaves, n_nodes, rounds, status of every set (synchronises)."""
+        return to_numpy(self.results[: 4 * self.n_sets]).reshape(self.n_sets, 4)
+
+    def set_view(self, s: int, res=None) -> dict:
+        """Device views of set s's outputs (after the build has finished)."""
+        if res is None:
+            res = self.set_results()[s]
+        nl, nn = int(res[0]), int(res[1])
+        p0, p1 = int(self.particle_offsets[s]), int(self.particle_offsets[s + 1])
+        l0, n0 = int(self.leaf_offsets[s]), int(self.node_offsets[s])
+        return {
+            "sorted_keys": self.sorted_keys[p0:p1], "perm": self.perm[p0:p1],
+            "leaves": self.leaves[l0:l0 + nl + 1], "counts": self.counts[l0:l0 + nl],
+            "node_keys": self.node_keys[n0:n0 + nn], "child": self.child[n0:n0 + nn],
+            "level_offsets": self.level_offsets[s * LEVEL_OFFSETS:(s + 1) * LEVEL_OFFSETS],
+            "n_leaves": nl, "n_nodes": nn, "rounds": int(res[2]), "status": STATUS.get(int(res[3]), int(res[3])),
+        }

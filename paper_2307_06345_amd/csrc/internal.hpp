@@ -22,17 +22,82 @@ size_t sort_workspace_bytes(size_t n, bool with_perm);
 // sort_first_histogram() (*mask + 1 counters), so neither step is repeated.
 cstone_status launch_sort(const uint64_t* keys_in, uint64_t* keys_out, uint32_t* perm_out, size_t n,
                           int sig_bits, void* ws, size_t ws_bytes, hipStream_t stream,
-                          hipEvent_t* pass_events = nullptr, bool prepared = false);
+                          hipEvent_t* pass_events = nullptr, bool prepared = false, int variant = -1);
 cstone_status sort_prepare(void* ws, size_t n, bool with_perm, hipStream_t stream);
 uint32_t* sort_first_histogram(void* ws, size_t n, bool with_perm, uint32_t* mask);
 int sort_passes(int sig_bits);
+
+// ---- batched builds: many independent sets in one pass of every stage -------
+
+// One particle set of a batch, as the kernels see it (device copy in the
+// caller's workspace). Particles of set s occupy [part_off, part_off + n) of
+// the concatenated particle arrays; its leaves, counts, nodes and level
+// offsets go to its own output regions.
+struct BatchSet {
+    double lo[3];
+    double scale[3];  // 2^21 / (hi - lo), per axis
+    uint32_t n;
+    uint32_t curve;
+    uint32_t n_crit;
+    uint32_t part_off;
+    uint64_t leaf_off;  // first slot of its leaves (cap + 1 slots) and counts
+    uint64_t node_off;  // first slot of its node keys and child offsets
+    uint64_t cap;       // leaf capacity
+    uint64_t node_cap;  // cap + (cap - 1) / 7
+};
+
+// Per-set result, written on the device: leaf and node counts, rebalance
+// rounds (including the final check) and a cstone_status.
+struct BatchResult {
+    uint32_t n_leaves, n_nodes, rounds, status;
+};
+
+// keys.hip — tiles[b] = {first particle, count, unused, set}; the lowest
+// digit (key & hist_mask) is counted into hist0 + set * hist_stride.
+cstone_status launch_keys_batch(const double* x, const double* y, const double* z, const uint4* tiles,
+                                uint32_t n_tiles, const BatchSet* sets, uint64_t* keys, uint32_t* set_flags,
+                                uint32_t* hist0, uint32_t hist_stride, uint32_t hist_mask, hipStream_t stream);
+
+// sort.hip — segmented sort: tiles[b] = {first key, count, first tile of its
+// set, set}, never straddling two sets; seg_base[s] = first key of set s.
+// Permutation values are relative to the set's first key.
+struct SortVariantInfo {
+    int bits, block, items, tile;
+};
+int sort_variant_count();
+SortVariantInfo sort_variant_info(int variant);
+int sort_default_variant();
+void sort_set_tuned_variant(int variant);  // -1: back to the built-in default
+size_t sort_seg_workspace_bytes(size_t n_total, size_t n_tiles, uint32_t n_sets, int variant);
+cstone_status sort_seg_prepare(void* ws, size_t n_total, size_t n_tiles, uint32_t n_sets, int variant,
+                               hipStream_t stream);
+// first-digit counters of the segmented sort (set s at + s * *stride)
+uint32_t* sort_seg_first_histogram(void* ws, size_t n_total, size_t n_tiles, uint32_t n_sets, int variant,
+                                   uint32_t* stride, uint32_t* mask);
+cstone_status launch_sort_segmented(const uint64_t* keys_in, uint64_t* keys_out, uint32_t* perm_out,
+                                    size_t n_total, const uint4* tiles, uint32_t n_tiles, const uint32_t* seg_base,
+                                    uint32_t n_sets, size_t max_set, int sig_bits, int variant, void* ws,
+                                    size_t ws_bytes, hipStream_t stream);
 
 // rebalance.hip
 cstone_status launch_node_counts(const uint64_t* sorted_keys, size_t n, const uint64_t* leaves, size_t n_leaves,
                                  uint32_t* counts, hipStream_t stream);
 size_t rebalance_workspace_bytes(size_t n, uint32_t n_crit, size_t leaf_capacity);
 
-struct LoopState;
+constexpr int kMaxRounds = 64;
+
+// Device-side loop state.
+struct LoopState {
+    uint64_t nl[kMaxRounds + 1];    // leaves entering round r (batched: entries, closing keys included)
+    uint32_t changed[kMaxRounds];   // some O_i != 1 in round r
+    uint32_t counters[kMaxRounds];  // dynamic tile counter of round r
+    uint32_t nsplit[kMaxRounds];    // split leaves listed in round r
+    uint32_t err;
+    uint32_t input_flags;  // copy of the caller's key-stage flag word
+    uint64_t final_nl;     // set by the finalize kernel: leaves (entries) of the result array
+    uint32_t final_last;   // rounds behind it
+    uint32_t final_code;   // 0 running, 1 converged, 2 capacity exceeded
+};
 
 // The rebalance loop, driven from the device: rounds are enqueued ahead of
 // the host's convergence check, and after every batch a finalize kernel picks
@@ -76,12 +141,33 @@ cstone_status run_rebalance(const uint64_t* sorted_keys, size_t n, uint32_t n_cr
                             size_t* n_leaves, size_t leaf_capacity, uint32_t* counts, uint32_t max_iters,
                             uint32_t* iters_done, void* ws, size_t ws_bytes, hipStream_t stream);
 
+// Batched rebalance from the root of every set, all rounds enqueued at once
+// (a round after global convergence exits at once), then per-set leaves,
+// counts and results. Sets' arrays are kept back to back on the device.
+size_t batch_rebalance_workspace_bytes(uint32_t n_sets, size_t entry_capacity, size_t split_capacity);
+cstone_status launch_batch_rebalance(const uint64_t* P, const BatchSet* sets, uint32_t n_sets,
+                                     size_t entry_capacity, size_t split_capacity, uint32_t rounds,
+                                     const uint32_t* set_flags, uint64_t* leaves, uint32_t* counts,
+                                     BatchResult* results, void* ws, size_t ws_bytes, hipStream_t stream);
+// The final back-to-back arrays, for the batched link.
+struct BatchTreeView {
+    const uint64_t* K[2];
+    const uint32_t* sid[2];
+    const uint32_t* starts[2];
+    const LoopState* st;
+};
+BatchTreeView batch_rebalance_view(void* ws, uint32_t n_sets, size_t entry_capacity, size_t split_capacity);
+
 // link.hip — n_leaves_dev, if not NULL, holds the leaf count on the device
 // (then n_leaves is only an upper bound used to size grids and workspace).
 size_t link_workspace_bytes(size_t n_leaves);
 cstone_status launch_link(const uint64_t* leaves, size_t n_leaves, const uint64_t* n_leaves_dev,
                           uint64_t* node_keys, uint32_t* child, uint32_t* level_offsets, void* ws, size_t ws_bytes,
                           hipStream_t stream);
+size_t link_batch_workspace_bytes(uint32_t n_sets, size_t entry_capacity);
+cstone_status launch_link_batch(const BatchTreeView& tree, const BatchSet* sets, uint32_t n_sets,
+                                size_t entry_capacity, uint64_t* node_keys, uint32_t* child,
+                                uint32_t* level_offsets, void* ws, size_t ws_bytes, hipStream_t stream);
 cstone_status launch_link_by_sort(const uint64_t* leaves, size_t n_leaves, uint64_t* node_keys, uint32_t* child,
                                   uint32_t* level_offsets, void* ws, size_t ws_bytes, hipStream_t stream);
 

@@ -232,7 +232,60 @@ void launch_keys_t(size_t blocks, hipStream_t stream, const double* x, const dou
                        box.lo[0], box.lo[1], box.lo[2], s[0], s[1], s[2], keys, flags, hist0, hmask);
 }
 
+// Batched keys: block b encodes tile tiles[b] = {first particle, count, -, set}
+// with that set's box and curve, and counts the lowest digit into the set's
+// histogram.
+__global__ __launch_bounds__(kKeysBlock) void keys_batch_kernel(const double* __restrict__ x,
+                                                                const double* __restrict__ y,
+                                                                const double* __restrict__ z,
+                                                                const uint4* __restrict__ tiles,
+                                                                const BatchSet* __restrict__ sets,
+                                                                uint64_t* __restrict__ keys, uint32_t* set_flags,
+                                                                uint32_t* hist0, uint32_t hist_stride,
+                                                                uint32_t hmask) {
+    __shared__ uint16_t two[kStates * 64];
+    __shared__ uint16_t first[8];
+    __shared__ uint32_t h[512];
+    const uint4 t = tiles[blockIdx.x];
+    const BatchSet& S = sets[t.w];
+    const bool hilbert = S.curve == CSTONE_HILBERT;
+    if (hilbert) {
+        for (int i = threadIdx.x; i < kStates * 64; i += kKeysBlock) two[i] = d_hilbert.two[i];
+        if (threadIdx.x < 8) first[threadIdx.x] = d_hilbert.first[threadIdx.x];
+    }
+    for (int i = threadIdx.x; i < 512; i += kKeysBlock) h[i] = 0;
+    __syncthreads();
+    const double lo0 = S.lo[0], lo1 = S.lo[1], lo2 = S.lo[2];
+    const double s0 = S.scale[0], s1 = S.scale[1], s2 = S.scale[2];
+    bool bad = false;
+    const uint32_t end = t.x + t.y;
+    for (uint32_t p = t.x + threadIdx.x; p < end; p += kKeysBlock) {
+        const double cx = x[p], cy = y[p], cz = z[p];
+        bad |= !finite3(cx, cy, cz);
+        const uint64_t k = hilbert ? key_of<CSTONE_HILBERT>(cx, cy, cz, lo0, lo1, lo2, s0, s1, s2, two, first)
+                                   : key_of<CSTONE_MORTON>(cx, cy, cz, lo0, lo1, lo2, s0, s1, s2, two, first);
+        keys[p] = k;
+        atomicAdd(&h[k & hmask], 1u);
+    }
+    if (__ballot(bad) != 0ull && lane_id() == 0) atomicOr(&set_flags[t.w], CSTONE_FLAG_NONFINITE);
+    __syncthreads();
+    uint32_t* hs = hist0 + static_cast<size_t>(t.w) * hist_stride;
+    for (uint32_t i = threadIdx.x; i <= hmask; i += kKeysBlock)
+        if (h[i]) atomicAdd(&hs[i], h[i]);
+}
+
 }  // namespace
+
+cstone_status launch_keys_batch(const double* x, const double* y, const double* z, const uint4* tiles,
+                                uint32_t n_tiles, const BatchSet* sets, uint64_t* keys, uint32_t* set_flags,
+                                uint32_t* hist0, uint32_t hist_stride, uint32_t hist_mask, hipStream_t stream) {
+    if (n_tiles == 0) return CSTONE_OK;
+    if (hist_mask >= 512) return CSTONE_ERR_INVALID_ARG;
+    hipLaunchKernelGGL(keys_batch_kernel, dim3(n_tiles), dim3(kKeysBlock), 0, stream, x, y, z, tiles, sets, keys,
+                       set_flags, hist0, hist_stride, hist_mask);
+    CS_HIP(hipGetLastError());
+    return CSTONE_OK;
+}
 
 cstone_status launch_keys(const double* x, const double* y, const double* z, size_t n, const cstone_box& box,
                           cstone_curve curve, uint64_t* keys, uint32_t* flags, hipStream_t stream, uint32_t* hist0,

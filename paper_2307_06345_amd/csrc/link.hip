@@ -21,6 +21,8 @@
 // ancestor whose path digit is >= 4 has its own 4|5 boundary further left.
 // Writing mu(k) = -k for k < 4 and 7 - k for k >= 4, sum mu equals
 // 7 #{k_m >= 4} - sum k_m, which popcounts of the prefix give directly.
+#include <algorithm>
+
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -224,7 +226,201 @@ __global__ __launch_bounds__(kBfBlock) void bf_write_kernel(const uint64_t* __re
     }
 }
 
+// ---- batched link: the back-to-back arrays of many sets ------------------------
+//
+// The same placement per set: node (l, j) of set s sits at
+// LO_s[l] + #{leaves j' < j of set s starting a node of level l}. The counts
+// and the per-level scan run over all entries at once (a closing entry starts
+// no node, the first leaf of a set has a = -1); subtracting the running count
+// at the set's first entry makes them relative to the set.
+
+__device__ __forceinline__ LeafLevels entry_levels(const uint64_t* __restrict__ K, size_t M, size_t first) {
+    LeafLevels r;
+#pragma unroll
+    for (int it = 0; it < kBfItems; ++it) {
+        const size_t j = first + it;
+        r.a[it] = 0;
+        r.lam[it] = -1;
+        if (j < M) {
+            const uint64_t kj = K[j];
+            if (kj != kKeyEnd) {
+                r.lam[it] = span_level(K[j + 1] - kj);
+                r.a[it] = kj == 0 ? -1 : (clz64(K[j - 1] ^ kj) - 1) / 3;
+            }
+        }
+    }
+    return r;
+}
+
+struct BatchSrc {
+    const uint64_t* K;
+    const uint32_t* sid;
+    const uint32_t* starts;
+    size_t M;
+};
+
+__device__ __forceinline__ BatchSrc batch_src(const BatchTreeView& v) {
+    const int b = v.st->final_last & 1u;
+    return {v.K[b], v.sid[b], v.starts[b], v.st->final_nl};
+}
+
+__global__ __launch_bounds__(kBfBlock) void batch_bf_count_kernel(BatchTreeView view,
+                                                                  uint32_t* __restrict__ tile_counts,
+                                                                  uint32_t stride) {
+    __shared__ uint32_t wtot[kLevels][kBfWaves];
+    const BatchSrc src = batch_src(view);
+    const uint32_t tiles = static_cast<uint32_t>((src.M + kBfTile - 1) / kBfTile);
+    const uint32_t wave = threadIdx.x / kWave;
+    for (uint32_t tile = blockIdx.x; tile < tiles && tile < stride; tile += gridDim.x) {
+        const LeafLevels r =
+            entry_levels(src.K, src.M, static_cast<size_t>(tile) * kBfTile + threadIdx.x * kBfItems);
+#pragma unroll
+        for (int l = 0; l < kLevels; ++l) {
+            const uint32_t sum = wave_sum<uint32_t>(level_count(r, l));
+            if (lane_id() == 0) wtot[l][wave] = sum;
+        }
+        __syncthreads();
+        if (threadIdx.x < kLevels) {
+            uint32_t sum = 0;
+#pragma unroll
+            for (int w = 0; w < kBfWaves; ++w) sum += wtot[threadIdx.x][w];
+            tile_counts[static_cast<size_t>(threadIdx.x) * stride + tile] = sum;
+        }
+        __syncthreads();
+    }
+}
+
+// Running count of level-l node starts before entry b (the scan gives it per
+// tile; the entries of b's tile before b are counted here). One wave per call.
+__device__ __forceinline__ void running_counts(const BatchSrc& src, const uint32_t* __restrict__ tile_offsets,
+                                               uint32_t stride, const uint32_t* __restrict__ totals, size_t b,
+                                               uint32_t* g) {
+    const uint32_t lane = lane_id();
+    uint32_t c[kLevels];
+#pragma unroll
+    for (int l = 0; l < kLevels; ++l) c[l] = 0;
+    const size_t tile = b / kBfTile;
+    if (b < src.M) {
+        for (size_t e = tile * kBfTile + lane; e < b; e += kWave) {
+            const uint64_t ke = src.K[e];
+            if (ke == kKeyEnd) continue;
+            const int lam = span_level(src.K[e + 1] - ke);
+            const int a = ke == 0 ? -1 : (clz64(src.K[e - 1] ^ ke) - 1) / 3;
+#pragma unroll
+            for (int l = 0; l < kLevels; ++l) c[l] += (a < l && l <= lam) ? 1u : 0u;
+        }
+    }
+#pragma unroll
+    for (int l = 0; l < kLevels; ++l) {
+        const uint32_t part = wave_sum<uint32_t>(c[l]);
+        g[l] = b < src.M ? tile_offsets[static_cast<size_t>(l) * stride + tile] + part : totals[l];
+    }
+}
+
+// Per set: level offsets LO_s and rel[s][l] = LO_s[l] - (running count at the set's first entry).
+__global__ __launch_bounds__(kBfBlock) void batch_bf_base_kernel(BatchTreeView view, uint32_t n_sets,
+                                                                 const uint32_t* __restrict__ tile_offsets,
+                                                                 uint32_t stride, const uint32_t* __restrict__ totals,
+                                                                 uint32_t* __restrict__ rel,
+                                                                 uint32_t* __restrict__ level_offsets) {
+    const BatchSrc src = batch_src(view);
+    const uint32_t s = blockIdx.x * kBfWaves + threadIdx.x / kWave;
+    if (s >= n_sets || src.M == 0) return;
+    uint32_t g0[kLevels], g1[kLevels];
+    running_counts(src, tile_offsets, stride, totals, src.starts[s], g0);
+    running_counts(src, tile_offsets, stride, totals, src.starts[s + 1], g1);
+    if (lane_id() == 0) {
+        uint32_t lo = 0;
+#pragma unroll
+        for (int l = 0; l < kLevels; ++l) {
+            level_offsets[static_cast<size_t>(s) * (kLevels + 1) + l] = lo;
+            rel[static_cast<size_t>(s) * kLevels + l] = lo - g0[l];
+            lo += g1[l] - g0[l];
+        }
+        level_offsets[static_cast<size_t>(s) * (kLevels + 1) + kLevels] = lo;
+    }
+}
+
+__global__ __launch_bounds__(kBfBlock) void batch_bf_write_kernel(BatchTreeView view,
+                                                                  const BatchSet* __restrict__ sets,
+                                                                  const uint32_t* __restrict__ tile_offsets,
+                                                                  uint32_t stride, const uint32_t* __restrict__ rel,
+                                                                  uint64_t* __restrict__ nk,
+                                                                  uint32_t* __restrict__ co) {
+    __shared__ uint32_t wtot[kLevels][kBfWaves];
+    __shared__ uint32_t run[kLevels][kBfBlock];
+    const BatchSrc src = batch_src(view);
+    const uint32_t tiles = static_cast<uint32_t>((src.M + kBfTile - 1) / kBfTile);
+    const uint32_t tid = threadIdx.x;
+    const uint32_t wave = tid / kWave;
+    for (uint32_t tile = blockIdx.x; tile < tiles && tile < stride; tile += gridDim.x) {
+        const size_t first = static_cast<size_t>(tile) * kBfTile + tid * kBfItems;
+        const LeafLevels r = entry_levels(src.K, src.M, first);
+        uint32_t c[kLevels], inc[kLevels];
+#pragma unroll
+        for (int l = 0; l < kLevels; ++l) {
+            c[l] = level_count(r, l);
+            inc[l] = wave_inclusive_sum(c[l]);
+            if (lane_id() == kWave - 1) wtot[l][wave] = inc[l];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int l = 0; l < kLevels; ++l) {
+            uint32_t before = 0;
+#pragma unroll
+            for (int w = 0; w < kBfWaves; ++w) before += w < static_cast<int>(wave) ? wtot[l][w] : 0u;
+            run[l][tid] = tile_offsets[static_cast<size_t>(l) * stride + tile] + before + inc[l] - c[l];
+        }
+#pragma unroll
+        for (int it = 0; it < kBfItems; ++it) {
+            const size_t j = first + it;
+            if (j >= src.M || r.lam[it] < 0) continue;
+            const uint64_t kj = src.K[j];
+            const uint32_t s = src.sid[j];
+            const BatchSet& S = sets[s];
+            const uint32_t* rs = rel + static_cast<size_t>(s) * kLevels;
+            for (int l = r.a[it] + 1; l <= r.lam[it]; ++l) {
+                const uint32_t p = rs[l] + run[l][tid]++;  // index within the set's node array
+                if (p >= S.node_cap) continue;            // never for a cornerstone array; guards memory
+                nk[S.node_off + p] = (1ull << (3 * l)) | (kj >> (3 * (kL - l)));
+                co[S.node_off + p] = l < r.lam[it] ? rs[l + 1] + run[l + 1][tid] : 0u;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace
+
+size_t link_batch_workspace_bytes(uint32_t n_sets, size_t C) {
+    Carve b(nullptr);
+    b.take<uint32_t>(static_cast<size_t>(kLevels) * ((C + 1 + kBfTile - 1) / kBfTile));
+    b.take<uint32_t>(kLevels);
+    b.take<uint32_t>(static_cast<size_t>(n_sets) * kLevels);
+    return b.off;
+}
+
+cstone_status launch_link_batch(const BatchTreeView& view, const BatchSet* sets, uint32_t n_sets, size_t C,
+                                uint64_t* node_keys, uint32_t* child, uint32_t* level_offsets, void* ws,
+                                size_t ws_bytes, hipStream_t stream) {
+    if (ws_bytes < link_batch_workspace_bytes(n_sets, C)) return CSTONE_ERR_INVALID_ARG;
+    if (n_sets == 0) return CSTONE_OK;
+    const uint32_t stride = static_cast<uint32_t>((C + 1 + kBfTile - 1) / kBfTile);
+    Carve c(ws);
+    uint32_t* tile_counts = c.take<uint32_t>(static_cast<size_t>(kLevels) * stride);
+    uint32_t* totals = c.take<uint32_t>(kLevels);
+    uint32_t* rel = c.take<uint32_t>(static_cast<size_t>(n_sets) * kLevels);
+    const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(stride, 2048));
+    hipLaunchKernelGGL(batch_bf_count_kernel, dim3(grid), dim3(kBfBlock), 0, stream, view, tile_counts, stride);
+    hipLaunchKernelGGL(bf_scan_kernel, dim3(kLevels), dim3(kBfBlock), 0, stream, tile_counts, &view.st->final_nl,
+                       static_cast<size_t>(0), stride, totals);
+    hipLaunchKernelGGL(batch_bf_base_kernel, dim3((n_sets + kBfWaves - 1) / kBfWaves), dim3(kBfBlock), 0, stream,
+                       view, n_sets, tile_counts, stride, totals, rel, level_offsets);
+    hipLaunchKernelGGL(batch_bf_write_kernel, dim3(grid), dim3(kBfBlock), 0, stream, view, sets, tile_counts,
+                       stride, rel, node_keys, child);
+    CS_HIP(hipGetLastError());
+    return CSTONE_OK;
+}
 
 size_t link_workspace_bytes(size_t n_leaves) {
     const size_t n = n_leaves + (n_leaves ? (n_leaves - 1) / 7 : 0);

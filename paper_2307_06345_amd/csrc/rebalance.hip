@@ -26,7 +26,6 @@
 namespace cs {
 namespace {
 
-constexpr int kMaxRounds = 64;
 constexpr int kCountBlock = 256;
 constexpr int kRBlock = 256;
 constexpr int kRItems = 8;
@@ -35,22 +34,6 @@ constexpr uint32_t kMaxGrid = 2048;
 constexpr uint32_t kSearchBlock = 256;
 constexpr uint32_t kWaveSearchMin = 1024;  // ranges at least this long use a whole wave
 
-}  // namespace
-
-// Device-side loop state.
-struct LoopState {
-    uint64_t nl[kMaxRounds + 1];    // leaves entering round r
-    uint32_t changed[kMaxRounds];   // some O_i != 1 in round r
-    uint32_t counters[kMaxRounds];  // dynamic tile counter of round r
-    uint32_t nsplit[kMaxRounds];    // split leaves listed in round r
-    uint32_t err;
-    uint32_t input_flags;  // copy of the caller's key-stage flag word
-    uint64_t final_nl;     // set by finalize_kernel: leaves of the result array
-    uint32_t final_last;   // rounds behind it
-    uint32_t final_code;   // 0 running, 1 converged, 2 capacity exceeded
-};
-
-namespace {
 
 // ---- f as a standalone operation -----------------------------------------
 
@@ -470,6 +453,317 @@ cstone_status run_rebalance(const uint64_t* P, size_t n, uint32_t n_crit, uint64
     *n_leaves = loop.n_leaves;
     if (iters_done) *iters_done = loop.rounds;
     return loop.status;
+}
+
+
+// ---- batched rebalance ----------------------------------------------------------
+//
+// The cornerstone arrays of all sets sit back to back, each followed by its
+// closing key 8^L, with sid[e] the set of entry e (sets stay in order and
+// contiguous). A round decides every entry as in the single-set case, with the
+// set's own N_crit; a closing entry is always kept (O = 1), and a merge group
+// must lie inside one set. The exclusive scan then runs over all entries at
+// once, so one launch serves every set; the first entry of each set (key 0)
+// records where that set starts in the next array.
+
+namespace {
+
+__global__ __launch_bounds__(256) void batch_init_kernel(LoopState* st, const BatchSet* __restrict__ sets,
+                                                         uint32_t n_sets, uint64_t* K, uint32_t* pos, uint32_t* sid,
+                                                         uint32_t* starts, uint64_t* lb, size_t lb_words,
+                                                         uint32_t* changed_set, size_t changed_words) {
+    const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+    const size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    for (size_t i = t; i < lb_words; i += stride) lb[i] = 0;
+    for (size_t i = t; i < changed_words; i += stride) changed_set[i] = 0;
+    for (size_t s = t; s < n_sets; s += stride) {  // every set starts as the root leaf
+        const BatchSet& S = sets[s];
+        K[2 * s] = 0;
+        K[2 * s + 1] = kKeyEnd;
+        pos[2 * s] = S.part_off;
+        pos[2 * s + 1] = S.part_off + S.n;
+        sid[2 * s] = sid[2 * s + 1] = static_cast<uint32_t>(s);
+        starts[s] = static_cast<uint32_t>(2 * s);
+    }
+    if (t < kMaxRounds) {
+        st->changed[t] = 0;
+        st->counters[t] = 0;
+        st->nsplit[t] = 0;
+    }
+    if (t <= kMaxRounds) st->nl[t] = t == 0 ? 2ull * n_sets : 0ull;
+    if (t == 0) {
+        starts[n_sets] = 2 * n_sets;
+        st->err = 0;
+        st->input_flags = 0;
+    }
+}
+
+__global__ __launch_bounds__(kRBlock) void batch_round_kernel(const BatchSet* __restrict__ sets,
+                                                               const uint64_t* __restrict__ K,
+                                                               const uint32_t* __restrict__ pos,
+                                                               const uint32_t* __restrict__ sid,
+                                                               uint64_t* __restrict__ K_out,
+                                                               uint32_t* __restrict__ pos_out,
+                                                               uint32_t* __restrict__ sid_out,
+                                                               uint32_t* __restrict__ starts_out, uint32_t n_sets,
+                                                               uint32_t* __restrict__ changed_set,
+                                                               uint64_t* __restrict__ splits, uint32_t split_capacity,
+                                                               LoopState* st, int round, uint64_t capacity,
+                                                               uint64_t* lb) {
+    __shared__ uint32_t slot;
+    __shared__ uint64_t scan_tmp[kRBlock / kWave];
+    __shared__ uint64_t tile_prefix;
+    __shared__ uint32_t split_base;
+    __shared__ uint32_t any_change;
+
+    if (round > 0 && st->changed[round - 1] == 0) return;  // every set converged earlier
+    const uint64_t M = st->nl[round];
+    if (M == 0 || M > capacity) return;  // an earlier round overflowed
+    const uint32_t tiles = static_cast<uint32_t>((M + kRTile - 1) / kRTile);
+    const uint32_t tid = threadIdx.x;
+    const uint32_t epoch = static_cast<uint32_t>(round + 1);
+    if (tid == 0) any_change = 0;
+
+    for (;;) {
+        const uint32_t tile = take_tile(&st->counters[round], &slot);
+        if (tile >= tiles) break;
+        const uint64_t first = static_cast<uint64_t>(tile) * kRTile + static_cast<uint64_t>(tid) * kRItems;
+
+        uint32_t op[kRItems];
+        uint32_t osum = 0, nsplit = 0;
+        bool changed = false;
+        uint32_t flagged = 0xffffffffu;  // last set whose change this thread reported
+#pragma unroll
+        for (int j = 0; j < kRItems; ++j) {
+            const uint64_t e = first + j;
+            uint32_t o = 0;
+            if (e < M) {
+                const uint64_t ke = K[e];
+                o = 1;
+                if (ke != kKeyEnd) {  // a leaf (closing entries are kept)
+                    const uint32_t s = sid[e];
+                    const uint32_t nc = sets[s].n_crit;
+                    const uint64_t delta = K[e + 1] - ke;
+                    const uint32_t cnt = pos[e + 1] - pos[e];
+                    if (cnt > nc && delta > 1) {
+                        o = 8;
+                    } else if (delta < kKeyEnd) {
+                        const uint64_t js = (ke >> (63 - clz64(delta))) & 7u;
+                        if (js >= 1 && e >= js && e - js + 8 < M && sid[e - js] == s && sid[e - js + 8] == s &&
+                            K[e - js] + 8 * delta == K[e - js + 8] && pos[e - js + 8] - pos[e - js] <= nc)
+                            o = 0;
+                    }
+                    if (o != 1) {
+                        changed = true;
+                        if (s != flagged) {
+                            atomicOr(&changed_set[s], 1u);
+                            flagged = s;
+                        }
+                    }
+                }
+            }
+            op[j] = o;
+            osum += o;
+            nsplit += o == 8;
+        }
+
+        uint64_t block_total;
+        const uint64_t excl = block_exclusive_sum<uint64_t, kRBlock>(
+            (static_cast<uint64_t>(nsplit) << 32) | osum, scan_tmp, &block_total);
+        if (tid < kWave) {
+            uint64_t prefix = 0;
+            uint64_t* w = lb + tile;
+            const uint64_t agg = block_total & 0xffffffffull;
+            if (tile == 0) {
+                if (tid == 0) st_agent(w, lb_word(kFlagInc, epoch, agg));
+            } else {
+                if (tid == 0) st_agent(w, lb_word(kFlagAgg, epoch, agg));
+                prefix = lookback_wave<4>(lb, tile, epoch, &st->err);
+                if (tid == 0) st_agent(w, lb_word(kFlagInc, epoch, prefix + agg));
+            }
+            if (tid == 0) {
+                tile_prefix = prefix;
+                const uint32_t sc = static_cast<uint32_t>(block_total >> 32);
+                split_base = sc ? atomicAdd(&st->nsplit[round], sc) : 0u;
+            }
+        }
+        if (changed) any_change = 1;
+        __syncthreads();
+        const uint64_t tp = tile_prefix;
+
+        uint64_t o_prime = tp + (excl & 0xffffffffull);
+        uint32_t s_at = split_base + static_cast<uint32_t>(excl >> 32);
+#pragma unroll
+        for (int j = 0; j < kRItems; ++j) {
+            const uint64_t e = first + j;
+            if (e < M) {
+                const uint64_t ke = K[e];
+                const uint32_t s = sid[e];
+                if (op[j] == 1) {
+                    if (o_prime <= capacity) {
+                        K_out[o_prime] = ke;
+                        pos_out[o_prime] = pos[e];
+                        sid_out[o_prime] = s;
+                        if (ke == 0) starts_out[s] = static_cast<uint32_t>(o_prime);
+                    }
+                    if (e + 1 == M) {  // the last closing key: size of the next array
+                        st->nl[round + 1] = o_prime + 1;
+                        starts_out[n_sets] = static_cast<uint32_t>(o_prime + 1);
+                    }
+                } else if (op[j] == 8) {
+                    if (o_prime + 7 <= capacity) {
+                        const uint64_t child = (K[e + 1] - ke) >> 3;
+#pragma unroll
+                        for (int c = 0; c < 8; ++c) {
+                            K_out[o_prime + c] = ke + c * child;
+                            sid_out[o_prime + c] = s;
+                        }
+                        pos_out[o_prime] = pos[e];
+                        if (ke == 0) starts_out[s] = static_cast<uint32_t>(o_prime);
+                        if (s_at < split_capacity) splits[s_at] = e | (o_prime << 32);
+                    }
+                    ++s_at;
+                }
+            }
+            o_prime += op[j];
+        }
+        __syncthreads();
+    }
+    if (tid == 0 && any_change) atomicOr(&st->changed[round], 1u);
+}
+
+// Per-set leaves, counts and results from the array of the last complete round.
+__global__ __launch_bounds__(256) void batch_finalize_kernel(LoopState* st, uint32_t enqueued, uint64_t capacity,
+                                                             const BatchSet* __restrict__ sets, uint32_t n_sets,
+                                                             const uint64_t* __restrict__ K0,
+                                                             const uint64_t* __restrict__ K1,
+                                                             const uint32_t* __restrict__ pos0,
+                                                             const uint32_t* __restrict__ pos1,
+                                                             const uint32_t* __restrict__ sid0,
+                                                             const uint32_t* __restrict__ sid1,
+                                                             const uint32_t* __restrict__ starts0,
+                                                             const uint32_t* __restrict__ starts1,
+                                                             const uint32_t* __restrict__ changed_set,
+                                                             const uint32_t* __restrict__ set_flags,
+                                                             uint64_t* __restrict__ leaves, uint32_t* __restrict__ counts,
+                                                             BatchResult* __restrict__ results) {
+    const Outcome o = loop_outcome(st, enqueued, capacity);
+    const uint64_t M = o.nl <= capacity ? o.nl : 0;
+    const bool odd = o.last & 1u;
+    const uint64_t* K = odd ? K1 : K0;
+    const uint32_t* pos = odd ? pos1 : pos0;
+    const uint32_t* sid = odd ? sid1 : sid0;
+    const uint32_t* starts = odd ? starts1 : starts0;
+    const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+    const size_t t0 = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    for (size_t e = t0; e < M; e += stride) {
+        const uint32_t s = sid[e];
+        const BatchSet& S = sets[s];
+        const uint64_t i = e - starts[s];
+        const uint64_t nl = starts[s + 1] - starts[s] - 1;
+        if (nl > S.cap) continue;  // this set outgrew its region
+        leaves[S.leaf_off + i] = K[e];
+        if (i < nl) counts[S.leaf_off + i] = pos[e + 1] - pos[e];
+    }
+    for (size_t s = t0; s < n_sets; s += stride) {
+        const uint64_t nl = M ? starts[s + 1] - starts[s] - 1 : 0;
+        uint32_t rounds = o.last, status;
+        bool converged = false;
+        for (uint32_t q = 0; q < o.last; ++q)
+            if (changed_set[static_cast<size_t>(q) * n_sets + s] == 0) {
+                rounds = q + 1;
+                converged = true;
+                break;
+            }
+        if (set_flags[s] & CSTONE_FLAG_NONFINITE)
+            status = CSTONE_ERR_NONFINITE;
+        else if (M == 0 || nl > sets[s].cap)
+            status = CSTONE_ERR_CAPACITY;
+        else if (!converged)
+            status = o.code == 2 ? CSTONE_ERR_CAPACITY : CSTONE_ERR_NOT_CONVERGED;
+        else
+            status = CSTONE_OK;
+        results[s] = {static_cast<uint32_t>(nl), static_cast<uint32_t>(nl ? nl + (nl - 1) / 7 : 0), rounds, status};
+    }
+    if (t0 == 0) {
+        st->final_nl = M;
+        st->final_last = o.last;
+        st->final_code = o.code;
+    }
+}
+
+struct BatchRebalanceWs {
+    uint64_t* K[2];
+    uint32_t* pos[2];
+    uint32_t* sid[2];
+    uint32_t* starts[2];
+    uint64_t* splits;
+    uint32_t* changed_set;
+    LoopState* st;
+    uint64_t* lb;
+    size_t lb_words;
+    size_t bytes;
+};
+
+BatchRebalanceWs carve_batch_rebalance(void* ws, uint32_t n_sets, size_t C, size_t split_capacity) {
+    Carve c(ws);
+    BatchRebalanceWs r{};
+    for (int b = 0; b < 2; ++b) {
+        r.K[b] = c.take<uint64_t>(C + 1);
+        r.pos[b] = c.take<uint32_t>(C + 1);
+        r.sid[b] = c.take<uint32_t>(C + 1);
+        r.starts[b] = c.take<uint32_t>(static_cast<size_t>(n_sets) + 1);
+    }
+    r.splits = c.take<uint64_t>(split_capacity);
+    r.changed_set = c.take<uint32_t>(static_cast<size_t>(kMaxRounds) * n_sets);
+    r.st = c.take<LoopState>(1);
+    r.lb_words = (C + kRTile - 1) / kRTile + 1;
+    r.lb = c.take<uint64_t>(r.lb_words);
+    r.bytes = c.off;
+    return r;
+}
+
+}  // namespace
+
+size_t batch_rebalance_workspace_bytes(uint32_t n_sets, size_t C, size_t split_capacity) {
+    return carve_batch_rebalance(nullptr, n_sets, C, split_capacity).bytes;
+}
+
+BatchTreeView batch_rebalance_view(void* ws, uint32_t n_sets, size_t C, size_t split_capacity) {
+    BatchRebalanceWs w = carve_batch_rebalance(ws, n_sets, C, split_capacity);
+    return {{w.K[0], w.K[1]}, {w.sid[0], w.sid[1]}, {w.starts[0], w.starts[1]}, w.st};
+}
+
+cstone_status launch_batch_rebalance(const uint64_t* P, const BatchSet* sets, uint32_t n_sets, size_t C,
+                                     size_t split_capacity, uint32_t rounds, const uint32_t* set_flags,
+                                     uint64_t* leaves, uint32_t* counts, BatchResult* results, void* ws,
+                                     size_t ws_bytes, hipStream_t stream) {
+    BatchRebalanceWs w = carve_batch_rebalance(ws, n_sets, C, split_capacity);
+    if (ws_bytes < w.bytes) return CSTONE_ERR_INVALID_ARG;
+    if (n_sets == 0) return CSTONE_OK;
+    if (C >= 0xffffffffull || split_capacity >= 0xffffffffull || C < 2ull * n_sets) return CSTONE_ERR_INVALID_ARG;
+    rounds = std::min<uint32_t>(std::max<uint32_t>(rounds, 1), kMaxRounds);
+    const size_t changed_words = static_cast<size_t>(kMaxRounds) * n_sets;
+    hipLaunchKernelGGL(batch_init_kernel,
+                       dim3(clamp_grid(grid_1d(std::max<size_t>({w.lb_words, changed_words, n_sets}), 256))),
+                       dim3(256), 0, stream, w.st, sets, n_sets, w.K[0], w.pos[0], w.sid[0], w.starts[0], w.lb,
+                       w.lb_words, w.changed_set, changed_words);
+    const uint32_t cap_u = static_cast<uint32_t>(split_capacity);
+    for (uint32_t q = 0; q < rounds; ++q) {
+        const int a = q & 1, b = (q + 1) & 1;
+        hipLaunchKernelGGL(batch_round_kernel, dim3(clamp_grid(grid_1d(C + 1, kRTile))), dim3(kRBlock), 0, stream,
+                           sets, w.K[a], w.pos[a], w.sid[a], w.K[b], w.pos[b], w.sid[b], w.starts[b], n_sets,
+                           w.changed_set + static_cast<size_t>(q) * n_sets, w.splits, cap_u, w.st,
+                           static_cast<int>(q), static_cast<uint64_t>(C), w.lb);
+        hipLaunchKernelGGL(split_search_kernel, dim3(clamp_grid(grid_1d(7 * split_capacity, kSearchBlock / kWave))),
+                           dim3(kSearchBlock), 0, stream, P, w.K[a], w.pos[a], w.pos[b], w.splits, cap_u, w.st,
+                           static_cast<int>(q), static_cast<uint64_t>(C));
+    }
+    hipLaunchKernelGGL(batch_finalize_kernel, dim3(clamp_grid(grid_1d(C + 1, 256))), dim3(256), 0, stream, w.st,
+                       rounds, static_cast<uint64_t>(C), sets, n_sets, w.K[0], w.K[1], w.pos[0], w.pos[1], w.sid[0],
+                       w.sid[1], w.starts[0], w.starts[1], w.changed_set, set_flags, leaves, counts, results);
+    CS_HIP(hipGetLastError());
+    return CSTONE_OK;
 }
 
 }  // namespace cs

@@ -11,6 +11,7 @@
 // pass's digit, so only the first digit needs a histogram of its own (which the
 // key kernel of a build provides while writing the keys).
 #include <algorithm>
+#include <atomic>
 #include <cstdlib>
 
 #include "common.hpp"
@@ -24,12 +25,12 @@ constexpr int kMaxPasses = 8;
 constexpr int kHistBlock = 256;
 constexpr int kMinTile = 2048;  // smallest tile of any variant (sizes the look-back rows)
 
-__global__ __launch_bounds__(256) void sort_init_kernel(uint32_t* ghist, uint32_t* err, uint64_t* lb,
-                                                        size_t lb_words) {
+__global__ __launch_bounds__(256) void sort_init_kernel(uint32_t* ghist, size_t ghist_words, uint32_t* err,
+                                                        uint64_t* lb, size_t lb_words) {
     const size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
     for (size_t i = t; i < lb_words; i += stride) lb[i] = 0;  // flag 0: not yet written
-    for (size_t i = t; i < static_cast<size_t>(kMaxPasses) * kMaxRadix; i += stride) ghist[i] = 0;
+    for (size_t i = t; i < ghist_words; i += stride) ghist[i] = 0;
     if (t == 0) *err = 0;
 }
 
@@ -457,13 +458,20 @@ const Variant kVariants[] = {
 #undef CS_VARIANT
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
-int default_variant() {
+int builtin_variant() {
     static const int v = [] {
         const char* e = std::getenv("CSTONE_SORT_VARIANT");
         int x = e ? std::atoi(e) : 1;  // 9-bit digits, 512 x 16 tiles
         return (x >= 0 && x < kNumVariants) ? x : 0;
     }();
     return v;
+}
+
+std::atomic<int> g_tuned_variant{-1};  // set by the autotuner
+
+int default_variant() {
+    const int t = g_tuned_variant.load(std::memory_order_relaxed);
+    return t >= 0 ? t : builtin_variant();
 }
 
 struct SortWs {
@@ -504,8 +512,8 @@ cstone_status sort_prepare(void* ws, size_t n, bool with_perm, hipStream_t strea
     SortWs s = carve_sort(ws, n, with_perm);
     const size_t lb_words = s.lb_bytes / 8;
     const size_t init_grid = std::max<size_t>(4, std::min<size_t>((lb_words + 255) / 256, 1024));
-    hipLaunchKernelGGL(sort_init_kernel, dim3(init_grid), dim3(256), 0, stream, s.ghist, s.err,
-                       static_cast<uint64_t*>(s.lb), lb_words);
+    hipLaunchKernelGGL(sort_init_kernel, dim3(init_grid), dim3(256), 0, stream, s.ghist,
+                       static_cast<size_t>(kMaxPasses) * kMaxRadix, s.err, static_cast<uint64_t*>(s.lb), lb_words);
     CS_HIP(hipGetLastError());
     return CSTONE_OK;
 }
@@ -517,13 +525,15 @@ uint32_t* sort_first_histogram(void* ws, size_t n, bool with_perm, uint32_t* mas
 
 cstone_status launch_sort(const uint64_t* keys_in, uint64_t* keys_out, uint32_t* perm_out, size_t n,
                           int sig_bits, void* ws, size_t ws_bytes, hipStream_t stream, hipEvent_t* pass_events,
-                          bool prepared) {
+                          bool prepared, int variant) {
     const bool with_perm = perm_out != nullptr;
     SortWs s = carve_sort(ws, n, with_perm);
     if (ws_bytes < s.bytes) return CSTONE_ERR_INVALID_ARG;
     if (n == 0) return CSTONE_OK;
     if (n > 0xffffffffull) return CSTONE_ERR_INVALID_ARG;
-    const Variant& var = kVariants[default_variant()];
+    if (variant >= kNumVariants) return CSTONE_ERR_INVALID_ARG;
+    if (prepared && variant >= 0 && variant != default_variant()) return CSTONE_ERR_INVALID_ARG;
+    const Variant& var = kVariants[variant >= 0 ? variant : default_variant()];
     const int radix = 1 << var.bits;
     const int passes = (sig_bits + var.bits - 1) / var.bits;
     if (passes < 1 || passes > kMaxPasses) return CSTONE_ERR_INVALID_ARG;
@@ -563,6 +573,120 @@ cstone_status launch_sort(const uint64_t* keys_in, uint64_t* keys_out, uint32_t*
         src_k = a.keys_out;
         src_v = a.vals_out;
         if (pass_events) CS_HIP(hipEventRecord(pass_events[p + 1], stream));
+    }
+    CS_HIP(hipGetLastError());
+    return CSTONE_OK;
+}
+
+
+// ---- segmented sort ---------------------------------------------------------
+
+int sort_variant_count() { return kNumVariants; }
+
+SortVariantInfo sort_variant_info(int v) {
+    const Variant& x = kVariants[(v >= 0 && v < kNumVariants) ? v : 0];
+    return {x.bits, x.block, x.items, x.block * x.items};
+}
+
+int sort_default_variant() { return default_variant(); }
+
+void sort_set_tuned_variant(int v) { g_tuned_variant.store((v >= 0 && v < kNumVariants) ? v : -1); }
+
+namespace {
+
+struct SegWs {
+    uint64_t* keys_alt;
+    uint32_t* vals_alt;
+    uint32_t* ghist;  // [set][pass][digit]
+    uint32_t stride;  // words per set
+    uint32_t* err;
+    void* lb;
+    size_t lb_bytes;
+    size_t rows;
+    size_t bytes;
+};
+
+SegWs carve_seg(void* ws, size_t n_total, size_t n_tiles, uint32_t n_sets, int variant) {
+    const Variant& var = kVariants[variant];
+    Carve c(ws);
+    SegWs s{};
+    s.keys_alt = c.take<uint64_t>(n_total);
+    s.vals_alt = c.take<uint32_t>(n_total);
+    s.stride = static_cast<uint32_t>(((64 + var.bits - 1) / var.bits) << var.bits);
+    s.ghist = c.take<uint32_t>(static_cast<size_t>(n_sets) * s.stride);
+    s.err = c.take<uint32_t>(1);
+    s.rows = n_tiles;
+    s.lb_bytes = s.rows * kMaxRadix * 8;  // 2 x 32-bit sets, or 1 x 64-bit set
+    s.lb = c.take<uint8_t>(s.lb_bytes);
+    s.bytes = c.off;
+    return s;
+}
+
+}  // namespace
+
+size_t sort_seg_workspace_bytes(size_t n_total, size_t n_tiles, uint32_t n_sets, int variant) {
+    return carve_seg(nullptr, n_total, n_tiles, n_sets, variant).bytes;
+}
+
+cstone_status sort_seg_prepare(void* ws, size_t n_total, size_t n_tiles, uint32_t n_sets, int variant,
+                               hipStream_t stream) {
+    SegWs s = carve_seg(ws, n_total, n_tiles, n_sets, variant);
+    const size_t lb_words = s.lb_bytes / 8;
+    const size_t gwords = static_cast<size_t>(n_sets) * s.stride;
+    const size_t init_grid =
+        std::max<size_t>(4, std::min<size_t>((std::max(lb_words, gwords) + 255) / 256, 2048));
+    hipLaunchKernelGGL(sort_init_kernel, dim3(init_grid), dim3(256), 0, stream, s.ghist, gwords, s.err,
+                       static_cast<uint64_t*>(s.lb), lb_words);
+    CS_HIP(hipGetLastError());
+    return CSTONE_OK;
+}
+
+uint32_t* sort_seg_first_histogram(void* ws, size_t n_total, size_t n_tiles, uint32_t n_sets, int variant,
+                                   uint32_t* stride, uint32_t* mask) {
+    SegWs s = carve_seg(ws, n_total, n_tiles, n_sets, variant);
+    *stride = s.stride;
+    *mask = (1u << kVariants[variant].bits) - 1u;
+    return s.ghist;
+}
+
+cstone_status launch_sort_segmented(const uint64_t* keys_in, uint64_t* keys_out, uint32_t* perm_out,
+                                    size_t n_total, const uint4* tiles, uint32_t n_tiles, const uint32_t* seg_base,
+                                    uint32_t n_sets, size_t max_set, int sig_bits, int variant, void* ws,
+                                    size_t ws_bytes, hipStream_t stream) {
+    if (variant < 0 || variant >= kNumVariants) return CSTONE_ERR_INVALID_ARG;
+    SegWs s = carve_seg(ws, n_total, n_tiles, n_sets, variant);
+    if (ws_bytes < s.bytes) return CSTONE_ERR_INVALID_ARG;
+    if (n_total == 0 || n_tiles == 0) return CSTONE_OK;
+    if (n_total > 0xffffffffull || !perm_out) return CSTONE_ERR_INVALID_ARG;
+    const Variant& var = kVariants[variant];
+    const int radix = 1 << var.bits;
+    const int passes = (sig_bits + var.bits - 1) / var.bits;
+    if (passes < 1 || static_cast<uint32_t>(passes * radix) > s.stride) return CSTONE_ERR_INVALID_ARG;
+    const bool wide = max_set >= (1ull << 30);
+    uint32_t* lb32[2] = {static_cast<uint32_t*>(s.lb), static_cast<uint32_t*>(s.lb) + s.rows * kMaxRadix};
+    SegArgs g{tiles, seg_base, n_tiles, s.stride};
+    const uint64_t* src_k = keys_in;
+    const uint32_t* src_v = nullptr;
+    for (int p = 0; p < passes; ++p) {
+        const bool to_out = ((passes - 1 - p) % 2) == 0;
+        PassArgs a{};
+        a.keys_in = src_k;
+        a.vals_in = src_v;
+        a.keys_out = to_out ? keys_out : s.keys_alt;
+        a.vals_out = to_out ? perm_out : s.vals_alt;
+        a.n = static_cast<uint32_t>(n_total);
+        a.shift = static_cast<uint32_t>(p * var.bits);
+        a.ghist = s.ghist + p * radix;
+        a.ghist_next = p + 1 < passes ? s.ghist + (p + 1) * radix : nullptr;
+        a.shift_next = static_cast<uint32_t>((p + 1) * var.bits) & 63u;
+        a.wide = wide;
+        a.lb = wide ? s.lb : static_cast<void*>(lb32[p & 1]);
+        a.lb_clear = (!wide && p + 1 < passes) ? static_cast<void*>(lb32[(p + 1) & 1]) : nullptr;
+        a.epoch = static_cast<uint32_t>(p + 1);
+        a.err = s.err;
+        var.launch_seg(a, g, p == 0, true, stream);
+        src_k = a.keys_out;
+        src_v = a.vals_out;
     }
     CS_HIP(hipGetLastError());
     return CSTONE_OK;

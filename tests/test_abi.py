@@ -64,3 +64,56 @@ def test_invalid_arguments_are_rejected_without_a_device():
     nl = ctypes.c_size_t(1)
     assert lib.cstone_rebalance(ctypes.c_void_p(8), 10, 0, ctypes.c_void_p(8), ctypes.byref(nl), 10, None, 0, None,
                                 ctypes.c_void_p(8), 1 << 20, None) == 1
+
+
+def _plan(cs, specs):
+    arr = (cs.CSet * max(len(specs), 1))()
+    for i, (n, box, curve, n_crit, cap) in enumerate(specs):
+        arr[i] = cs.CSet(n, cs.Box.of(box), curve, n_crit, cap)
+    plan = ctypes.c_void_p()
+    st = cs._lib.cstone_batch_create(arr, len(specs), ctypes.byref(plan))
+    return st, plan
+
+
+def test_batch_plan_layout_on_the_host():
+    """The batch plan is host-only: offsets are prefix sums of the sizes and
+    of the per-set capacities, tiles never straddle two sets."""
+    import paper_2307_06345_amd as cs
+    unit = ((0, 0, 0), (1, 1, 1))
+    specs = [(0, unit, 0, 8, 0), (1000, unit, 1, 16, 0), (8192, unit, 0, 64, 500), (8193, unit, 1, 1, 0)]
+    st, plan = _plan(cs, specs)
+    assert st == 0
+    try:
+        lay = cs.BatchLayout()
+        k = len(specs) + 1
+        po, lo, no = (ctypes.c_uint64 * k)(), (ctypes.c_uint64 * k)(), (ctypes.c_uint64 * k)()
+        assert cs._lib.cstone_batch_get_layout(plan, ctypes.byref(lay), po, lo, no) == 0
+        ns = [s[0] for s in specs]
+        caps = [s[4] or cs.leaf_capacity_bound(s[0], s[3]) for s in specs]
+        assert list(po) == [0, 0, 1000, 9192, 17385]
+        assert list(lo) == [0] + list(__import__("itertools").accumulate(c + 1 for c in caps))
+        assert list(no) == [0] + list(__import__("itertools").accumulate(c + (c - 1) // 7 for c in caps))
+        assert lay.n_sets == 4 and lay.n_particles == sum(ns)
+        assert lay.leaf_slots == lo[-1] and lay.node_slots == no[-1]
+        for v in range(cs._lib.cstone_sort_variant_count()):
+            bits, block, items = cs.sort_variants()[v]
+            assert cs._lib.cstone_batch_set_variant(plan, v) == 0
+            assert cs._lib.cstone_batch_get_layout(plan, ctypes.byref(lay), None, None, None) == 0
+            tile = block * items
+            assert lay.n_tiles == sum((n + tile - 1) // tile for n in ns)
+            assert lay.sort_variant == v
+            assert lay.workspace_bytes >= 8 * sum(ns)
+    finally:
+        cs._lib.cstone_batch_destroy(plan)
+
+
+def test_batch_plan_rejects_bad_sets():
+    import paper_2307_06345_amd as cs
+    unit = ((0, 0, 0), (1, 1, 1))
+    for bad in [(10, unit, 0, 0, 0),                       # N_crit 0
+                (10, ((0, 0, 0), (1, 0, 1)), 0, 8, 0),     # empty box
+                (10, unit, 7, 8, 0),                       # unknown curve
+                (1 << 32, unit, 0, 8, 0)]:                 # too many particles
+        st, plan = _plan(cs, [bad])
+        assert st == 1 and not plan.value, bad
+    assert cs._lib.cstone_batch_launch(None, None) == 1

@@ -1,0 +1,208 @@
+"""GPU parity of batched builds: many independent sets of uneven sizes, curves
+and N_crit in one launch sequence (eager and replayed from a hipGraph), every
+set bit-exact against the CPU oracle built on that set alone."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as wl
+from tests import invariants as inv
+
+pytestmark = pytest.mark.gpu
+
+cs = pytest.importorskip("paper_2307_06345_amd")
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def host(t):
+    return cs.to_numpy(t)
+
+
+def eq(a, b, what):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    assert a.shape == b.shape, (what, a.shape, b.shape)
+    bad = np.nonzero(a != b)[0]
+    assert bad.size == 0, f"{what}: {bad.size} mismatches, first at {bad[:5]}: {a[bad[:5]]} vs {b[bad[:5]]}"
+
+
+def duplicate_set(n, distinct, seed, curve, n_crit):
+    """Particles stacked on a few distinct points (level-21 leaves over N_crit)."""
+    x, y, z = wl.uniform_cube(distinct, seed, 0)
+    idx = np.arange(n) % distinct
+    return wl.ParticleSet(x[idx].copy(), y[idx].copy(), z[idx].copy(), wl.UNIT_BOX, curve, n_crit, "duplicates")
+
+
+def mixed_sets():
+    H, M = wl.HILBERT, wl.MORTON
+    return [
+        wl.make_set("uniform", 0, 31, 1, M, 8),
+        wl.make_set("uniform", 1, 31, 2, H, 1),
+        wl.make_set("uniform", 1000, 31, 3, M, 8),
+        wl.make_set("plummer", 5000, 31, 4, H, 16),
+        wl.make_set("uniform", 8191, 31, 5, H, 64),
+        wl.make_set("uniform", 8192, 31, 6, M, 32),
+        wl.make_set("plummer", 30000, 31, 7, M, 8),
+        wl.make_set("uniform", 65536, 31, 8, H, 128),
+        wl.make_set("uniform", 20, 31, 9, H, 1),
+        duplicate_set(3000, 7, 31, H, 4),
+        wl.make_set("plummer", 12289, 31, 10, H, 32),
+    ]
+
+
+def coords(sets):
+    cat = [np.concatenate([getattr(s, a) for s in sets] + [np.zeros(0)]) for a in "xyz"]
+    return [cs.from_numpy(c, "cuda") if c.size else torch.zeros(1, dtype=torch.float64, device="cuda")
+            for c in cat]
+
+
+def specs(sets):
+    return [(s.n, s.box, s.curve, s.n_crit) for s in sets]
+
+
+def snapshot(b):
+    """Host copy of every output region of the batch."""
+    torch.cuda.synchronize()
+    return {k: host(getattr(b, k)).copy() for k in
+            ("sorted_keys", "perm", "leaves", "counts", "node_keys", "child", "level_offsets", "results")}
+
+
+def check_against_oracle(b, sets, which=None):
+    res = b.set_results()
+    for s, ps in enumerate(sets):
+        if which is not None and s not in which:
+            continue
+        o = oracle.build_tree(ps.x, ps.y, ps.z, ps.box, ps.curve, ps.n_crit)
+        v = b.set_view(s, res[s])
+        tag = f"set {s} ({ps.kind} n={ps.n} curve={ps.curve} n_crit={ps.n_crit})"
+        assert v["status"] == "OK", (tag, v["status"])
+        eq(host(v["sorted_keys"]), o["P"], tag + " P")
+        eq(host(v["perm"]), o["perm"], tag + " perm")
+        eq(host(v["leaves"]), o["K"], tag + " leaves")
+        eq(host(v["counts"]), o["counts"], tag + " counts")
+        eq(host(v["node_keys"]), o["NK"], tag + " NK")
+        eq(host(v["child"]), o["CO"], tag + " CO")
+        eq(host(v["level_offsets"]), o["LO"], tag + " LO")
+        # from the root every round deepens the tree by one level, plus the final check
+        depth = int(inv.span_level(np.diff(o["K"])).max())
+        assert v["rounds"] == depth + 1, (tag, v["rounds"], depth)
+
+
+def test_batch_mixed_eager():
+    sets = mixed_sets()
+    say("batch mixed eager", [s.n for s in sets])
+    b = cs.Batch(specs(sets))
+    b.build(*coords(sets))
+    torch.cuda.synchronize()
+    check_against_oracle(b, sets)
+
+
+def test_batch_graph_replays_match_eager():
+    sets = mixed_sets()
+    b = cs.Batch(specs(sets))
+    x, y, z = coords(sets)
+    say("batch eager reference")
+    b.build(x, y, z)
+    ref = snapshot(b)
+    side = torch.cuda.Stream()
+    say("batch capture")
+    b.capture(x, y, z, side)
+    for rep in range(3):
+        for k in ("sorted_keys", "perm", "leaves", "counts", "node_keys", "child", "level_offsets", "results"):
+            getattr(b, k).fill_(-1)  # eager work between replays
+        torch.cuda.synchronize()
+        say("batch replay", rep)
+        b.launch(side)
+        side.synchronize()
+        got = snapshot(b)
+        res = ref["results"].reshape(-1, 4)
+        for s in range(len(sets)):
+            p0, p1 = b.particle_offsets[s], b.particle_offsets[s + 1]
+            l0, n0 = b.leaf_offsets[s], b.node_offsets[s]
+            nl, nn = int(res[s, 0]), int(res[s, 1])
+            tag = f"replay {rep} set {s}"
+            eq(got["sorted_keys"][p0:p1], ref["sorted_keys"][p0:p1], tag + " P")
+            eq(got["perm"][p0:p1], ref["perm"][p0:p1], tag + " perm")
+            eq(got["leaves"][l0:l0 + nl + 1], ref["leaves"][l0:l0 + nl + 1], tag + " leaves")
+            eq(got["counts"][l0:l0 + nl], ref["counts"][l0:l0 + nl], tag + " counts")
+            eq(got["node_keys"][n0:n0 + nn], ref["node_keys"][n0:n0 + nn], tag + " NK")
+            eq(got["child"][n0:n0 + nn], ref["child"][n0:n0 + nn], tag + " CO")
+        eq(got["level_offsets"], ref["level_offsets"], f"replay {rep} LO")
+        eq(got["results"], ref["results"], f"replay {rep} results")
+    check_against_oracle(b, sets)
+
+
+def test_batch_every_sort_shape_bit_exact():
+    sets = mixed_sets()
+    b = cs.Batch(specs(sets))
+    x, y, z = coords(sets)
+    for v in range(len(cs.sort_variants())):
+        say("batch sort shape", v, cs.sort_variants()[v])
+        b.set_variant(v)
+        for k in ("sorted_keys", "perm", "leaves", "node_keys"):
+            getattr(b, k).fill_(-1)
+        b.build(x, y, z)
+        torch.cuda.synchronize()
+        check_against_oracle(b, sets)
+
+
+def test_batch_autotune_keeps_results():
+    sets = mixed_sets()
+    b = cs.Batch(specs(sets))
+    x, y, z = coords(sets)
+    say("batch autotune")
+    ms = b.autotune(x, y, z, reps=1)
+    assert len(ms) == len(cs.sort_variants()) and all(t > 0 for t in ms)
+    assert b.sort_variant == int(np.argmin(ms))
+    b.build(x, y, z)
+    torch.cuda.synchronize()
+    check_against_oracle(b, sets)
+
+
+def test_batch_nonfinite_set_reported_alone():
+    sets = mixed_sets()
+    bad = 3
+    sets[bad].x[17] = np.inf
+    b = cs.Batch(specs(sets))
+    say("batch with a non-finite set")
+    b.build(*coords(sets))
+    torch.cuda.synchronize()
+    res = b.set_results()
+    assert cs.STATUS[int(res[bad, 3])] == "NONFINITE"
+    check_against_oracle(b, sets, which=[s for s in range(len(sets)) if s != bad])
+
+
+def test_batch_config4_full_size():
+    """512 sets, sizes log-uniform in [2^10, 2^20]: captured graph, every set's
+    structure checked, and a sample (every 8th set plus the largest) bit-exact
+    against the oracle."""
+    sets = wl.batched_sets()
+    say("config 4: 512 sets, total", sum(s.n for s in sets))
+    b = cs.Batch(specs(sets))
+    x, y, z = coords(sets)
+    side = torch.cuda.Stream()
+    b.capture(x, y, z, side)
+    b.launch(side)
+    side.synchronize()
+    res = b.set_results()
+    assert all(cs.STATUS[int(r)] == "OK" for r in res[:, 3])
+    P_all, perm_all = host(b.sorted_keys), host(b.perm)
+    leaves_all, counts_all = host(b.leaves), host(b.counts)
+    for s, ps in enumerate(sets):
+        p0, p1 = b.particle_offsets[s], b.particle_offsets[s + 1]
+        l0 = b.leaf_offsets[s]
+        nl = int(res[s, 0])
+        P = P_all[p0:p1]
+        K = leaves_all[l0:l0 + nl + 1]
+        assert np.all(P[1:] >= P[:-1]), s
+        perm = perm_all[p0:p1].astype(np.int64)
+        assert np.array_equal(np.sort(perm), np.arange(ps.n)), s
+        inv.check_cornerstone(K)
+        inv.check_balanced(P, K, ps.n_crit, counts_all[l0:l0 + nl])
+    sample = set(range(0, len(sets), 8)) | {int(np.argmax([s.n for s in sets]))}
+    say("oracle on", len(sample), "sets")
+    check_against_oracle(b, sets, which=sample)
