@@ -6,8 +6,9 @@ N_crit = 64, inputs resident in HBM.
 
 Prints one JSON line: particles/s over K timed builds, the HBM roofline of the
 dominant kernel (a radix-sort digit pass) from HIP events recorded around every
-pass during the timed builds, the byte-model fraction of the whole build, and
-the CPU oracle timed on a bounded sample of the same workload.
+pass during the timed builds, the byte-model fraction of the whole build, the
+batched-vs-plain ratio on 512 independent sets, and the CPU oracle timed on a
+bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -17,6 +18,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -78,6 +81,70 @@ def cpu_baseline(sample_n: int) -> dict:
                       f"uniform particles, Hilbert, N_crit 64 ({ref['K'].size - 1} leaves) in {dt:.2f} s"}
 
 
+def bench_batched(steps: int) -> dict:
+    """512 independent sets (sizes log-uniform in [2^10, 2^20], uniform or
+    Plummer, Morton or Hilbert, N_crit in {8..128}): one captured hipGraph
+    launch per step, against plain per-set cstone_build calls (each
+    synchronous, as a caller without batching would issue them). The sort shape
+    is autotuned and the graph captured before timing; both are excluded."""
+    import torch
+
+    import paper_2307_06345_amd as cs
+    import workloads as wl
+
+    sets = wl.batched_sets()
+    total = sum(p.n for p in sets)
+    x, y, z = (cs.from_numpy(np.concatenate([getattr(p, a) for p in sets]), "cuda") for a in "xyz")
+    b = cs.Batch([(p.n, p.box, p.curve, p.n_crit) for p in sets])
+    t0 = time.perf_counter()
+    tune_ms = b.autotune(x, y, z, reps=1)
+    side = torch.cuda.Stream()
+    b.capture(x, y, z, side)
+    setup_s = time.perf_counter() - t0
+    for _ in range(2):
+        b.launch(side)
+    side.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(steps):
+        e0.record(side)
+        b.launch(side)
+        e1.record(side)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    res = b.set_results()
+    ok = bool(all(int(r) == 0 for r in res[:, 3]))
+    t_batched = float(np.median(times))
+
+    # plain: every set alone through cstone_build, one after another
+    big = max(p.n for p in sets)
+    builder = cs.Builder(big, n_crit_min=min(p.n_crit for p in sets))
+    po = b.particle_offsets
+    views = [(x[po[i]:po[i + 1]], y[po[i]:po[i + 1]], z[po[i]:po[i + 1]]) for i in range(len(sets))]
+
+    def plain_pass():
+        for (vx, vy, vz), p in zip(views, sets):
+            builder.build(vx, vy, vz, p.box, p.curve, p.n_crit)
+        torch.cuda.synchronize()
+
+    plain_pass()  # warm-up
+    plain = []
+    for _ in range(max(1, min(steps, 3))):
+        t1 = time.perf_counter()
+        plain_pass()
+        plain.append((time.perf_counter() - t1) * 1e3)
+    t_plain = float(np.median(plain))
+    return {"workload": "512 independent sets, sizes floor(2^U), U ~ U[10, 20], uniform/Plummer, Morton/Hilbert, "
+                        "N_crit in {8,16,32,64,128}, seed 4",
+            "sets": len(sets), "particles": total, "all_sets_ok": ok,
+            "batched_ms": t_batched, "batched_ms_all": times,
+            "batched_particles_per_s": total / (t_batched * 1e-3),
+            "plain_ms": t_plain, "plain_particles_per_s": total / (t_plain * 1e-3),
+            "ratio": t_plain / t_batched,
+            "sort_variant": b.sort_variant, "sort_shapes": cs.sort_variants(), "autotune_ms": tune_ms,
+            "setup_s_excluded": setup_s, "max_rounds": int(res[:, 2].max())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +153,8 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 24)
     ap.add_argument("--cpu-sample", type=int, default=1 << 24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs the single-GPU octree build only; --gpus {args.gpus} is not supported "
@@ -167,6 +236,8 @@ def main():
                   "sort_pass_ms": passes, "model_bytes": model,
                   "model_fraction": model["total"] / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9)},
     }
+    if not args.no_batched:
+        out["batched"] = bench_batched(args.batch_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(min(args.cpu_sample, n))
         out["cpu_baseline"]["host_cpus"] = os.cpu_count()
