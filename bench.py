@@ -7,8 +7,9 @@ N_crit = 64, inputs resident in HBM.
 Prints one JSON line: particles/s over K timed builds, the HBM roofline of the
 dominant kernel (a radix-sort digit pass) from HIP events recorded around every
 pass during the timed builds, the byte-model fraction of the whole build, the
-batched-vs-plain ratio on 512 independent sets, and the CPU oracle timed on a
-bounded sample of the same workload.
+batched-vs-plain ratio on 512 independent sets, the latency of a continuous-
+batching serving run, and the CPU oracle timed on a bounded sample of the
+same workload.
 """
 from __future__ import annotations
 
@@ -145,6 +146,51 @@ def bench_batched(steps: int) -> dict:
             "setup_s_excluded": setup_s, "max_rounds": int(res[:, 2].max())}
 
 
+def bench_serving(count: int, rhos=(0.5, 0.7, 0.9)) -> dict:
+    """Continuous batching of `count` build requests (sizes floor(2^U), U ~
+    U[12, 22], uniform/Plummer, Hilbert, N_crit in {16, 64}) arriving as a
+    Poisson stream, HBM budget 64 GB, coordinates drawn on the device as each
+    group is launched. Capacity is measured first with every request of a
+    2000-request prefix available at once; the arrival rate is then
+    rho * capacity / E[N] for each rho."""
+    import torch
+
+    from paper_2307_06345_amd import serving as sv
+    import workloads as wl
+
+    specs = wl.serving_specs(count)
+    mean_n = float(np.mean([s[1] for s in specs]))
+
+    def run(reqs):
+        ex = sv.GpuExecutor(max_inflight=3)
+        loop = sv.ServingLoop(ex, budget_bytes=64 * 10**9, max_inflight=3)
+        done, st = loop.run(reqs)
+        torch.cuda.synchronize()
+        return done, st
+
+    run(sv.poisson_requests(specs[:200], rate_per_s=1e12))  # warm-up (allocator, code objects)
+    _, cal = run(sv.poisson_requests(specs[:min(count, 2000)], rate_per_s=1e12))
+    capacity = cal.particles_per_s
+    runs = {}
+    for rho in rhos:
+        rate = rho * capacity / mean_n
+        done, st = run(sv.poisson_requests(specs, rate_per_s=rate))
+        runs[str(rho)] = {"arrival_rate_per_s": rate, "particles_per_s": st.particles_per_s,
+                          "latency_p50_ms": st.latency_p50_ms, "latency_p99_ms": st.latency_p99_ms,
+                          "latency_mean_ms": st.latency_mean_ms, "makespan_s": st.makespan_s,
+                          "batches": st.batches, "mean_batch_requests": st.mean_batch_requests,
+                          "max_inflight": st.max_inflight, "peak_reserved_gb": st.peak_reserved_bytes / 1e9,
+                          "retries": st.retries, "statuses": st.statuses}
+    main_run = runs[str(0.7)] if str(0.7) in runs else next(iter(runs.values()))
+    return {"workload": f"{count} requests, sizes floor(2^U), U ~ U[12, 22], uniform/Plummer, Hilbert, "
+                        "N_crit in {16, 64}, Poisson arrivals, HBM budget 64 GB, seed 5",
+            "requests": count, "particles": int(sum(s[1] for s in specs)), "mean_n": mean_n,
+            "capacity_particles_per_s": capacity, "capacity_batches": cal.batches,
+            "rho": 0.7, "latency_p50_ms": main_run["latency_p50_ms"],
+            "latency_p99_ms": main_run["latency_p99_ms"], "particles_per_s": main_run["particles_per_s"],
+            "runs": runs}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -155,6 +201,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=10000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs the single-GPU octree build only; --gpus {args.gpus} is not supported "
@@ -238,6 +286,8 @@ def main():
     }
     if not args.no_batched:
         out["batched"] = bench_batched(args.batch_steps)
+    if not args.no_serving:
+        out["serving"] = bench_serving(args.serving_requests)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(min(args.cpu_sample, n))
         out["cpu_baseline"]["host_cpus"] = os.cpu_count()

@@ -282,6 +282,9 @@ CSTONE_API cstone_status cstone_batch_get_layout(const cstone_batch* plan, cston
 /* Sort shape of this plan (cstone_sort_variant_count() shapes); call
  * cstone_batch_upload again afterwards. */
 CSTONE_API cstone_status cstone_batch_set_variant(cstone_batch* plan, int variant);
+/* Rebalance rounds enqueued per build, 1 .. L + 1 = 22 (the default); a set
+ * whose tree needs more reports NOT_CONVERGED. Drops a captured graph. */
+CSTONE_API cstone_status cstone_batch_set_rounds(cstone_batch* plan, uint32_t rounds);
 /* Copy the plan's tables into the workspace (device, layout.workspace_bytes).
  * Synchronises `stream`; needed once before building with that workspace. */
 CSTONE_API cstone_status cstone_batch_upload(const cstone_batch* plan, void* ws, size_t ws_bytes, hipStream_t stream);

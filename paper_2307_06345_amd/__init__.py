@@ -94,6 +94,7 @@ def _load() -> ctypes.CDLL:
         "cstone_batch_destroy": (None, [P]),
         "cstone_batch_get_layout": (i32, [P, ctypes.POINTER(BatchLayout), P, P, P]),
         "cstone_batch_set_variant": (i32, [P, i32]),
+        "cstone_batch_set_rounds": (i32, [P, u32]),
         "cstone_batch_upload": (i32, [P, P, sz, P]),
         "cstone_batch_build": (i32, [P] + [P] * 11 + [P, sz, P]),
         "cstone_batch_capture": (i32, [P] + [P] * 11 + [P, sz, P]),
@@ -429,6 +430,12 @@ class Batch:
         _check(_lib.cstone_batch_set_variant(self._plan, int(variant)), "cstone_batch_set_variant")
         self._refresh_layout()
         self.upload(stream)
+
+    def set_rounds(self, rounds: int):
+        """Rebalance rounds enqueued per build (1..22; a set that needs more
+        reports NOT_CONVERGED)."""
+        _check(_lib.cstone_batch_set_rounds(self._plan, int(rounds)), "cstone_batch_set_rounds")
+        self._refresh_layout()
 
     def upload(self, stream=None):
         _check(_lib.cstone_batch_upload(self._plan, _ptr(self.ws), self.ws.numel(), _stream(stream)),

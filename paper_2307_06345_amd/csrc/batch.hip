@@ -264,6 +264,13 @@ CSTONE_API cstone_status cstone_batch_set_variant(cstone_batch* p, int variant) 
     return CSTONE_OK;
 }
 
+CSTONE_API cstone_status cstone_batch_set_rounds(cstone_batch* p, uint32_t rounds) {
+    if (!p || rounds < 1 || rounds > static_cast<uint32_t>(cs::kL + 1)) return CSTONE_ERR_INVALID_ARG;
+    if (rounds != p->rounds) cs::drop_graph(p);
+    p->rounds = rounds;
+    return CSTONE_OK;
+}
+
 CSTONE_API cstone_status cstone_batch_upload(const cstone_batch* p, void* ws, size_t ws_bytes, hipStream_t stream) {
     if (!p) return CSTONE_ERR_INVALID_ARG;
     const cs::BatchWs w = cs::carve_batch(*p, ws);

@@ -1,0 +1,135 @@
+"""GPU checks of the serving path: the device input generator (Philox
+known answers, determinism, a set drawn alone equals the same set drawn in a
+group), and continuous batching: every request's tree built in the mix of a
+serving run is bit-identical to the same request built alone (plain build and
+batch of one), and to the oracle on a sample."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+cs = pytest.importorskip("paper_2307_06345_amd")
+from paper_2307_06345_amd import serving as sv  # noqa: E402
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def host(t):
+    return cs.to_numpy(t)
+
+
+def eq(a, b, what):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    assert a.shape == b.shape, (what, a.shape, b.shape)
+    bad = np.nonzero(a != b)[0]
+    assert bad.size == 0, f"{what}: {bad.size} mismatches, first at {bad[:5]}"
+
+
+def test_device_philox_known_answers():
+    """Philox4x32-10 known-answer vectors (Salmon et al., SC'11 reference set)."""
+    say("philox KAT")
+    got = wl.device_philox(np.array([[0, 0, 0, 0]], dtype=np.uint32), (0, 0))
+    assert [hex(v) for v in got[0]] == ["0x6627e8d5", "0xe169c58d", "0xbc57ac4c", "0x9b00dbd8"]
+    got = wl.device_philox(np.array([[0xffffffff] * 4], dtype=np.uint32), (0xffffffff, 0xffffffff))
+    assert [hex(v) for v in got[0]] == ["0x408f276d", "0x41c83b0e", "0xa20bc7c6", "0x6d5451fd"]
+    got = wl.device_philox(np.array([[0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344]], dtype=np.uint32),
+                           (0xa4093822, 0x299f31d0))
+    assert [hex(v) for v in got[0]] == ["0xd16cfe09", "0x94fdcceb", "0x5001e420", "0x24126ea1"]
+
+
+def test_device_sets_are_keyed_per_set():
+    specs = [("uniform", 5000, 5, 11), ("plummer", 7001, 5, 12), ("uniform", 1, 5, 13), ("plummer", 40000, 5, 14)]
+    say("device generator", specs)
+    x, y, z, offs = wl.device_sets(specs)
+    torch.cuda.synchronize()
+    X, Y, Z = (host(t) for t in (x, y, z))
+    for k, spec in enumerate(specs):
+        a, b = offs[k], offs[k + 1]
+        xa, ya, za, oa = wl.device_sets([spec])  # the same set alone
+        eq(host(xa)[:spec[1]], X[a:b], f"set {k} x alone vs group")
+        eq(host(za)[:spec[1]], Z[a:b], f"set {k} z alone vs group")
+        if spec[0] == "uniform":
+            assert X[a:b].min() >= 0.0 and X[a:b].max() < 1.0
+        else:
+            r = np.sqrt(X[a:b] ** 2 + Y[a:b] ** 2 + Z[a:b] ** 2)
+            assert r.max() <= 20.0 + 1e-9
+            if spec[1] > 10000:  # Plummer half-mass radius (a = 1): (2^(2/3) - 1)^(-1/2) = 1.305
+                assert abs(np.median(r) - 1.305) < 0.05
+    x2, _, _, _ = wl.device_sets(specs)
+    eq(host(x2), X, "second draw")
+
+
+def _alone(rec, kind, n, n_crit):
+    box = sv.BOXES[kind]
+    x, y, z = (cs.from_numpy(rec[a], "cuda") for a in "xyz")
+    r = cs.build(x, y, z, box, cs.HILBERT, n_crit)
+    b = cs.Batch([(n, box, cs.HILBERT, n_crit)])
+    b.build(x, y, z)
+    torch.cuda.synchronize()
+    return r, b.set_view(0)
+
+
+def _serve(reqs, keep, reserve=None, **kw):
+    ex = sv.GpuExecutor(max_inflight=3, keep=keep, reserve=reserve)
+    loop = sv.ServingLoop(ex, **kw)
+    done, st = loop.run(reqs)
+    torch.cuda.synchronize()
+    return ex, done, st
+
+
+def test_serving_results_equal_alone():
+    specs = wl.serving_specs(count=160, seed=7, log2_min=12.0, log2_max=16.5)
+    reqs = sv.poisson_requests(specs, rate_per_s=20000.0)
+    keep = set(range(0, 160, 9))
+    say("serving 160 requests, kept", sorted(keep))
+    ex, done, st = _serve(reqs, keep)
+    assert len(done) == 160 and all(r.status == "OK" for r in done), st.statuses
+    assert st.batches < 160  # requests shared batches
+    say("batches", st.batches, "mean", st.mean_batch_requests, "max in flight", st.max_inflight)
+    for rid in sorted(keep):
+        r, rec = done[rid], ex.kept[rid]
+        xa, ya, za, _ = wl.device_sets([(r.kind, r.n, r.seed, r.stream)])
+        eq(host(xa)[:r.n], rec["x"], f"request {rid} coordinates")
+        plain, one = _alone(rec, r.kind, r.n, r.n_crit)
+        for name, a, b in (("sorted_keys", plain.sorted_keys, one["sorted_keys"]), ("perm", plain.perm, one["perm"]),
+                           ("leaves", plain.leaves, one["leaves"]), ("counts", plain.counts, one["counts"]),
+                           ("node_keys", plain.node_keys, one["node_keys"]), ("child", plain.child, one["child"]),
+                           ("level_offsets", plain.level_offsets, one["level_offsets"])):
+            eq(rec[name], host(a), f"request {rid} {name}: mix vs plain alone")
+            eq(rec[name], host(b), f"request {rid} {name}: mix vs batch of one")
+        assert r.n_leaves == plain.leaves.numel() - 1 and r.rounds == plain.rounds
+    for rid in sorted(keep)[:4]:
+        r, rec = done[rid], ex.kept[rid]
+        o = oracle.build_tree(rec["x"], rec["y"], rec["z"], sv.BOXES[r.kind], cs.HILBERT, r.n_crit)
+        eq(rec["leaves"], o["K"], f"request {rid} leaves vs oracle")
+        eq(rec["perm"], o["perm"], f"request {rid} perm vs oracle")
+        eq(rec["node_keys"], o["NK"], f"request {rid} NK vs oracle")
+
+
+def test_serving_retries_sets_over_their_reservation():
+    specs = wl.serving_specs(count=24, seed=8, log2_min=12.0, log2_max=14.0)
+    reqs = sv.poisson_requests(specs, rate_per_s=50000.0)
+    keep = set(range(24))
+    tiny = {2, 5, 11}  # first attempt with room for one leaf only
+
+    def reserve(r):
+        return 1 if (r.rid in tiny and not r.full) else sv.leaf_reservation(r.n, r.n_crit, r.full)
+
+    say("serving with forced capacity overflow", sorted(tiny))
+    ex, done, st = _serve(reqs, keep, reserve=reserve)
+    assert all(r.status == "OK" for r in done), st.statuses
+    assert st.retries >= len(tiny)
+    for rid in tiny:
+        assert done[rid].attempts == 2 and done[rid].full
+    for rid in sorted(keep)[:8] + sorted(tiny):
+        r, rec = done[rid], ex.kept[rid]
+        plain, _ = _alone(rec, r.kind, r.n, r.n_crit)
+        eq(rec["leaves"], host(plain.leaves), f"request {rid} leaves vs alone")
+        eq(rec["node_keys"], host(plain.node_keys), f"request {rid} NK vs alone")

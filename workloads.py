@@ -4,9 +4,12 @@ This module is shared by the tests, the benchmark, the oracle checks and the
 GPU path as the single source of input data. It holds none of the method's
 arithmetic (no keys, sorting or trees): it only draws particle coordinates.
 
-Every generator is deterministic in (seed, stream): numpy's Philox4x32-10
-counter-based bit generator keyed by the seed, with the stream number as the
-counter's starting block, so any set can be regenerated on its own.
+Every host generator is deterministic in (seed, stream): numpy's Philox
+(4x64, 10 rounds) counter-based bit generator keyed by the seed, with the
+stream number as the counter's starting block, so any set can be regenerated
+on its own. The device generator (workloads_gpu.hip, for workloads too large
+to draw on the host) uses Philox4x32-10 keyed by (seed, stream) with the same
+recipes; its sets are copied back to the host whenever an oracle checks them.
 
 Recipes (shapes of the workloads the octree build is measured on):
   * uniform cube: x, y, z i.i.d. uniform in [0, 1), each drawn as
@@ -18,10 +21,18 @@ Recipes (shapes of the workloads the octree build is measured on):
 """
 from __future__ import annotations
 
+import ctypes
 import math
+import os
+import subprocess
 from dataclasses import dataclass
 
 import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+GPU_SRC = os.path.join(_HERE, "workloads_gpu.hip")
+GPU_LIB = os.path.join(_HERE, "libworkloads_gpu.so")
+KINDS = {"uniform": 0, "plummer": 1}
 
 UNIT_BOX = ((0.0, 0.0, 0.0), (1.0, 1.0, 1.0))
 PLUMMER_RT = 20.0
@@ -155,3 +166,80 @@ def serving_specs(count: int = 10000, seed: int = 5, log2_min: float = 12.0, log
     gaps = g.exponential(1.0, count)
     return [("plummer" if kinds[s] else "uniform", int(2.0 ** U[s]), int(ncrits[s]), s + 1, float(gaps[s]))
             for s in range(count)]
+
+
+# ---- device generator --------------------------------------------------------------
+
+def build_gpu_generator() -> str:
+    """Compile workloads_gpu.hip for gfx950 into libworkloads_gpu.so."""
+    cmd = ["hipcc", "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared", "-ffp-contract=off",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-fvisibility=hidden",
+           GPU_SRC, "-o", GPU_LIB]
+    subprocess.run(cmd, check=True)
+    return GPU_LIB
+
+
+_gpu = None
+
+
+def _gpu_lib():
+    global _gpu
+    if _gpu is None:
+        if not os.path.exists(GPU_LIB):
+            raise ImportError(f"{GPU_LIB} is missing: run workloads.build_gpu_generator()")
+        lib = ctypes.CDLL(GPU_LIB)
+        P = ctypes.c_void_p
+        lib.wl_generate.restype = ctypes.c_int
+        lib.wl_generate.argtypes = [P, P, P, P, P, ctypes.c_uint32, P, P, P, P]
+        lib.wl_philox.restype = ctypes.c_int
+        lib.wl_philox.argtypes = [P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, P, P]
+        _gpu = lib
+    return _gpu
+
+
+def device_generate(sets, x, y, z, stream=None, base: int = 0):
+    """Draw sets [(kind, n, seed, stream), ...] back to back into the float64
+    device tensors x, y, z starting at element `base`; returns the offsets
+    (n_sets + 1, relative to base). Asynchronous on `stream`."""
+    import torch
+
+    k = len(sets)
+    counts = np.array([int(s[1]) for s in sets], dtype=np.uint64)
+    offs = np.zeros(k + 1, dtype=np.uint64)
+    np.cumsum(counts, out=offs[1:])
+    assert x.numel() >= base + int(offs[-1]) and x.dtype == torch.float64
+    kinds = np.array([KINDS[s[0]] for s in sets], dtype=np.uint32)
+    seeds = np.array([int(s[2]) for s in sets], dtype=np.uint32)
+    streams = np.array([int(s[3]) for s in sets], dtype=np.uint32)
+    o = offs[:-1] + np.uint64(base)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    rc = _gpu_lib().wl_generate(o.ctypes.data, counts.ctypes.data, kinds.ctypes.data, seeds.ctypes.data,
+                                streams.ctypes.data, k, x.data_ptr(), y.data_ptr(), z.data_ptr(), st.cuda_stream)
+    if rc != 0:
+        raise RuntimeError("wl_generate failed")
+    return offs.astype(np.int64)
+
+
+def device_sets(sets, device="cuda"):
+    """Allocate and draw sets [(kind, n, seed, stream), ...] on the device:
+    (x, y, z, offsets)."""
+    import torch
+
+    total = sum(int(s[1]) for s in sets)
+    x, y, z = (torch.empty(max(total, 1), dtype=torch.float64, device=device) for _ in range(3))
+    offs = device_generate(sets, x, y, z)
+    return x, y, z, offs
+
+
+def device_philox(counters: np.ndarray, key: tuple, device="cuda") -> np.ndarray:
+    """Philox4x32-10 of (n, 4) uint32 counters under a 2-word key, on the device."""
+    import torch
+
+    c = np.ascontiguousarray(counters, dtype=np.uint32).reshape(-1, 4)
+    ct = torch.from_numpy(c.view(np.int32)).to(device)
+    out = torch.empty_like(ct)
+    rc = _gpu_lib().wl_philox(ct.data_ptr(), c.shape[0], int(key[0]), int(key[1]), out.data_ptr(),
+                              torch.cuda.current_stream().cuda_stream)
+    if rc != 0:
+        raise RuntimeError("wl_philox failed")
+    return out.cpu().numpy().view(np.uint32)
