@@ -191,6 +191,8 @@ def _gpu_lib():
         P = ctypes.c_void_p
         lib.wl_generate.restype = ctypes.c_int
         lib.wl_generate.argtypes = [P, P, P, P, P, ctypes.c_uint32, P, P, P, P]
+        lib.wl_displace.restype = ctypes.c_int
+        lib.wl_displace.argtypes = [P, P, P, ctypes.c_uint64, ctypes.c_double, ctypes.c_uint32, ctypes.c_uint32, P]
         lib.wl_philox.restype = ctypes.c_int
         lib.wl_philox.argtypes = [P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, P, P]
         _gpu = lib
@@ -229,6 +231,18 @@ def device_sets(sets, device="cuda"):
     x, y, z = (torch.empty(max(total, 1), dtype=torch.float64, device=device) for _ in range(3))
     offs = device_generate(sets, x, y, z)
     return x, y, z, offs
+
+
+def device_displace(x, y, z, sigma: float, seed: int, stream: int):
+    """Move every particle of the float64 device tensors by N(0, sigma^2) per
+    coordinate, in place (keyed by seed and stream; asynchronous)."""
+    import torch
+
+    n = x.numel()
+    rc = _gpu_lib().wl_displace(x.data_ptr(), y.data_ptr(), z.data_ptr(), n, float(sigma), int(seed), int(stream),
+                                torch.cuda.current_stream().cuda_stream)
+    if rc != 0:
+        raise RuntimeError("wl_displace failed")
 
 
 def device_philox(counters: np.ndarray, key: tuple, device="cuda") -> np.ndarray:

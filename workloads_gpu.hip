@@ -104,6 +104,28 @@ __global__ __launch_bounds__(256) void generate_kernel(Sets sets, uint64_t total
     }
 }
 
+// Cumulative Gaussian displacement: every coordinate moves by sigma * N(0, 1),
+// the normals drawn by the Box-Muller transform from two Philox blocks
+// (counter (i, 2) and (i, 3)) under key (seed, stream).
+__global__ __launch_bounds__(256) void displace_kernel(uint64_t n, double sigma, uint32_t seed, uint32_t stream,
+                                                       double* __restrict__ x, double* __restrict__ y,
+                                                       double* __restrict__ z) {
+    const uint64_t step = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += step) {
+        const uint32_t ilo = static_cast<uint32_t>(i), ihi = static_cast<uint32_t>(i >> 32);
+        const uint4 a = philox4x32_10(make_uint4(ilo, ihi, 2u, 0u), seed, stream);
+        const uint4 b = philox4x32_10(make_uint4(ilo, ihi, 3u, 0u), seed, stream);
+        // 1 - u lies in (0, 1], so the logarithm is finite
+        const double r0 = sqrt(-2.0 * log(1.0 - unit(a.x, a.y)));
+        const double t0 = 2.0 * M_PI * unit(a.z, a.w);
+        const double r1 = sqrt(-2.0 * log(1.0 - unit(b.x, b.y)));
+        const double t1 = 2.0 * M_PI * unit(b.z, b.w);
+        x[i] += sigma * (r0 * cos(t0));
+        y[i] += sigma * (r0 * sin(t0));
+        z[i] += sigma * (r1 * cos(t1));
+    }
+}
+
 // Philox4x32-10 blocks for known-answer checks: out[4 i ..] = philox(ctr[4 i ..], key).
 __global__ void philox_kernel(const uint32_t* ctr, uint32_t n, uint32_t k0, uint32_t k1, uint32_t* out) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -142,6 +164,18 @@ WL_API int wl_generate(const uint64_t* offsets, const uint64_t* counts, const ui
         if (hipGetLastError() != hipSuccess) return 1;
     }
     return 0;
+}
+
+// Move n particles (device x, y, z) by independent N(0, sigma^2) offsets keyed by (seed, stream).
+WL_API int wl_displace(double* x, double* y, double* z, uint64_t n, double sigma, uint32_t seed, uint32_t stream,
+                       hipStream_t hs) {
+    if (n == 0) return 0;
+    if (!x || !y || !z) return 1;
+    uint64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(displace_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, hs, n, sigma, seed, stream,
+                       x, y, z);
+    return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 
 WL_API int wl_philox(const uint32_t* ctr_dev, uint32_t n, uint32_t k0, uint32_t k1, uint32_t* out_dev,
