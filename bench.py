@@ -7,8 +7,9 @@ N_crit = 64, inputs resident in HBM.
 Prints one JSON line: particles/s over K timed builds, the HBM roofline of the
 dominant kernel (a radix-sort digit pass) from HIP events recorded around every
 pass during the timed builds, the byte-model fraction of the whole build, the
-batched-vs-plain ratio on 512 independent sets, the latency of a continuous-
-batching serving run, and the CPU oracle timed on a bounded sample of the
+batched-vs-plain ratio on 512 independent sets, the 2^27 Plummer build with
+its incremental rebuilds, the latency of a continuous-batching serving run,
+and the CPU oracle timed on a bounded sample of the
 same workload.
 """
 from __future__ import annotations
@@ -191,6 +192,46 @@ def bench_serving(count: int, rhos=(0.5, 0.7, 0.9)) -> dict:
             "runs": runs}
 
 
+def bench_plummer(reps: int = 3, rebuilds: int = 10) -> dict:
+    """2^27 Plummer particles (a = 1, r_t = 20), Hilbert, N_crit 16: build from
+    the root (median of `reps`), then `rebuilds` incremental rebuilds from the
+    previous leaves after cumulative N(0, 1e-3^2) displacements (each timed;
+    the displacement itself is outside the timed region)."""
+    import torch
+
+    import paper_2307_06345_amd as cs
+    import workloads as wl
+
+    n, n_crit = 1 << 27, 16
+    x, y, z, _ = wl.device_sets([("plummer", n, 3, 0)])
+    b = cs.Builder(n, n_crit, leaf_capacity=8 * n // (n_crit + 1) + 64)
+    b.build(x, y, z, wl.PLUMMER_BOX, wl.HILBERT, n_crit)  # warm-up
+    torch.cuda.synchronize()
+    root_ms = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        r = b.build(x, y, z, wl.PLUMMER_BOX, wl.HILBERT, n_crit)
+        torch.cuda.synchronize()
+        root_ms.append((time.perf_counter() - t0) * 1e3)
+    leaves, rounds = r.leaves.numel() - 1, r.rounds
+    reb_ms, reb_rounds = [], []
+    for k in range(1, rebuilds + 1):
+        wl.device_displace(x, y, z, 1e-3, 3, k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = b.build(x, y, z, wl.PLUMMER_BOX, wl.HILBERT, n_crit, incremental=True)
+        torch.cuda.synchronize()
+        reb_ms.append((time.perf_counter() - t0) * 1e3)
+        reb_rounds.append(r.rounds)
+    t_root = float(np.median(root_ms))
+    return {"workload": "2^27 Plummer particles (a = 1, r_t = 20, box [-20, 20]^3), Hilbert, N_crit 16; "
+                        "then 10 incremental rebuilds after cumulative N(0, 1e-3^2) displacements",
+            "n": n, "leaves": leaves, "rounds_from_root": rounds,
+            "from_root_ms": t_root, "from_root_particles_per_s": n / (t_root * 1e-3),
+            "rebuild_ms": reb_ms, "rebuild_rounds": reb_rounds,
+            "rebuild_particles_per_s": n / (float(np.mean(reb_ms)) * 1e-3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -202,6 +243,10 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-plummer", action="store_true")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="also copy 24 N bytes device to device once (the same bytes as a digit pass), "
+                         "to scale hardware traffic counters")
     ap.add_argument("--serving-requests", type=int, default=10000)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -232,6 +277,14 @@ def main():
         passes = list(r.sort_pass_ms) if passes is None else [a + v for a, v in zip(passes, r.sort_pass_ms)]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+
+    if args.calibration_copy:
+        src = torch.empty(24 * s.n, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     n = s.n
     ms_per_step = dt * 1e3 / args.steps
@@ -286,6 +339,8 @@ def main():
     }
     if not args.no_batched:
         out["batched"] = bench_batched(args.batch_steps)
+    if not args.no_plummer:
+        out["plummer_2_27"] = bench_plummer()
     if not args.no_serving:
         out["serving"] = bench_serving(args.serving_requests)
     if not args.no_cpu_baseline:
