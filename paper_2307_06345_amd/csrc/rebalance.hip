@@ -85,6 +85,16 @@ __global__ __launch_bounds__(256) void loop_init_kernel(LoopState* st, uint64_t 
 }
 
 // ---- one round: g1 + g2 + g3 -------------------------------------------------
+//
+// A tile is kRTile consecutive leaves. Their keys and positions, with kRHalo
+// entries on either side (K_{i+1} and the 8-sibling checks reach up to 8
+// entries away), are first read into LDS with coalesced loads; each thread
+// then decides its kRItems consecutive leaves from LDS. When the tile's new
+// entries fit in the same LDS (no split-heavy tile), they are assembled there
+// and stored with coalesced writes; otherwise every thread writes its own.
+
+constexpr int kRHalo = 8;
+constexpr int kRSpan = kRTile + 2 * kRHalo;
 
 __global__ __launch_bounds__(kRBlock) void round_kernel(uint32_t n, uint32_t n_crit, const uint64_t* __restrict__ K,
                                                          const uint32_t* __restrict__ pos,
@@ -96,6 +106,8 @@ __global__ __launch_bounds__(kRBlock) void round_kernel(uint32_t n, uint32_t n_c
     __shared__ uint64_t tile_prefix;
     __shared__ uint32_t split_base;
     __shared__ uint32_t any_change;
+    __shared__ uint64_t sK[kRSpan];  // K[base - kRHalo ...], then the tile's new entries
+    __shared__ uint32_t sP[kRSpan];
 
     if (round > 0 && st->changed[round - 1] == 0) return;  // converged in an earlier round
     const uint64_t nl = st->nl[round];
@@ -108,28 +120,44 @@ __global__ __launch_bounds__(kRBlock) void round_kernel(uint32_t n, uint32_t n_c
     for (;;) {
         const uint32_t tile = take_tile(&st->counters[round], &slot);
         if (tile >= tiles) break;
-        const uint64_t first = static_cast<uint64_t>(tile) * kRTile + static_cast<uint64_t>(tid) * kRItems;
+        const int64_t base = static_cast<int64_t>(tile) * kRTile;
+        for (int j = tid; j < kRSpan; j += kRBlock) {  // K and positions of entries base-8 .. base+2055
+            const int64_t g = base - kRHalo + j;
+            if (g >= 0 && g <= static_cast<int64_t>(nl)) {
+                sK[j] = K[g];
+                sP[j] = pos[g];
+            }
+        }
+        __syncthreads();
+        const uint32_t lfirst = tid * kRItems;  // first leaf of this thread, relative to base
+        const uint64_t first = static_cast<uint64_t>(base) + lfirst;
 
         // g1: decision O_i for this thread's leaves
         uint32_t op[kRItems];
+        uint64_t kk[kRItems + 1];
+        uint32_t pp[kRItems];
         uint32_t osum = 0, nsplit = 0;
         bool changed = false;
 #pragma unroll
+        for (int j = 0; j <= kRItems; ++j) kk[j] = sK[kRHalo + lfirst + j];
+#pragma unroll
         for (int j = 0; j < kRItems; ++j) {
             const uint64_t i = first + j;
+            const int li = kRHalo + static_cast<int>(lfirst) + j;
             uint32_t o = 0;
+            pp[j] = sP[li];
             if (i < nl) {
-                const uint64_t ki = K[i];
-                const uint64_t delta = K[i + 1] - ki;
-                const uint32_t cnt = pos[i + 1] - pos[i];
+                const uint64_t ki = kk[j];
+                const uint64_t delta = kk[j + 1] - ki;
+                const uint32_t cnt = sP[li + 1] - pp[j];
                 o = 1;
                 if (cnt > n_crit && delta > 1) {
                     o = 8;  // subdivide
                 } else if (delta < kKeyEnd) {  // the root never merges
                     // place among its siblings, (K_i mod 8 delta) / delta; delta is a power of 8
                     const uint64_t js = (ki >> (63 - clz64(delta))) & 7u;
-                    if (js >= 1 && i >= js && i - js + 8 <= nl && K[i - js] + 8 * delta == K[i - js + 8] &&
-                        pos[i - js + 8] - pos[i - js] <= n_crit)
+                    if (js >= 1 && i >= js && i - js + 8 <= nl && sK[li - js] + 8 * delta == sK[li - js + 8] &&
+                        sP[li - js + 8] - sP[li - js] <= n_crit)
                         o = 0;  // 8 sibling leaves with at most n_crit particles: merge
                 }
                 changed |= (o != 1);
@@ -156,42 +184,62 @@ __global__ __launch_bounds__(kRBlock) void round_kernel(uint32_t n, uint32_t n_c
             }
             if (tid == 0) {
                 tile_prefix = prefix;
-                const uint32_t s = static_cast<uint32_t>(block_total >> 32);
-                split_base = s ? atomicAdd(&st->nsplit[round], s) : 0u;
+                const uint32_t sc = static_cast<uint32_t>(block_total >> 32);
+                split_base = sc ? atomicAdd(&st->nsplit[round], sc) : 0u;
             }
         }
         if (changed) any_change = 1;
         __syncthreads();
         const uint64_t tp = tile_prefix;
+        const uint32_t out_total = static_cast<uint32_t>(block_total);  // new entries of this tile
+        const bool staged = out_total <= static_cast<uint32_t>(kRSpan);  // block-uniform
 
         // g3: K' (Eqs. rebalancecopy / rebalancesplit) and the known positions of K'
-        uint64_t o_prime = tp + (excl & 0xffffffffull);
+        uint32_t lo = static_cast<uint32_t>(excl);  // this thread's first new entry, relative to tp
         uint32_t s_at = split_base + static_cast<uint32_t>(excl >> 32);
 #pragma unroll
         for (int j = 0; j < kRItems; ++j) {
             const uint64_t i = first + j;
             if (i < nl) {
-                const uint64_t ki = K[i];
+                const uint64_t ki = kk[j];
+                const uint64_t o_prime = tp + lo;
                 if (op[j] == 1) {
-                    if (o_prime <= capacity) {
+                    if (staged) {
+                        sK[lo] = ki;
+                        sP[lo] = pp[j];
+                    } else if (o_prime <= capacity) {
                         K_out[o_prime] = ki;
-                        pos_out[o_prime] = pos[i];
+                        pos_out[o_prime] = pp[j];
                     }
                 } else if (op[j] == 8) {
-                    if (o_prime + 7 <= capacity) {
-                        const uint64_t child = (K[i + 1] - ki) >> 3;
+                    const uint64_t child = (kk[j + 1] - ki) >> 3;
+                    if (staged) {
+#pragma unroll
+                        for (int c = 0; c < 8; ++c) sK[lo + c] = ki + c * child;
+                        sP[lo] = pp[j];  // the other 7 come from the split search
+                    } else if (o_prime + 7 <= capacity) {
 #pragma unroll
                         for (int c = 0; c < 8; ++c) K_out[o_prime + c] = ki + c * child;
-                        pos_out[o_prime] = pos[i];
-                        if (s_at < split_capacity) splits[s_at] = i | (o_prime << 32);
+                        pos_out[o_prime] = pp[j];
                     }
+                    if (o_prime + 7 <= capacity && s_at < split_capacity) splits[s_at] = i | (o_prime << 32);
                     ++s_at;
                 }
             }
-            o_prime += op[j];
+            lo += op[j];
+        }
+        if (staged) {  // the g3 writes above went to LDS (sK / sP were free after g1)
+            __syncthreads();
+            for (uint32_t j = tid; j < out_total; j += kRBlock) {
+                if (tp + j <= capacity) {
+                    K_out[tp + j] = sK[j];
+                    pos_out[tp + j] = sP[j];  // split children 1..7 are overwritten by the split search
+                }
+            }
         }
         // the owner of the last leaf closes K' with 8^L
         if (first < nl && nl <= first + kRItems) {
+            const uint64_t o_prime = tp + lo;
             st->nl[round + 1] = o_prime;
             if (o_prime <= capacity) {
                 K_out[o_prime] = kKeyEnd;
@@ -325,6 +373,9 @@ uint32_t clamp_grid(size_t blocks) {
     return static_cast<uint32_t>(std::max<size_t>(1, std::min<size_t>(blocks, kMaxGrid)));
 }
 
+// one wave per search while searches are few
+uint32_t search_grid(size_t searches) { return clamp_grid(grid_1d(searches, kSearchBlock / kWave)); }
+
 }  // namespace
 
 cstone_status launch_node_counts(const uint64_t* sorted_keys, size_t n, const uint64_t* leaves, size_t n_leaves,
@@ -394,7 +445,7 @@ cstone_status RebalanceLoop::enqueue(uint32_t rounds) {
                            static_cast<uint64_t>(cap_), w.lb);
         // one wave per search while searches are few
         const size_t searches = 7 * std::min<size_t>(rows, w.split_capacity);
-        hipLaunchKernelGGL(split_search_kernel, dim3(clamp_grid(grid_1d(searches, kSearchBlock / kWave))),
+        hipLaunchKernelGGL(split_search_kernel, dim3(search_grid(searches)),
                            dim3(kSearchBlock), 0, stream_, P_, bufK[q & 1], w.pos[q & 1], w.pos[(q + 1) & 1],
                            w.splits, w.split_capacity, w.st, static_cast<int>(q), static_cast<uint64_t>(cap_));
     }
@@ -755,7 +806,7 @@ cstone_status launch_batch_rebalance(const uint64_t* P, const BatchSet* sets, ui
                            sets, w.K[a], w.pos[a], w.sid[a], w.K[b], w.pos[b], w.sid[b], w.starts[b], n_sets,
                            w.changed_set + static_cast<size_t>(q) * n_sets, w.splits, cap_u, w.st,
                            static_cast<int>(q), static_cast<uint64_t>(C), w.lb);
-        hipLaunchKernelGGL(split_search_kernel, dim3(clamp_grid(grid_1d(7 * split_capacity, kSearchBlock / kWave))),
+        hipLaunchKernelGGL(split_search_kernel, dim3(search_grid(7 * split_capacity)),
                            dim3(kSearchBlock), 0, stream, P, w.K[a], w.pos[a], w.pos[b], w.splits, cap_u, w.st,
                            static_cast<int>(q), static_cast<uint64_t>(C));
     }
