@@ -15,8 +15,6 @@ from __future__ import annotations
 
 import ctypes
 import os
-from dataclasses import dataclass
-
 import numpy as np
 import torch
 
@@ -262,18 +260,48 @@ def link_octree(leaves, node_keys=None, child=None, level_offsets=None, ws=None,
 
 # ---- whole build with preallocated buffers ----------------------------------------
 
-@dataclass
 class BuildResult:
-    sorted_keys: torch.Tensor
-    perm: torch.Tensor
-    leaves: torch.Tensor
-    counts: torch.Tensor
-    node_keys: torch.Tensor | None
-    child: torch.Tensor | None
-    level_offsets: torch.Tensor | None
-    rounds: int
-    stage_ms: tuple      # keys, sort, rebalance, link (timed builds only)
-    sort_pass_ms: tuple  # every digit pass of the particle sort (timed builds only)
+    """Outputs of one build: views into the Builder's buffers (valid until its
+    next build). The views are made on first access, so a caller that only
+    needs some of them pays for none of the others."""
+
+    __slots__ = ("_b", "n", "n_leaves", "rounds", "stage_ms", "sort_pass_ms")
+
+    def __init__(self, builder, n, n_leaves, rounds, stage_ms=(), sort_pass_ms=()):
+        self._b = builder
+        self.n = n
+        self.n_leaves = n_leaves
+        self.rounds = rounds
+        self.stage_ms = stage_ms          # keys, sort, rebalance, link (timed builds only)
+        self.sort_pass_ms = sort_pass_ms  # every digit pass of the particle sort (timed builds only)
+
+    @property
+    def sorted_keys(self):
+        return self._b.sorted_keys[: self.n]
+
+    @property
+    def perm(self):
+        return self._b.perm[: self.n]
+
+    @property
+    def leaves(self):
+        return self._b.leaves[: self.n_leaves + 1]
+
+    @property
+    def counts(self):
+        return self._b.counts[: self.n_leaves]
+
+    @property
+    def node_keys(self):
+        return self._b.node_keys[: node_count(self.n_leaves)] if self._b.link else None
+
+    @property
+    def child(self):
+        return self._b.child[: node_count(self.n_leaves)] if self._b.link else None
+
+    @property
+    def level_offsets(self):
+        return self._b.level_offsets if self._b.link else None
 
 
 class Builder:
@@ -298,6 +326,13 @@ class Builder:
         self.level_offsets = torch.empty(LEVEL_OFFSETS, dtype=torch.int32, device=dev) if link else None
         self.ws = _workspace(_lib.cstone_build_workspace_bytes(self.n_max, self.capacity), dev)
         self.n_leaves = 0
+        # pointers of the fixed buffers, marshalled once
+        self._out = (_ptr(self.sorted_keys), _ptr(self.perm), _ptr(self.leaves))
+        self._out2 = (_ptr(self.counts), _ptr(self.node_keys), _ptr(self.child), _ptr(self.level_offsets))
+        self._ws = (_ptr(self.ws), self.ws.numel())
+        self._boxes = {}
+        self._nl = ctypes.c_size_t(0)
+        self._rounds = ctypes.c_uint32(0)
 
     def build(self, x, y, z, box, curve, n_crit: int, incremental: bool = False, max_iters: int = 0,
               timed: bool = False, stream=None) -> BuildResult:
@@ -305,25 +340,22 @@ class Builder:
         assert n <= self.n_max
         for t in (x, y, z):
             _dev(t, torch.float64)
-        nl = ctypes.c_size_t(self.n_leaves if incremental else 0)
-        rounds = ctypes.c_uint32(0)
-        tm = Timings()
-        b = Box.of(box)
-        st = _lib.cstone_build(_ptr(x), _ptr(y), _ptr(z), n, ctypes.byref(b), int(curve), int(n_crit),
-                               _ptr(self.sorted_keys), _ptr(self.perm), _ptr(self.leaves), ctypes.byref(nl),
-                               self.capacity, _ptr(self.counts), _ptr(self.node_keys), _ptr(self.child),
-                               _ptr(self.level_offsets), int(max_iters), ctypes.byref(rounds), _ptr(self.ws),
-                               self.ws.numel(), ctypes.byref(tm) if timed else None, _stream(stream))
+        key = (tuple(box[0]), tuple(box[1]))
+        b = self._boxes.get(key)
+        if b is None:
+            b = self._boxes[key] = Box.of(box)
+        self._nl.value = self.n_leaves if incremental else 0
+        tm = Timings() if timed else None
+        st = _lib.cstone_build(x.data_ptr(), y.data_ptr(), z.data_ptr(), n, ctypes.byref(b), int(curve), int(n_crit),
+                               *self._out, ctypes.byref(self._nl), self.capacity, *self._out2, int(max_iters),
+                               ctypes.byref(self._rounds), *self._ws, ctypes.byref(tm) if timed else None,
+                               _stream(stream))
         if st != 0:
             err = CstoneError(st, "cstone_build")
-            err.n_leaves = nl.value
+            err.n_leaves = self._nl.value
             raise err
-        self.n_leaves = nl.value
-        nlv = nl.value
-        nn = node_count(nlv)
-        return BuildResult(self.sorted_keys[:n], self.perm[:n], self.leaves[: nlv + 1], self.counts[:nlv],
-                           self.node_keys[:nn] if self.link else None, self.child[:nn] if self.link else None,
-                           self.level_offsets if self.link else None, int(rounds.value),
+        self.n_leaves = self._nl.value
+        return BuildResult(self, n, self._nl.value, int(self._rounds.value),
                            tuple(tm.stage_ms) if timed else (),
                            tuple(tm.sort_pass_ms[: tm.sort_passes]) if timed else ())
 

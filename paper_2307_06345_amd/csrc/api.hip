@@ -152,9 +152,13 @@ cstone_status cstone_build(const double* x, const double* y, const double* z, si
     size_t nl = *n_leaves;
     do {
         if (mark(0) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
-        hipLaunchKernelGGL(clear_word_kernel, dim3(1), dim3(1), 0, stream, flag);
-        // the key kernel counts the sort's first digit as it writes the keys
-        if (n && (s = sort_prepare(stage_ws, n, true, stream)) != CSTONE_OK) break;
+        // the key kernel counts the sort's first digit as it writes the keys;
+        // the sort's set-up launch also clears the non-finite flag
+        if (n) {
+            if ((s = sort_prepare(stage_ws, n, true, stream, flag)) != CSTONE_OK) break;
+        } else {
+            hipLaunchKernelGGL(clear_word_kernel, dim3(1), dim3(1), 0, stream, flag);
+        }
         uint32_t hist_mask = 0;
         uint32_t* hist0 = n ? sort_first_histogram(stage_ws, n, true, &hist_mask) : nullptr;
         s = launch_keys(x, y, z, n, *box, curve, keys, flag, stream, hist0, hist_mask);

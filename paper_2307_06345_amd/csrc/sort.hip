@@ -26,12 +26,15 @@ constexpr int kHistBlock = 256;
 constexpr int kMinTile = 2048;  // smallest tile of any variant (sizes the look-back rows)
 
 __global__ __launch_bounds__(256) void sort_init_kernel(uint32_t* ghist, size_t ghist_words, uint32_t* err,
-                                                        uint64_t* lb, size_t lb_words) {
+                                                        uint64_t* lb, size_t lb_words, uint32_t* extra) {
     const size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
     for (size_t i = t; i < lb_words; i += stride) lb[i] = 0;  // flag 0: not yet written
     for (size_t i = t; i < ghist_words; i += stride) ghist[i] = 0;
-    if (t == 0) *err = 0;
+    if (t == 0) {
+        *err = 0;
+        if (extra) *extra = 0;  // a caller's word cleared along the way
+    }
 }
 
 // Counts of the lowest digit (mask = radix - 1).
@@ -142,11 +145,12 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid) {
 // One tile of a pass: `base` .. `base + count` of the keys, in the segment
 // whose first tile is `first` and whose particles start at `seg_base`
 // (segment-relative permutation values; the plain sort is one segment).
-// Minimum waves per SIMD (the second launch bound): room for two blocks of up
-// to 512 threads per CU (4 SIMDs), so that one block's waits overlap the
-// other's work; a block's LDS stays below half of the CU's 160 KB.
-template <int BLOCK>
-constexpr int kMinBlocks = BLOCK <= 512 ? 2 * BLOCK / (4 * kWave) : BLOCK / (4 * kWave);
+// Minimum waves per SIMD (the second launch bound): room for two blocks per
+// CU (4 SIMDs) when a block's LDS (mostly the 8-byte keys of its tile) stays
+// below half of the CU's 160 KB, so that one block's waits overlap the other's
+// work; otherwise one block, which may then use up to 256 VGPRs a lane.
+template <int BLOCK, int ITEMS>
+constexpr int kMinBlocks = (BLOCK <= 512 && BLOCK * ITEMS * 8 <= 72 * 1024 ? 2 : 1) * BLOCK / (4 * kWave);
 
 struct TileDesc {
     uint32_t tile, base, count, first, seg_base;
@@ -289,7 +293,7 @@ __device__ __forceinline__ void onesweep_tile(const TileDesc td, const uint64_t*
 }
 
 template <int BITS, int BLOCK, int ITEMS, int WIN, bool FIRST, bool WITH_VALUES, class LB>
-__global__ __launch_bounds__(BLOCK, kMinBlocks<BLOCK>) void onesweep_kernel(const uint64_t* __restrict__ keys_in,
+__global__ __launch_bounds__(BLOCK, (kMinBlocks<BLOCK, ITEMS>)) void onesweep_kernel(const uint64_t* __restrict__ keys_in,
                                                           const uint32_t* __restrict__ vals_in,
                                                           uint64_t* __restrict__ keys_out,
                                                           uint32_t* __restrict__ vals_out, uint32_t n, uint32_t shift,
@@ -331,7 +335,7 @@ __global__ __launch_bounds__(BLOCK, kMinBlocks<BLOCK>) void onesweep_kernel(cons
 // set has its own digit histograms (ghist + set * hist_stride) and its own
 // look-back chain, and its permutation values count from the set's start.
 template <int BITS, int BLOCK, int ITEMS, int WIN, bool FIRST, bool WITH_VALUES, class LB>
-__global__ __launch_bounds__(BLOCK, kMinBlocks<BLOCK>) void onesweep_seg_kernel(const uint64_t* __restrict__ keys_in,
+__global__ __launch_bounds__(BLOCK, (kMinBlocks<BLOCK, ITEMS>)) void onesweep_seg_kernel(const uint64_t* __restrict__ keys_in,
                                                               const uint32_t* __restrict__ vals_in,
                                                               uint64_t* __restrict__ keys_out,
                                                               uint32_t* __restrict__ vals_out, uint32_t n,
@@ -454,6 +458,7 @@ struct Variant {
 const Variant kVariants[] = {
     CS_VARIANT(8, 512, 16, 4), CS_VARIANT(9, 512, 16, 4), CS_VARIANT(9, 512, 12, 4), CS_VARIANT(8, 512, 12, 4),
     CS_VARIANT(8, 256, 16, 4), CS_VARIANT(9, 512, 8, 4),  CS_VARIANT(9, 1024, 8, 4),
+    CS_VARIANT(9, 512, 32, 4), CS_VARIANT(8, 512, 32, 4),
 };
 #undef CS_VARIANT
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
@@ -508,12 +513,13 @@ int sort_passes(int sig_bits) {
     return (sig_bits + bits - 1) / bits;
 }
 
-cstone_status sort_prepare(void* ws, size_t n, bool with_perm, hipStream_t stream) {
+cstone_status sort_prepare(void* ws, size_t n, bool with_perm, hipStream_t stream, uint32_t* clear_word) {
     SortWs s = carve_sort(ws, n, with_perm);
     const size_t lb_words = s.lb_bytes / 8;
     const size_t init_grid = std::max<size_t>(4, std::min<size_t>((lb_words + 255) / 256, 1024));
     hipLaunchKernelGGL(sort_init_kernel, dim3(init_grid), dim3(256), 0, stream, s.ghist,
-                       static_cast<size_t>(kMaxPasses) * kMaxRadix, s.err, static_cast<uint64_t*>(s.lb), lb_words);
+                       static_cast<size_t>(kMaxPasses) * kMaxRadix, s.err, static_cast<uint64_t*>(s.lb), lb_words,
+                       clear_word);
     CS_HIP(hipGetLastError());
     return CSTONE_OK;
 }
@@ -636,7 +642,7 @@ cstone_status sort_seg_prepare(void* ws, size_t n_total, size_t n_tiles, uint32_
     const size_t init_grid =
         std::max<size_t>(4, std::min<size_t>((std::max(lb_words, gwords) + 255) / 256, 2048));
     hipLaunchKernelGGL(sort_init_kernel, dim3(init_grid), dim3(256), 0, stream, s.ghist, gwords, s.err,
-                       static_cast<uint64_t*>(s.lb), lb_words);
+                       static_cast<uint64_t*>(s.lb), lb_words, static_cast<uint32_t*>(nullptr));
     CS_HIP(hipGetLastError());
     return CSTONE_OK;
 }

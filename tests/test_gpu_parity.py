@@ -299,3 +299,19 @@ def test_build_uniform_2_24_full_parity():
     r2 = b.build(*coords(s), s.box, s.curve, s.n_crit)
     eq(host(r2.perm), ref["perm"], "second build perm")
     eq(host(r2.node_keys), ref["NK"], "second build NK")
+
+
+def test_sort_autotune_keeps_the_sort_exact():
+    """The shape autotuner times every compiled sort shape and makes the fastest
+    the default; whichever it picks, the sort stays bit-exact."""
+    s = wl.make_set("plummer", 300001, 41, 0, wl.HILBERT, 16)
+    keys, _ = oracle.compute_keys(s.x, s.y, s.z, s.box, s.curve)
+    ref_P, ref_perm = oracle.sort(keys)
+    say("sort autotune", len(cs.sort_variants()), "shapes")
+    chosen, ms = cs.sort_autotune(dev(keys), reps=1)
+    assert 0 <= chosen < len(cs.sort_variants()) and len(ms) == len(cs.sort_variants())
+    assert all(t > 0 for t in ms) and ms[chosen] == min(ms)
+    P, perm = cs.sort(dev(keys))
+    torch.cuda.synchronize()
+    eq(host(P), ref_P, "tuned sort P")
+    eq(host(perm), ref_perm, "tuned sort perm")
