@@ -23,8 +23,10 @@ size_t sort_workspace_bytes(size_t n, bool with_perm);
 cstone_status launch_sort(const uint64_t* keys_in, uint64_t* keys_out, uint32_t* perm_out, size_t n,
                           int sig_bits, void* ws, size_t ws_bytes, hipStream_t stream,
                           hipEvent_t* pass_events = nullptr, bool prepared = false, int variant = -1);
-// clear_word: NULL, or one caller word zeroed by the same launch
-cstone_status sort_prepare(void* ws, size_t n, bool with_perm, hipStream_t stream, uint32_t* clear_word = nullptr);
+// clear_word: NULL, or one caller word zeroed by the same launch; variant: the
+// sort shape the passes will use (-1: the default)
+cstone_status sort_prepare(void* ws, size_t n, bool with_perm, hipStream_t stream, uint32_t* clear_word = nullptr,
+                           int variant = -1);
 uint32_t* sort_first_histogram(void* ws, size_t n, bool with_perm, uint32_t* mask);
 int sort_passes(int sig_bits);
 

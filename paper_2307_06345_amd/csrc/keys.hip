@@ -145,7 +145,12 @@ __device__ __forceinline__ uint64_t hilbert_from_morton(uint64_t m, const uint16
     return key;
 }
 
-constexpr int kKeysBlock = 256;
+constexpr int kKeysBlock = 256;   // batched key kernel: one tile per block
+// plain key kernel: few large blocks (grid-stride), so that the blocks'
+// histogram flushes (512 global atomics each, all on the same 512 counters)
+// are few; 2 blocks of 1024 per CU still fill every SIMD
+constexpr int kKeysBlockPlain = 1024;
+constexpr size_t kKeysMaxBlocks = 512;
 
 template <int CURVE>
 __device__ __forceinline__ uint64_t key_of(double cx, double cy, double cz, double lo0, double lo1, double lo2,
@@ -163,7 +168,7 @@ __device__ __forceinline__ bool finite3(double a, double b, double c) {
 // and stores (all four arrays 16-byte aligned); the odd last particle, if any,
 // is done by thread 0 of block 0.
 template <int CURVE, bool PAIRED>
-__global__ __launch_bounds__(kKeysBlock) void keys_kernel(const double* __restrict__ x,
+__global__ __launch_bounds__(kKeysBlockPlain) void keys_kernel(const double* __restrict__ x,
                                                           const double* __restrict__ y,
                                                           const double* __restrict__ z, size_t n, double lo0,
                                                           double lo1, double lo2, double s0, double s1, double s2,
@@ -173,15 +178,15 @@ __global__ __launch_bounds__(kKeysBlock) void keys_kernel(const double* __restri
     __shared__ uint16_t first[8];
     __shared__ uint32_t h[512];
     if (CURVE == CSTONE_HILBERT) {
-        for (int i = threadIdx.x; i < kStates * 64; i += kKeysBlock) two[i] = d_hilbert.two[i];
+        for (int i = threadIdx.x; i < kStates * 64; i += kKeysBlockPlain) two[i] = d_hilbert.two[i];
         if (threadIdx.x < 8) first[threadIdx.x] = d_hilbert.first[threadIdx.x];
     }
     if (hist0)
-        for (int i = threadIdx.x; i < 512; i += kKeysBlock) h[i] = 0;
+        for (int i = threadIdx.x; i < 512; i += kKeysBlockPlain) h[i] = 0;
     __syncthreads();
     bool bad = false;
-    const size_t stride = static_cast<size_t>(gridDim.x) * kKeysBlock;
-    const size_t t0 = static_cast<size_t>(blockIdx.x) * kKeysBlock + threadIdx.x;
+    const size_t stride = static_cast<size_t>(gridDim.x) * kKeysBlockPlain;
+    const size_t t0 = static_cast<size_t>(blockIdx.x) * kKeysBlockPlain + threadIdx.x;
     if (PAIRED) {
         const size_t pairs = n / 2;
         const double2* x2 = reinterpret_cast<const double2*>(x);
@@ -219,7 +224,7 @@ __global__ __launch_bounds__(kKeysBlock) void keys_kernel(const double* __restri
     if (flags && __ballot(bad) != 0ull && lane_id() == 0) atomicOr(flags, CSTONE_FLAG_NONFINITE);
     if (hist0) {
         __syncthreads();
-        for (uint32_t i = threadIdx.x; i <= hmask; i += kKeysBlock)
+        for (uint32_t i = threadIdx.x; i <= hmask; i += kKeysBlockPlain)
             if (h[i]) atomicAdd(&hist0[i], h[i]);
     }
 }
@@ -228,7 +233,7 @@ template <int CURVE, bool PAIRED>
 void launch_keys_t(size_t blocks, hipStream_t stream, const double* x, const double* y, const double* z, size_t n,
                    const cstone_box& box, const double* s, uint64_t* keys, uint32_t* flags, uint32_t* hist0,
                    uint32_t hmask) {
-    hipLaunchKernelGGL((keys_kernel<CURVE, PAIRED>), dim3(blocks), dim3(kKeysBlock), 0, stream, x, y, z, n,
+    hipLaunchKernelGGL((keys_kernel<CURVE, PAIRED>), dim3(blocks), dim3(kKeysBlockPlain), 0, stream, x, y, z, n,
                        box.lo[0], box.lo[1], box.lo[2], s[0], s[1], s[2], keys, flags, hist0, hmask);
 }
 
@@ -297,9 +302,8 @@ cstone_status launch_keys(const double* x, const double* y, const double* z, siz
     auto aligned = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; };
     const bool paired = aligned(x) && aligned(y) && aligned(z) && aligned(keys);
     const size_t per_thread = paired ? 2 : 1;
-    size_t blocks = (n + kKeysBlock * per_thread - 1) / (kKeysBlock * per_thread);
-    const size_t max_blocks = 256 * 8;  // grid-stride beyond 8 blocks per CU
-    if (blocks > max_blocks) blocks = max_blocks;
+    size_t blocks = (n + kKeysBlockPlain * per_thread - 1) / (kKeysBlockPlain * per_thread);
+    if (blocks > kKeysMaxBlocks) blocks = kKeysMaxBlocks;  // grid-stride beyond that
     if (curve == CSTONE_HILBERT) {
         if (paired)
             launch_keys_t<CSTONE_HILBERT, true>(blocks, stream, x, y, z, n, box, s, keys, flags, hist0, hist_mask);

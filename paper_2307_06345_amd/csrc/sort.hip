@@ -513,9 +513,16 @@ int sort_passes(int sig_bits) {
     return (sig_bits + bits - 1) / bits;
 }
 
-cstone_status sort_prepare(void* ws, size_t n, bool with_perm, hipStream_t stream, uint32_t* clear_word) {
+cstone_status sort_prepare(void* ws, size_t n, bool with_perm, hipStream_t stream, uint32_t* clear_word,
+                           int variant) {
     SortWs s = carve_sort(ws, n, with_perm);
-    const size_t lb_words = s.lb_bytes / 8;
+    // only the first pass's look-back rows need clearing: each pass clears the
+    // rows of the next (32-bit words), or words carry the pass's epoch (64-bit)
+    const Variant& var = kVariants[variant >= 0 && variant < kNumVariants ? variant : default_variant()];
+    const size_t tile = static_cast<size_t>(var.block) * var.items;
+    const size_t words = ((n + tile - 1) / tile) << var.bits;
+    const bool wide = n >= (1ull << 30);
+    const size_t lb_words = std::min(s.lb_bytes / 8, wide ? words : (words + 1) / 2);
     const size_t init_grid = std::max<size_t>(4, std::min<size_t>((lb_words + 255) / 256, 1024));
     hipLaunchKernelGGL(sort_init_kernel, dim3(init_grid), dim3(256), 0, stream, s.ghist,
                        static_cast<size_t>(kMaxPasses) * kMaxRadix, s.err, static_cast<uint64_t*>(s.lb), lb_words,
@@ -546,7 +553,7 @@ cstone_status launch_sort(const uint64_t* keys_in, uint64_t* keys_out, uint32_t*
     const bool wide = n >= (1ull << 30);  // 30-bit look-back values otherwise
 
     if (!prepared) {
-        cstone_status st = sort_prepare(ws, n, with_perm, stream);
+        cstone_status st = sort_prepare(ws, n, with_perm, stream, nullptr, variant);
         if (st != CSTONE_OK) return st;
         const size_t hblocks =
             std::max<size_t>(1, std::min<size_t>((n + kHistBlock * 16 - 1) / (kHistBlock * 16), 1024));

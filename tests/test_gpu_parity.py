@@ -315,3 +315,26 @@ def test_sort_autotune_keeps_the_sort_exact():
     torch.cuda.synchronize()
     eq(host(P), ref_P, "tuned sort P")
     eq(host(perm), ref_perm, "tuned sort perm")
+
+
+@pytest.mark.slow
+def test_sort_beyond_2_30_uses_wide_lookback_words():
+    """n >= 2^30 switches the look-back words to 64 bits (epoch-tagged). At this
+    size the sort is checked by its characterisation on the device: sorted,
+    a permutation, equal keys in ascending original order, and P[i] equal to
+    keys[perm[i]] on a sample."""
+    from tests import device_checks as dc
+    n = (1 << 30) + 12345
+    g = torch.Generator(device="cuda")
+    g.manual_seed(30)
+    say("sort n =", n)
+    keys = torch.randint(0, 1 << 62, (n,), device="cuda", dtype=torch.int64, generator=g)
+    keys[: n // 8] %= 1 << 16  # runs of equal keys
+    P, perm = cs.sort(keys)
+    torch.cuda.synchronize()
+    dc.check_sorted_perm(P, perm, n)
+    i = torch.randint(0, n, (1 << 20,), device="cuda", generator=g)
+    assert torch.equal(P[i], keys[perm.long()[i]])
+    # the ties: within equal keys the permutation ascends (checked above), and the
+    # number of keys below 2^16 is preserved
+    assert int((P < (1 << 16)).sum()) == int((keys < (1 << 16)).sum())
