@@ -292,7 +292,24 @@ __device__ __forceinline__ void onesweep_tile(const TileDesc td, const uint64_t*
     }
 }
 
-template <int BITS, int BLOCK, int ITEMS, int WIN, bool FIRST, bool WITH_VALUES, class LB>
+// Tile of block b. Blocks are dealt to the 8 XCDs in turn; with XG > 1 every
+// XCD takes XG consecutive tiles in a row, so that where one tile's run of a
+// digit ends and the next tile's run begins (a partly written 64-byte
+// segment) both writes meet in the same L2. A tile then waits only on tiles
+// whose blocks are at most 8 XG - 1 dispatches later: the look-back progresses
+// whenever 8 XG blocks of the pass can be resident. With XG = 8 that is 64 of
+// the 256-512 a CU-filling pass holds, so even several passes sharing the GPU
+// (sorts on other streams) leave one of them enough to finish and free room.
+// The last, incomplete round of 8 XG blocks keeps tile = block.
+template <int XG>
+__device__ __forceinline__ uint32_t tile_of_block(uint32_t b, uint32_t nblocks) {
+    constexpr uint32_t R = 8u * XG;
+    if (XG == 1 || b >= nblocks / R * R) return b;
+    const uint32_t r = b / R, q = b % R;
+    return (r * 8u + q % 8u) * XG + q / 8u;
+}
+
+template <int BITS, int BLOCK, int ITEMS, int WIN, bool FIRST, bool WITH_VALUES, class LB, int XG>
 __global__ __launch_bounds__(BLOCK, (kMinBlocks<BLOCK, ITEMS>)) void onesweep_kernel(const uint64_t* __restrict__ keys_in,
                                                           const uint32_t* __restrict__ vals_in,
                                                           uint64_t* __restrict__ keys_out,
@@ -314,7 +331,7 @@ __global__ __launch_bounds__(BLOCK, (kMinBlocks<BLOCK, ITEMS>)) void onesweep_ke
     const uint32_t tid = threadIdx.x;
     // tiles follow the block index: the dispatcher starts lower blocks first,
     // so every tile a block waits for is running or done
-    const uint32_t tile = blockIdx.x;
+    const uint32_t tile = tile_of_block<XG>(blockIdx.x, gridDim.x);
     if (lb_clear && tid < RADIX) lb_clear[static_cast<size_t>(tile) * RADIX + tid] = 0;  // rows of the next pass
     for (int i = tid; i < W * RADIX; i += BLOCK) (&whist[0][0])[i] = 0;
     if (tid < RADIX) nhist[tid] = 0;
@@ -334,7 +351,7 @@ __global__ __launch_bounds__(BLOCK, (kMinBlocks<BLOCK, ITEMS>)) void onesweep_ke
 // tile tiles[b] = {first key, key count, first tile of its set, set}; every
 // set has its own digit histograms (ghist + set * hist_stride) and its own
 // look-back chain, and its permutation values count from the set's start.
-template <int BITS, int BLOCK, int ITEMS, int WIN, bool FIRST, bool WITH_VALUES, class LB>
+template <int BITS, int BLOCK, int ITEMS, int WIN, bool FIRST, bool WITH_VALUES, class LB, int XG>
 __global__ __launch_bounds__(BLOCK, (kMinBlocks<BLOCK, ITEMS>)) void onesweep_seg_kernel(const uint64_t* __restrict__ keys_in,
                                                               const uint32_t* __restrict__ vals_in,
                                                               uint64_t* __restrict__ keys_out,
@@ -355,7 +372,7 @@ __global__ __launch_bounds__(BLOCK, (kMinBlocks<BLOCK, ITEMS>)) void onesweep_se
     __shared__ uint32_t ddelta[RADIX];
     __shared__ uint64_t scan_tmp[W];
     const uint32_t tid = threadIdx.x;
-    const uint32_t tile = blockIdx.x;
+    const uint32_t tile = tile_of_block<XG>(blockIdx.x, gridDim.x);
     if (lb_clear && tid < RADIX) lb_clear[static_cast<size_t>(tile) * RADIX + tid] = 0;
     for (int i = tid; i < W * RADIX; i += BLOCK) (&whist[0][0])[i] = 0;
     if (tid < RADIX) nhist[tid] = 0;
@@ -391,29 +408,29 @@ struct PassArgs {
     bool wide;  // 64-bit look-back words (n >= 2^30)
 };
 
-template <int BITS, int BLOCK, int ITEMS, int WIN, bool FIRST, bool VALS>
+template <int BITS, int BLOCK, int ITEMS, int WIN, bool FIRST, bool VALS, int XG>
 void launch_one(const PassArgs& a, hipStream_t stream) {
     constexpr uint32_t tile = BLOCK * ITEMS;
     const dim3 grid((a.n + tile - 1) / tile), block(BLOCK);
     if (a.wide)
-        hipLaunchKernelGGL((onesweep_kernel<BITS, BLOCK, ITEMS, WIN, FIRST, VALS, Lb64>), grid, block, 0, stream,
+        hipLaunchKernelGGL((onesweep_kernel<BITS, BLOCK, ITEMS, WIN, FIRST, VALS, Lb64, XG>), grid, block, 0, stream,
                            a.keys_in, a.vals_in, a.keys_out, a.vals_out, a.n, a.shift, a.ghist, a.ghist_next,
                            a.shift_next, static_cast<uint64_t*>(a.lb), nullptr, a.epoch, a.err);
     else
-        hipLaunchKernelGGL((onesweep_kernel<BITS, BLOCK, ITEMS, WIN, FIRST, VALS, Lb32>), grid, block, 0, stream,
+        hipLaunchKernelGGL((onesweep_kernel<BITS, BLOCK, ITEMS, WIN, FIRST, VALS, Lb32, XG>), grid, block, 0, stream,
                            a.keys_in, a.vals_in, a.keys_out, a.vals_out, a.n, a.shift, a.ghist, a.ghist_next,
                            a.shift_next, static_cast<uint32_t*>(a.lb), static_cast<uint32_t*>(a.lb_clear), a.epoch,
                            a.err);
 }
 
-template <int BITS, int BLOCK, int ITEMS, int WIN>
+template <int BITS, int BLOCK, int ITEMS, int WIN, int XG>
 void launch_pass_t(const PassArgs& a, bool first, bool with_values, hipStream_t stream) {
     if (with_values && first)
-        launch_one<BITS, BLOCK, ITEMS, WIN, true, true>(a, stream);
+        launch_one<BITS, BLOCK, ITEMS, WIN, true, true, XG>(a, stream);
     else if (with_values)
-        launch_one<BITS, BLOCK, ITEMS, WIN, false, true>(a, stream);
+        launch_one<BITS, BLOCK, ITEMS, WIN, false, true, XG>(a, stream);
     else
-        launch_one<BITS, BLOCK, ITEMS, WIN, false, false>(a, stream);
+        launch_one<BITS, BLOCK, ITEMS, WIN, false, false, XG>(a, stream);
 }
 
 struct SegArgs {
@@ -423,42 +440,42 @@ struct SegArgs {
     uint32_t hist_stride;
 };
 
-template <int BITS, int BLOCK, int ITEMS, int WIN, bool FIRST, bool VALS>
+template <int BITS, int BLOCK, int ITEMS, int WIN, bool FIRST, bool VALS, int XG>
 void launch_one_seg(const PassArgs& a, const SegArgs& g, hipStream_t stream) {
     const dim3 grid(g.n_tiles), block(BLOCK);
     if (a.wide)
-        hipLaunchKernelGGL((onesweep_seg_kernel<BITS, BLOCK, ITEMS, WIN, FIRST, VALS, Lb64>), grid, block, 0, stream,
+        hipLaunchKernelGGL((onesweep_seg_kernel<BITS, BLOCK, ITEMS, WIN, FIRST, VALS, Lb64, XG>), grid, block, 0, stream,
                            a.keys_in, a.vals_in, a.keys_out, a.vals_out, a.n, a.shift, a.ghist, a.ghist_next,
                            a.shift_next, g.hist_stride, g.tiles, g.seg_base, static_cast<uint64_t*>(a.lb), nullptr,
                            a.epoch, a.err);
     else
-        hipLaunchKernelGGL((onesweep_seg_kernel<BITS, BLOCK, ITEMS, WIN, FIRST, VALS, Lb32>), grid, block, 0, stream,
+        hipLaunchKernelGGL((onesweep_seg_kernel<BITS, BLOCK, ITEMS, WIN, FIRST, VALS, Lb32, XG>), grid, block, 0, stream,
                            a.keys_in, a.vals_in, a.keys_out, a.vals_out, a.n, a.shift, a.ghist, a.ghist_next,
                            a.shift_next, g.hist_stride, g.tiles, g.seg_base, static_cast<uint32_t*>(a.lb),
                            static_cast<uint32_t*>(a.lb_clear), a.epoch, a.err);
 }
 
-template <int BITS, int BLOCK, int ITEMS, int WIN>
+template <int BITS, int BLOCK, int ITEMS, int WIN, int XG>
 void launch_seg_t(const PassArgs& a, const SegArgs& g, bool first, bool with_values, hipStream_t stream) {
     if (with_values && first)
-        launch_one_seg<BITS, BLOCK, ITEMS, WIN, true, true>(a, g, stream);
+        launch_one_seg<BITS, BLOCK, ITEMS, WIN, true, true, XG>(a, g, stream);
     else if (with_values)
-        launch_one_seg<BITS, BLOCK, ITEMS, WIN, false, true>(a, g, stream);
+        launch_one_seg<BITS, BLOCK, ITEMS, WIN, false, true, XG>(a, g, stream);
     else
-        launch_one_seg<BITS, BLOCK, ITEMS, WIN, false, false>(a, g, stream);
+        launch_one_seg<BITS, BLOCK, ITEMS, WIN, false, false, XG>(a, g, stream);
 }
 
 struct Variant {
-    int bits, block, items, window;
+    int bits, block, items, window, xcd_group;
     void (*launch)(const PassArgs&, bool, bool, hipStream_t);
     void (*launch_seg)(const PassArgs&, const SegArgs&, bool, bool, hipStream_t);
 };
 
-#define CS_VARIANT(B, BL, IT, WI) {B, BL, IT, WI, launch_pass_t<B, BL, IT, WI>, launch_seg_t<B, BL, IT, WI>}
+#define CS_VARIANT(B, BL, IT, WI, XG) {B, BL, IT, WI, XG, launch_pass_t<B, BL, IT, WI, XG>, launch_seg_t<B, BL, IT, WI, XG>}
 const Variant kVariants[] = {
-    CS_VARIANT(8, 512, 16, 4), CS_VARIANT(9, 512, 16, 4), CS_VARIANT(9, 512, 12, 4), CS_VARIANT(8, 512, 12, 4),
-    CS_VARIANT(8, 256, 16, 4), CS_VARIANT(9, 512, 8, 4),  CS_VARIANT(9, 1024, 8, 4),
-    CS_VARIANT(9, 512, 32, 4), CS_VARIANT(8, 512, 32, 4),
+    CS_VARIANT(9, 512, 16, 4, 8), CS_VARIANT(9, 512, 16, 4, 1), CS_VARIANT(8, 512, 16, 4, 8),
+    CS_VARIANT(9, 512, 12, 4, 8), CS_VARIANT(9, 512, 32, 4, 8), CS_VARIANT(8, 512, 16, 4, 1),
+    CS_VARIANT(9, 512, 12, 4, 1), CS_VARIANT(9, 512, 32, 4, 1),
 };
 #undef CS_VARIANT
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
@@ -466,7 +483,7 @@ constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 int builtin_variant() {
     static const int v = [] {
         const char* e = std::getenv("CSTONE_SORT_VARIANT");
-        int x = e ? std::atoi(e) : 1;  // 9-bit digits, 512 x 16 tiles
+        int x = e ? std::atoi(e) : 0;  // 9-bit digits, 512 x 16 tiles, 8 tiles in a row per XCD
         return (x >= 0 && x < kNumVariants) ? x : 0;
     }();
     return v;
