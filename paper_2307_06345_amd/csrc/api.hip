@@ -178,19 +178,31 @@ cstone_status cstone_build(const double* x, const double* y, const double* z, si
         s = loop.begin(sorted_keys, n, n_crit, leaves, nl, leaf_capacity, counts, max_iters, stage_ws, reb_bytes,
                        stream, flag);
         if (s != CSTONE_OK) break;
-        bool finished = false;
-        for (uint32_t batch = 0; !finished; batch = 2) {
+        // The link is enqueued behind the first batch of rounds (usually the
+        // last one), so one synchronisation serves both; if more rounds are
+        // needed, it runs again once, after the last batch.
+        bool finished = false, linked = false;
+        for (uint32_t batch = 0; !finished; batch = 4) {
             if ((s = loop.enqueue(batch)) != CSTONE_OK) break;
             if (mark(3) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
-            if (node_keys) {
+            if (node_keys && batch == 0) {
                 s = launch_link(leaves, leaf_capacity, loop.device_leaf_count(), node_keys, child, level_offsets,
                                 link_ws, link_bytes, stream);
                 if (s != CSTONE_OK) break;
+                linked = true;
             }
             if (mark(4) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
             loop.wait(&finished);
+            if (!finished) linked = false;
         }
         if (s != CSTONE_OK) break;
+        if (node_keys && !linked && loop.status == CSTONE_OK) {  // the tree the first link saw was not the last
+            if (mark(3) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
+            s = launch_link(leaves, leaf_capacity, loop.device_leaf_count(), node_keys, child, level_offsets, link_ws,
+                            link_bytes, stream);
+            if (s != CSTONE_OK) break;
+            if (mark(4) != hipSuccess || hipStreamSynchronize(stream) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
+        }
         *n_leaves = loop.n_leaves;
         if (iters_done) *iters_done = loop.rounds;
         host_flag = loop.input_flags;

@@ -148,7 +148,8 @@ cstone_status enqueue_build(const cstone_batch& p, const double* x, const double
             return st;
     }
     const size_t rb = batch_rebalance_workspace_bytes(ns, p.entries, p.split_capacity);
-    if ((st = launch_batch_rebalance(sorted_keys, w.sets, ns, p.entries, p.split_capacity, p.rounds, w.flags, leaves,
+    if ((st = launch_batch_rebalance(sorted_keys, p.n_total, w.sets, ns, p.entries, p.split_capacity, p.rounds, w.flags,
+                                     leaves,
                                      counts, reinterpret_cast<BatchResult*>(results), rebalance_ws(w), rb,
                                      stream)) != CSTONE_OK)
         return st;

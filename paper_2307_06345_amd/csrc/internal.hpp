@@ -100,6 +100,9 @@ struct LoopState {
     uint64_t final_nl;     // set by the finalize kernel: leaves (entries) of the result array
     uint32_t final_last;   // rounds behind it
     uint32_t final_code;   // 0 running, 1 converged, 2 capacity exceeded
+    uint32_t start_level;  // from the root: rounds skipped by starting at the uniform grid of this level
+    uint32_t start_fine;   // the start-level search went finer than level 3
+    uint32_t mins[kL + 1]; // least node count of every level (start-level search)
 };
 
 // The rebalance loop, driven from the device: rounds are enqueued ahead of
@@ -138,6 +141,7 @@ private:
     void* ws_ = nullptr;
     LoopState* st_ = nullptr;
     bool root_ = false;
+    int start_top_ = 0;  // > 0: the loop may start at a uniform level up to this one
 };
 
 cstone_status run_rebalance(const uint64_t* sorted_keys, size_t n, uint32_t n_crit, uint64_t* leaves,
@@ -148,7 +152,7 @@ cstone_status run_rebalance(const uint64_t* sorted_keys, size_t n, uint32_t n_cr
 // (a round after global convergence exits at once), then per-set leaves,
 // counts and results. Sets' arrays are kept back to back on the device.
 size_t batch_rebalance_workspace_bytes(uint32_t n_sets, size_t entry_capacity, size_t split_capacity);
-cstone_status launch_batch_rebalance(const uint64_t* P, const BatchSet* sets, uint32_t n_sets,
+cstone_status launch_batch_rebalance(const uint64_t* P, size_t n_total, const BatchSet* sets, uint32_t n_sets,
                                      size_t entry_capacity, size_t split_capacity, uint32_t rounds,
                                      const uint32_t* set_flags, uint64_t* leaves, uint32_t* counts,
                                      BatchResult* results, void* ws, size_t ws_bytes, hipStream_t stream);

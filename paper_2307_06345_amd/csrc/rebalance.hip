@@ -72,8 +72,10 @@ __global__ __launch_bounds__(256) void loop_init_kernel(LoopState* st, uint64_t 
         st->nsplit[t] = 0;
     }
     if (t <= kMaxRounds) st->nl[t] = t == 0 ? nl0 : 0;
+    if (t <= kL) st->mins[t] = 0xffffffffu;
     if (t == 0) {
         st->err = 0;
+        st->start_level = 0;
         st->input_flags = input_flags ? *input_flags : 0u;
         if (root) {  // the only one-leaf cornerstone array
             K[0] = 0;
@@ -81,6 +83,123 @@ __global__ __launch_bounds__(256) void loop_init_kernel(LoopState* st, uint64_t 
             pos[0] = 0;
             pos[1] = n;
         }
+    }
+}
+
+// ---- an exact start from a uniform level ---------------------------------------
+//
+// From the root, a round splits every leaf holding more than n_crit particles
+// and merges nothing (8 children hold more than n_crit together). So if every
+// node of level l - 1 holds more than n_crit particles, the array after l
+// rounds is the uniform grid of level l, and the loop may start there, with
+// the l rounds counted. The node positions of level 3 come first (one wave per
+// boundary); only if every level-2 node is over n_crit are those of a finer
+// level (at most kStartFine) searched inside them, and only if every level-3
+// node is over n_crit. Per-level least counts then give the deepest such l.
+
+constexpr int kStartCoarse = 3;
+constexpr int kStartFine = 6;
+constexpr uint32_t kCoarseNodes = 1u << (3 * kStartCoarse);  // 512
+
+__global__ __launch_bounds__(256) void start_coarse_kernel(const uint64_t* __restrict__ P, uint32_t n,
+                                                           uint32_t* __restrict__ posc) {
+    const uint32_t w = blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
+    if (w > kCoarseNodes) return;  // whole waves
+    const uint64_t key = static_cast<uint64_t>(w) << (3 * (kL - kStartCoarse));  // w = 512: 8^21
+    const uint32_t at = wave_lower_bound(P, 0, n, key);
+    if (lane_id() == 0) posc[w] = at;
+}
+
+// One block of 512: least counts of levels 0..3 from the level-3 positions,
+// and whether a start finer than level 3 is possible (every level-3 node over
+// n_crit), so whether the finer positions are worth searching.
+__global__ __launch_bounds__(kCoarseNodes) void start_check_kernel(const uint32_t* __restrict__ posc, uint32_t n_crit,
+                                                                   int lf, LoopState* st) {
+    __shared__ uint32_t red[kCoarseNodes / kWave];
+    const uint32_t t = threadIdx.x;
+    uint32_t lvl_min[kStartCoarse + 1];
+#pragma unroll
+    for (int k = 0; k <= kStartCoarse; ++k) {
+        const int span = 1 << (3 * (kStartCoarse - k));  // level-3 nodes per level-k node
+        uint32_t c = 0xffffffffu;
+        if ((t & (span - 1)) == 0) c = posc[t + span] - posc[t];
+        for (int d = 1; d < kWave; d <<= 1) c = min(c, static_cast<uint32_t>(__shfl_xor(static_cast<int>(c), d, kWave)));
+        if (lane_id() == 0) red[t / kWave] = c;
+        __syncthreads();
+        uint32_t m = 0xffffffffu;
+        for (uint32_t w = 0; w < kCoarseNodes / kWave; ++w) m = min(m, red[w]);
+        lvl_min[k] = m;
+        __syncthreads();
+    }
+    if (t == 0) {
+        for (int k = 0; k <= kStartCoarse; ++k) st->mins[k] = lvl_min[k];
+        st->start_fine = (lf > kStartCoarse && lvl_min[kStartCoarse] > n_crit) ? 1u : 0u;
+    }
+}
+
+__global__ __launch_bounds__(256) void start_fine_kernel(const uint64_t* __restrict__ P,
+                                                         const uint32_t* __restrict__ posc, int lf,
+                                                         const LoopState* st, uint32_t* __restrict__ posf) {
+    if (!st->start_fine) return;
+    const uint32_t nodes = 1u << (3 * lf);
+    const int sub = 3 * (lf - kStartCoarse);  // fine nodes per coarse node: 2^sub
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j <= nodes; j += stride) {
+        const uint32_t p = j >> sub;
+        uint32_t at;
+        if ((j & ((1u << sub) - 1)) == 0) {
+            at = posc[p];  // a coarse boundary
+        } else {
+            const uint64_t key = static_cast<uint64_t>(j) << (3 * (kL - lf));
+            at = static_cast<uint32_t>(lower_bound_u64(P, posc[p], posc[p + 1], key));
+        }
+        posf[j] = at;
+    }
+}
+
+// least counts of levels 4 .. lf - 1 from the finer positions (block minima,
+// then one atomic per block and level)
+__global__ __launch_bounds__(256) void start_mins_kernel(const uint32_t* __restrict__ posf, int lf, LoopState* st) {
+    __shared__ uint32_t red[256 / kWave];
+    if (!st->start_fine) return;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (int k = kStartCoarse + 1; k < lf; ++k) {
+        const uint32_t nodes = 1u << (3 * k);
+        const uint32_t span = 1u << (3 * (lf - k));
+        uint32_t c = 0xffffffffu;
+        for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < nodes; u += stride)
+            c = min(c, posf[(u + 1) * span] - posf[u * span]);
+        for (int d = 1; d < kWave; d <<= 1) c = min(c, static_cast<uint32_t>(__shfl_xor(static_cast<int>(c), d, kWave)));
+        if (lane_id() == 0) red[threadIdx.x / kWave] = c;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t m = 0xffffffffu;
+            for (int w = 0; w < 256 / kWave; ++w) m = min(m, red[w]);
+            if (m != 0xffffffffu) atomicMin(&st->mins[k], m);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void start_write_kernel(const uint32_t* __restrict__ posc,
+                                                          const uint32_t* __restrict__ posf, int lf, uint32_t n_crit,
+                                                          LoopState* st, uint64_t* __restrict__ K,
+                                                          uint32_t* __restrict__ pos_out) {
+    const bool fine = st->start_fine != 0;
+    const int e = fine ? lf : kStartCoarse;
+    const uint32_t* pos = fine ? posf : posc;
+    int l = 0;  // deepest level whose nodes' parents all hold more than n_crit
+    while (l < e && st->mins[l] > n_crit) ++l;
+    const uint32_t nodes = 1u << (3 * l);
+    const int step = 3 * (e - l);
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j <= nodes; j += stride) {
+        K[j] = j == nodes ? kKeyEnd : static_cast<uint64_t>(j) << (3 * (kL - l));
+        pos_out[j] = pos[static_cast<size_t>(j) << step];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->nl[0] = nodes;
+        st->start_level = static_cast<uint32_t>(l);
     }
 }
 
@@ -253,7 +372,7 @@ __global__ __launch_bounds__(kRBlock) void round_kernel(uint32_t n, uint32_t n_c
 
 // ---- f for the next round: positions of the inner child boundaries ----------
 
-__global__ __launch_bounds__(kSearchBlock) void split_search_kernel(const uint64_t* __restrict__ P,
+__global__ __launch_bounds__(kSearchBlock) void split_search_kernel(const uint64_t* __restrict__ P, uint32_t n,
                                                                      const uint64_t* __restrict__ K,
                                                                      const uint32_t* __restrict__ pos,
                                                                      uint32_t* __restrict__ pos_out,
@@ -280,8 +399,8 @@ __global__ __launch_bounds__(kSearchBlock) void split_search_kernel(const uint64
             const uint32_t c = w % 7u + 1u;
             const uint64_t ki = K[i];
             key = ki + c * ((K[i + 1] - ki) >> 3);
-            lo = pos[i];
-            hi = pos[i + 1];
+            hi = min(pos[i + 1], n);  // positions never exceed n; the clamps guard memory all the same
+            lo = min(pos[i], hi);
             dst = static_cast<uint32_t>(e >> 32) + c;
         }
         valid = valid && dst <= capacity;  // always true for a listed split; guards memory
@@ -347,6 +466,7 @@ struct RebalanceWs {
     LoopState* st;
     uint64_t* lb;
     size_t lb_words;
+    uint32_t* posc;  // level-3 node positions (start-level search)
     size_t bytes;
 };
 
@@ -363,6 +483,7 @@ RebalanceWs carve_rebalance(void* ws, size_t n, uint32_t n_crit, size_t cap) {
     r.st = c.take<LoopState>(1);
     r.lb_words = (cap + kRTile - 1) / kRTile + 1;
     r.lb = c.take<uint64_t>(r.lb_words);
+    r.posc = c.take<uint32_t>(kCoarseNodes + 1);
     r.bytes = c.off;
     return r;
 }
@@ -410,12 +531,39 @@ cstone_status RebalanceLoop::begin(const uint64_t* P, size_t n, uint32_t n_crit,
     ws_ = ws;
     st_ = w.st;
     root_ = nl0 == 1;
+    // From the root and to convergence, the loop may skip the rounds that only
+    // split every leaf: aim at the level where nodes hold about 8 (n_crit + 1)
+    // particles, not finer than kStartFine, and at least level 3.
+    start_top_ = 0;
+    if (root_ && max_iters_ >= static_cast<uint32_t>(kL + 1) && n > 0) {
+        int lf = 1;
+        for (double r = static_cast<double>(n) / (static_cast<double>(n_crit) + 1.0); r >= 8.0; r /= 8.0) ++lf;
+        lf = std::min(std::max(lf, kStartCoarse), kStartFine);
+        if ((size_t{1} << (3 * lf)) <= cap) start_top_ = lf;
+    }
     hipLaunchKernelGGL(loop_init_kernel, dim3(clamp_grid(grid_1d(std::max<size_t>(w.lb_words, kMaxRounds + 1), 256))),
                        dim3(256), 0, stream, w.st, static_cast<uint64_t>(nl0), w.lb, w.lb_words, w.pos[0],
-                       static_cast<uint32_t>(n), root_ ? 1 : 0, leaves, input_flags);
+                       static_cast<uint32_t>(n), (root_ && !start_top_) ? 1 : 0, leaves, input_flags);
     if (!root_)
         hipLaunchKernelGGL(positions_kernel, dim3(grid_1d(nl0 + 1, kCountBlock)), dim3(kCountBlock), 0, stream, P, n,
                            leaves, nl0, w.pos[0]);
+    if (start_top_) {
+        const int lf = start_top_;
+        const uint32_t un = static_cast<uint32_t>(n);
+        hipLaunchKernelGGL(start_coarse_kernel, dim3(grid_1d(kCoarseNodes + 1, 256 / kWave)), dim3(256), 0, stream, P,
+                           un, w.posc);
+        hipLaunchKernelGGL(start_check_kernel, dim3(1), dim3(kCoarseNodes), 0, stream, w.posc, n_crit, lf, w.st);
+        if (lf > kStartCoarse) {
+            hipLaunchKernelGGL(start_fine_kernel, dim3(clamp_grid(grid_1d((size_t{1} << (3 * lf)) + 1, 256))),
+                               dim3(256), 0, stream, P, w.posc, lf, w.st, w.pos[1]);
+            if (lf > kStartCoarse + 1)
+                hipLaunchKernelGGL(start_mins_kernel, dim3(clamp_grid(grid_1d(size_t{1} << (3 * (lf - 1)), 256))),
+                                   dim3(256), 0, stream, w.pos[1], lf, w.st);
+        }
+        hipLaunchKernelGGL(start_write_kernel, dim3(clamp_grid(grid_1d((size_t{1} << (3 * lf)) + 1, 256))), dim3(256),
+                           0, stream, w.posc, w.pos[1], lf, n_crit, w.st, leaves, w.pos[0]);
+        nl0_ = size_t{1} << (3 * lf);  // round 0 starts with at most this many leaves
+    }
     CS_HIP(hipGetLastError());
     return CSTONE_OK;
 }
@@ -430,6 +578,9 @@ cstone_status RebalanceLoop::enqueue(uint32_t rounds) {
                 ratio /= 8.0;
                 ++rounds;
             }
+            // less the rounds a uniform start skips, with one level to spare (a
+            // start coarser than that needs a later batch)
+            if (start_top_ > 1) rounds = std::max<uint32_t>(2, rounds - static_cast<uint32_t>(start_top_ - 1));
         }
     }
     rounds = std::min(rounds, max_iters_ - enqueued_);
@@ -446,7 +597,8 @@ cstone_status RebalanceLoop::enqueue(uint32_t rounds) {
         // one wave per search while searches are few
         const size_t searches = 7 * std::min<size_t>(rows, w.split_capacity);
         hipLaunchKernelGGL(split_search_kernel, dim3(search_grid(searches)),
-                           dim3(kSearchBlock), 0, stream_, P_, bufK[q & 1], w.pos[q & 1], w.pos[(q + 1) & 1],
+                           dim3(kSearchBlock), 0, stream_, P_, static_cast<uint32_t>(n_), bufK[q & 1], w.pos[q & 1],
+                           w.pos[(q + 1) & 1],
                            w.splits, w.split_capacity, w.st, static_cast<int>(q), static_cast<uint64_t>(cap_));
     }
     enqueued_ += rounds;
@@ -463,7 +615,7 @@ cstone_status RebalanceLoop::wait(bool* finished) {
     CS_HIP(hipMemcpyAsync(&host, st_, sizeof(LoopState), hipMemcpyDeviceToHost, stream_));
     CS_HIP(hipStreamSynchronize(stream_));
     input_flags = host.input_flags;
-    rounds = host.final_last;
+    rounds = host.final_last + host.start_level;
     *finished = true;
     if (host.err) {
         status = CSTONE_ERR_DEVICE;
@@ -498,7 +650,7 @@ cstone_status run_rebalance(const uint64_t* P, size_t n, uint32_t n_crit, uint64
     while (!finished) {
         if ((s = loop.enqueue(batch)) != CSTONE_OK) return s;
         loop.wait(&finished);
-        batch = 2;
+        batch = 4;
     }
     if (loop.status == CSTONE_ERR_DEVICE) return loop.status;
     *n_leaves = loop.n_leaves;
@@ -785,7 +937,8 @@ BatchTreeView batch_rebalance_view(void* ws, uint32_t n_sets, size_t C, size_t s
     return {{w.K[0], w.K[1]}, {w.sid[0], w.sid[1]}, {w.starts[0], w.starts[1]}, w.st};
 }
 
-cstone_status launch_batch_rebalance(const uint64_t* P, const BatchSet* sets, uint32_t n_sets, size_t C,
+cstone_status launch_batch_rebalance(const uint64_t* P, size_t n_total, const BatchSet* sets, uint32_t n_sets,
+                                     size_t C,
                                      size_t split_capacity, uint32_t rounds, const uint32_t* set_flags,
                                      uint64_t* leaves, uint32_t* counts, BatchResult* results, void* ws,
                                      size_t ws_bytes, hipStream_t stream) {
@@ -807,8 +960,8 @@ cstone_status launch_batch_rebalance(const uint64_t* P, const BatchSet* sets, ui
                            w.changed_set + static_cast<size_t>(q) * n_sets, w.splits, cap_u, w.st,
                            static_cast<int>(q), static_cast<uint64_t>(C), w.lb);
         hipLaunchKernelGGL(split_search_kernel, dim3(search_grid(7 * split_capacity)),
-                           dim3(kSearchBlock), 0, stream, P, w.K[a], w.pos[a], w.pos[b], w.splits, cap_u, w.st,
-                           static_cast<int>(q), static_cast<uint64_t>(C));
+                           dim3(kSearchBlock), 0, stream, P, static_cast<uint32_t>(n_total), w.K[a], w.pos[a],
+                           w.pos[b], w.splits, cap_u, w.st, static_cast<int>(q), static_cast<uint64_t>(C));
     }
     hipLaunchKernelGGL(batch_finalize_kernel, dim3(clamp_grid(grid_1d(C + 1, 256))), dim3(256), 0, stream, w.st,
                        rounds, static_cast<uint64_t>(C), sets, n_sets, w.K[0], w.K[1], w.pos[0], w.pos[1], w.sid[0],
