@@ -338,3 +338,19 @@ def test_sort_beyond_2_30_uses_wide_lookback_words():
     # the ties: within equal keys the permutation ascends (checked above), and the
     # number of keys below 2^16 is preserved
     assert int((P < (1 << 16)).sum()) == int((keys < (1 << 16)).sum())
+
+
+def test_rebalance_from_root_start_between_levels():
+    """Every level-3 node is over N_crit but some level-4 nodes are empty
+    (particles only in x < 0.9): the loop starts at level 4, not at the finer
+    level it searched, and still reports the rounds counted from the root."""
+    x, y, z = wl.uniform_cube(1 << 20, 17, 0)
+    x = x * 0.9
+    keys, _ = oracle.compute_keys(x, y, z, wl.UNIT_BOX, wl.HILBERT)
+    P, _ = oracle.sort(keys)
+    say("rebalance start between levels")
+    K, counts, rounds = cs.rebalance(dev(P), 8)
+    rK, rN, rrounds, _, _ = oracle.rebalance_iterate(P, np.array([0, END], np.uint64), 8)
+    eq(host(K), rK, "leaves")
+    eq(host(counts), rN, "counts")
+    assert rounds == rrounds
