@@ -132,7 +132,7 @@ cstone_status cstone_build(const double* x, const double* y, const double* z, si
 
     hipEvent_t ev[5] = {};
     hipEvent_t pass_ev[9] = {};
-    const int passes = sort_passes(63);
+    const int passes = sort_passes(n, 63, true);
     const bool timed = timings != nullptr;
     auto cleanup = [&]() {
         for (auto& e : ev)
@@ -159,9 +159,9 @@ cstone_status cstone_build(const double* x, const double* y, const double* z, si
         } else {
             hipLaunchKernelGGL(clear_word_kernel, dim3(1), dim3(1), 0, stream, flag);
         }
-        uint32_t hist_mask = 0;
-        uint32_t* hist0 = n ? sort_first_histogram(stage_ws, n, true, &hist_mask) : nullptr;
-        s = launch_keys(x, y, z, n, *box, curve, keys, flag, stream, hist0, hist_mask);
+        uint32_t hist_mask = 0, hist_shift = 0;
+        uint32_t* hist0 = n ? sort_first_histogram(stage_ws, n, true, 63, &hist_mask, &hist_shift) : nullptr;
+        s = launch_keys(x, y, z, n, *box, curve, keys, flag, stream, hist0, hist_mask, hist_shift);
         if (s != CSTONE_OK) break;
         if (mark(1) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
         s = launch_sort(keys, sorted_keys, perm, n, 63, stage_ws, stage_bytes, stream,

@@ -7,19 +7,22 @@ namespace cs {
 
 // keys.hip
 // hist0: NULL, or hist_mask + 1 (<= 512) counters to which the count of
-// every key's value of (key & hist_mask) is added
+// every key's value of ((key >> hist_shift) & hist_mask) is added
 cstone_status launch_keys(const double* x, const double* y, const double* z, size_t n, const cstone_box& box,
                           cstone_curve curve, uint64_t* keys, uint32_t* flags, hipStream_t stream,
-                          uint32_t* hist0 = nullptr, uint32_t hist_mask = 0);
+                          uint32_t* hist0 = nullptr, uint32_t hist_mask = 0, uint32_t hist_shift = 0);
 
-// sort.hip — stable LSD radix sort of 64-bit keys (63 or 64 significant bits)
+// sort.hip — stable radix sort of 64-bit keys (63 or 64 significant bits)
 // with an optional uint32 permutation; sig_bits selects how many low bits are
-// sorted on.
+// sorted on. Particle keys with a permutation take the split path (top two
+// digits, then every bucket on its own), other sorts plain LSD passes.
 size_t sort_workspace_bytes(size_t n, bool with_perm);
-// pass_events: NULL, or passes + 1 events recorded before the first digit pass
-// and after every pass. prepared: sort_prepare() already ran on this
-// workspace and the producer of the keys counted their lowest digit into
-// sort_first_histogram() (*mask + 1 counters), so neither step is repeated.
+// pass_events: NULL, or sort_passes() + 1 events recorded before the first
+// pass and after every pass (split path: after each top pass, the bucket
+// sort and the low passes). prepared: sort_prepare() already ran on this
+// workspace and the producer of the keys counted their first digit into
+// sort_first_histogram() (*mask + 1 counters of (key >> *shift) & *mask), so
+// neither step is repeated.
 cstone_status launch_sort(const uint64_t* keys_in, uint64_t* keys_out, uint32_t* perm_out, size_t n,
                           int sig_bits, void* ws, size_t ws_bytes, hipStream_t stream,
                           hipEvent_t* pass_events = nullptr, bool prepared = false, int variant = -1);
@@ -27,8 +30,8 @@ cstone_status launch_sort(const uint64_t* keys_in, uint64_t* keys_out, uint32_t*
 // sort shape the passes will use (-1: the default)
 cstone_status sort_prepare(void* ws, size_t n, bool with_perm, hipStream_t stream, uint32_t* clear_word = nullptr,
                            int variant = -1);
-uint32_t* sort_first_histogram(void* ws, size_t n, bool with_perm, uint32_t* mask);
-int sort_passes(int sig_bits);
+uint32_t* sort_first_histogram(void* ws, size_t n, bool with_perm, int sig_bits, uint32_t* mask, uint32_t* shift);
+int sort_passes(size_t n, int sig_bits, bool with_perm);
 
 // ---- batched builds: many independent sets in one pass of every stage -------
 

@@ -173,7 +173,7 @@ __global__ __launch_bounds__(kKeysBlockPlain) void keys_kernel(const double* __r
                                                           const double* __restrict__ z, size_t n, double lo0,
                                                           double lo1, double lo2, double s0, double s1, double s2,
                                                           uint64_t* __restrict__ keys, uint32_t* flags,
-                                                          uint32_t* hist0, uint32_t hmask) {
+                                                          uint32_t* hist0, uint32_t hmask, uint32_t hshift) {
     __shared__ uint16_t two[kStates * 64];
     __shared__ uint16_t first[8];
     __shared__ uint32_t h[512];
@@ -201,8 +201,8 @@ __global__ __launch_bounds__(kKeysBlockPlain) void keys_kernel(const double* __r
             k.y = key_of<CURVE>(cx.y, cy.y, cz.y, lo0, lo1, lo2, s0, s1, s2, two, first);
             k2[p] = k;
             if (hist0) {
-                atomicAdd(&h[k.x & hmask], 1u);
-                atomicAdd(&h[k.y & hmask], 1u);
+                atomicAdd(&h[(k.x >> hshift) & hmask], 1u);
+                atomicAdd(&h[(k.y >> hshift) & hmask], 1u);
             }
         }
         if ((n & 1) && t0 == 0) {
@@ -210,7 +210,7 @@ __global__ __launch_bounds__(kKeysBlockPlain) void keys_kernel(const double* __r
             bad |= !finite3(x[p], y[p], z[p]);
             const uint64_t k = key_of<CURVE>(x[p], y[p], z[p], lo0, lo1, lo2, s0, s1, s2, two, first);
             keys[p] = k;
-            if (hist0) atomicAdd(&h[k & hmask], 1u);
+            if (hist0) atomicAdd(&h[(k >> hshift) & hmask], 1u);
         }
     } else {
         for (size_t p = t0; p < n; p += stride) {
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(kKeysBlockPlain) void keys_kernel(const double* __r
             bad |= !finite3(cx, cy, cz);
             const uint64_t k = key_of<CURVE>(cx, cy, cz, lo0, lo1, lo2, s0, s1, s2, two, first);
             keys[p] = k;
-            if (hist0) atomicAdd(&h[k & hmask], 1u);
+            if (hist0) atomicAdd(&h[(k >> hshift) & hmask], 1u);
         }
     }
     if (flags && __ballot(bad) != 0ull && lane_id() == 0) atomicOr(flags, CSTONE_FLAG_NONFINITE);
@@ -232,9 +232,9 @@ __global__ __launch_bounds__(kKeysBlockPlain) void keys_kernel(const double* __r
 template <int CURVE, bool PAIRED>
 void launch_keys_t(size_t blocks, hipStream_t stream, const double* x, const double* y, const double* z, size_t n,
                    const cstone_box& box, const double* s, uint64_t* keys, uint32_t* flags, uint32_t* hist0,
-                   uint32_t hmask) {
+                   uint32_t hmask, uint32_t hshift) {
     hipLaunchKernelGGL((keys_kernel<CURVE, PAIRED>), dim3(blocks), dim3(kKeysBlockPlain), 0, stream, x, y, z, n,
-                       box.lo[0], box.lo[1], box.lo[2], s[0], s[1], s[2], keys, flags, hist0, hmask);
+                       box.lo[0], box.lo[1], box.lo[2], s[0], s[1], s[2], keys, flags, hist0, hmask, hshift);
 }
 
 // Batched keys: block b encodes tile tiles[b] = {first particle, count, -, set}
@@ -294,9 +294,9 @@ cstone_status launch_keys_batch(const double* x, const double* y, const double* 
 
 cstone_status launch_keys(const double* x, const double* y, const double* z, size_t n, const cstone_box& box,
                           cstone_curve curve, uint64_t* keys, uint32_t* flags, hipStream_t stream, uint32_t* hist0,
-                          uint32_t hist_mask) {
+                          uint32_t hist_mask, uint32_t hist_shift) {
     if (n == 0) return CSTONE_OK;
-    if (hist0 && hist_mask >= 512) return CSTONE_ERR_INVALID_ARG;
+    if (hist0 && (hist_mask >= 512 || hist_shift >= 64)) return CSTONE_ERR_INVALID_ARG;
     double s[3];
     for (int d = 0; d < 3; ++d) s[d] = 2097152.0 / (box.hi[d] - box.lo[d]);
     auto aligned = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; };
@@ -306,14 +306,14 @@ cstone_status launch_keys(const double* x, const double* y, const double* z, siz
     if (blocks > kKeysMaxBlocks) blocks = kKeysMaxBlocks;  // grid-stride beyond that
     if (curve == CSTONE_HILBERT) {
         if (paired)
-            launch_keys_t<CSTONE_HILBERT, true>(blocks, stream, x, y, z, n, box, s, keys, flags, hist0, hist_mask);
+            launch_keys_t<CSTONE_HILBERT, true>(blocks, stream, x, y, z, n, box, s, keys, flags, hist0, hist_mask, hist_shift);
         else
-            launch_keys_t<CSTONE_HILBERT, false>(blocks, stream, x, y, z, n, box, s, keys, flags, hist0, hist_mask);
+            launch_keys_t<CSTONE_HILBERT, false>(blocks, stream, x, y, z, n, box, s, keys, flags, hist0, hist_mask, hist_shift);
     } else {
         if (paired)
-            launch_keys_t<CSTONE_MORTON, true>(blocks, stream, x, y, z, n, box, s, keys, flags, hist0, hist_mask);
+            launch_keys_t<CSTONE_MORTON, true>(blocks, stream, x, y, z, n, box, s, keys, flags, hist0, hist_mask, hist_shift);
         else
-            launch_keys_t<CSTONE_MORTON, false>(blocks, stream, x, y, z, n, box, s, keys, flags, hist0, hist_mask);
+            launch_keys_t<CSTONE_MORTON, false>(blocks, stream, x, y, z, n, box, s, keys, flags, hist0, hist_mask, hist_shift);
     }
     CS_HIP(hipGetLastError());
     return CSTONE_OK;

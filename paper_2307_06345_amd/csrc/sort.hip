@@ -37,15 +37,16 @@ __global__ __launch_bounds__(256) void sort_init_kernel(uint32_t* ghist, size_t 
     }
 }
 
-// Counts of the lowest digit (mask = radix - 1).
+// Counts of the first pass's digit ((key >> shift) & mask, mask = radix - 1).
 __global__ __launch_bounds__(kHistBlock) void sort_hist0_kernel(const uint64_t* __restrict__ keys, uint32_t n,
-                                                                 uint32_t mask, uint32_t* __restrict__ ghist) {
+                                                                 uint32_t shift, uint32_t mask,
+                                                                 uint32_t* __restrict__ ghist) {
     __shared__ uint32_t h[kMaxRadix];
     for (int i = threadIdx.x; i < kMaxRadix; i += kHistBlock) h[i] = 0;
     __syncthreads();
     const uint32_t stride = gridDim.x * kHistBlock;
     for (uint32_t i = blockIdx.x * kHistBlock + threadIdx.x; i < n; i += stride)
-        atomicAdd(&h[static_cast<uint32_t>(keys[i]) & mask], 1u);
+        atomicAdd(&h[static_cast<uint32_t>(keys[i] >> shift) & mask], 1u);
     __syncthreads();
     for (int i = threadIdx.x; i <= static_cast<int>(mask); i += kHistBlock)
         if (h[i]) atomicAdd(&ghist[i], h[i]);
@@ -361,7 +362,8 @@ __global__ __launch_bounds__(BLOCK, (kMinBlocks<BLOCK, ITEMS>)) void onesweep_se
                                                               uint32_t hist_stride, const uint4* __restrict__ tiles,
                                                               const uint32_t* __restrict__ seg_base,
                                                               typename LB::word* lb, typename LB::word* lb_clear,
-                                                              uint32_t epoch, uint32_t* err) {
+                                                              uint32_t epoch, uint32_t* err,
+                                                              const uint32_t* __restrict__ live_tiles) {
     constexpr int RADIX = 1 << BITS;
     constexpr int W = BLOCK / kWave;
     constexpr int TILE = BLOCK * ITEMS;
@@ -373,10 +375,13 @@ __global__ __launch_bounds__(BLOCK, (kMinBlocks<BLOCK, ITEMS>)) void onesweep_se
     __shared__ uint64_t scan_tmp[W];
     const uint32_t tid = threadIdx.x;
     const uint32_t tile = tile_of_block<XG>(blockIdx.x, gridDim.x);
+    // a tile table written on the device: blocks past its length have nothing to do
+    if (live_tiles && tile >= *live_tiles) return;
+    const uint4 t = tiles[tile];
+    if (live_tiles && (t.y == 0 || t.y > static_cast<uint32_t>(TILE) || t.x > n - t.y)) return;
     if (lb_clear && tid < RADIX) lb_clear[static_cast<size_t>(tile) * RADIX + tid] = 0;
     for (int i = tid; i < W * RADIX; i += BLOCK) (&whist[0][0])[i] = 0;
     if (tid < RADIX) nhist[tid] = 0;
-    const uint4 t = tiles[tile];
     const TileDesc td{tile, t.x, t.y, t.z, seg_base[t.w]};
     const uint32_t* gh = ghist + static_cast<size_t>(t.w) * hist_stride;
     uint32_t* gn = ghist_next ? ghist_next + static_cast<size_t>(t.w) * hist_stride : nullptr;
@@ -388,6 +393,294 @@ __global__ __launch_bounds__(BLOCK, (kMinBlocks<BLOCK, ITEMS>)) void onesweep_se
         onesweep_tile<BITS, BLOCK, ITEMS, WIN, FIRST, WITH_VALUES, LB, false>(
             td, keys_in, vals_in, keys_out, vals_out, n, shift, gh, gn, shift_next, lb, epoch, err, stage, whist,
             nhist, ddelta, scan_tmp);
+}
+
+// ---- prefix split: the top two digits, then every bucket on its own ---------
+//
+// For particle keys the two most significant digits (18 bits: the level-6
+// octant of a key) are sorted first, by two onesweep passes. The keys then
+// form runs of one prefix ("buckets"), each still in input order. A block
+// owns the buckets that start in its chunk of kLocalChunk keys and sorts each
+// segment of at most kLocalCap keys in LDS, by an LSD sort over only the bits
+// in which the segment's keys differ (stable, so input order is kept among
+// equal keys). A bucket longer than kLocalCap is listed instead; the listed
+// buckets are sorted on their low bits by segmented onesweep passes whose tile
+// table the listing blocks write.
+
+constexpr int kLocalBlock = 512;
+constexpr int kLocalItems = 8;
+constexpr uint32_t kLocalCap = kLocalBlock * kLocalItems;  // keys one block holds and sorts in LDS
+constexpr uint32_t kLocalLook = 512;                        // look-ahead past the chunk for its last bucket's end
+constexpr uint32_t kLocalChunk = kLocalCap - kLocalLook;    // a block owns the buckets starting in its chunk
+constexpr uint32_t kErrLarge = 2u;                          // bucket list overflow (not reachable by the sizing)
+
+struct LargeList {
+    uint32_t* count;  // [0] buckets listed, [1] tiles listed
+    uint4* tiles;     // {first key, key count, first tile of the bucket, bucket}
+    uint32_t* start;  // first key of each bucket
+    uint32_t* hist;   // per bucket: digit counts of every low pass (stride words)
+    void* lb;         // look-back rows of the first low pass (32- or 64-bit words)
+    uint32_t stride, row_words, tile, max_buckets, max_tiles, wide;
+};
+
+template <int BITS, int BLOCK, int ITEMS>
+struct LocalSmem {
+    uint64_t keys[BLOCK * ITEMS];
+    uint32_t vals[BLOCK * ITEMS];
+    uint16_t whist[BLOCK / kWave][1 << BITS];
+    uint32_t scan[BLOCK / kWave];
+    uint64_t bits[BLOCK / kWave];
+    uint32_t first, last, end, slot, tile0;
+};
+
+__device__ __forceinline__ uint64_t wave_or64(uint64_t v) {
+    uint32_t lo = static_cast<uint32_t>(v), hi = static_cast<uint32_t>(v >> 32);
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) {
+        lo |= __shfl_xor(lo, d, kWave);
+        hi |= __shfl_xor(hi, d, kWave);
+    }
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+// First index >= from whose key is >= bound, for keys ordered by prefix and a
+// bound whose bits below the prefix are zero (so "key < bound" holds on a
+// leading run). One wave: lane l probes from + 2^l - 1, then the bracket the
+// probes leave is searched 64 ways per step. All lanes must call it.
+__device__ __forceinline__ uint32_t run_end(const uint64_t* __restrict__ a, uint32_t n, uint32_t from, uint64_t bound) {
+    const uint32_t lane = lane_id();
+    const uint64_t probe = static_cast<uint64_t>(from) + ((1ull << (lane & 31u)) - 1u);
+    const bool beyond = lane >= 32u || probe >= n || a[probe] >= bound;
+    const uint32_t f = static_cast<uint32_t>(__builtin_ctzll(__ballot(beyond)));  // lanes >= 32 are set
+    const uint64_t lo = f ? static_cast<uint64_t>(from) + (1ull << (f - 1)) : from;  // probe f-1 lies in the run
+    const uint64_t pf = static_cast<uint64_t>(from) + ((1ull << f) - 1u);
+    const uint64_t hi = f < 32u && pf < n ? pf : n;  // probe f (or the end) is past it
+    return wave_lower_bound(a, static_cast<uint32_t>(lo), static_cast<uint32_t>(hi), bound);
+}
+
+// Sort keys [a, a + m) with their values (1 <= m <= BLOCK * ITEMS) into the
+// same places of kout / vout, reading them from the block's window in LDS
+// (at window offset a - wlo) if `in_lds`, else from kin / vin. Keys sit in a
+// wave-blocked layout, so the ballot ranks follow input order and every pass
+// is stable.
+template <int BITS, int BLOCK, int ITEMS>
+__device__ __forceinline__ void lds_sort_segment(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                 uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                 uint32_t a, uint32_t m, bool in_lds, uint32_t wlo,
+                                                 LocalSmem<BITS, BLOCK, ITEMS>& sm) {
+    constexpr int RADIX = 1 << BITS;
+    constexpr int W = BLOCK / kWave;
+    static_assert(BLOCK >= RADIX, "one digit per thread in the digit loops");
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    const uint32_t wbase = wave * ITEMS * kWave;
+    const uint32_t off = a - wlo;
+    const uint64_t k0 = in_lds ? sm.keys[off] : kin[a];
+    uint64_t k[ITEMS];
+    uint32_t v[ITEMS];
+    uint64_t diff = 0;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t p = wbase + i * kWave + lane;
+        const bool ok = p < m;
+        if (in_lds) {
+            k[i] = ok ? sm.keys[off + p] : k0;
+            v[i] = ok ? sm.vals[off + p] : 0u;
+        } else {
+            k[i] = ok ? kin[a + p] : k0;
+            v[i] = ok ? vin[a + p] : 0u;
+        }
+        diff |= k[i] ^ k0;
+    }
+    // only the bits in which the segment's keys differ need sorting
+    diff = wave_or64(diff);
+    if (lane == 0) sm.bits[wave] = diff;
+    __syncthreads();
+    uint64_t all = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) all |= sm.bits[w];
+    const int passes = (64 - clz64(all) + BITS - 1) / BITS;
+    for (int pass = 0; pass < passes; ++pass) {
+        const uint32_t shift = static_cast<uint32_t>(pass * BITS);
+        for (int i = tid; i < W * RADIX; i += BLOCK) (&sm.whist[0][0])[i] = 0;
+        __syncthreads();
+        uint32_t rank[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const bool ok = wbase + i * kWave + lane < m;
+            const uint32_t d = digit_of<BITS>(k[i], shift);
+            const uint64_t peers = match_digit<BITS>(d, __ballot(ok));
+            const uint32_t below = lanes_below(peers);
+            const uint32_t base = sm.whist[wave][d];
+            if (ok && below == 0) sm.whist[wave][d] = static_cast<uint16_t>(base + static_cast<uint32_t>(__popcll(peers)));
+            rank[i] = base + below;
+        }
+        __syncthreads();
+        uint32_t total = 0;
+        if (tid < RADIX) {
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                const uint32_t c = sm.whist[w][tid];
+                sm.whist[w][tid] = static_cast<uint16_t>(total);
+                total += c;
+            }
+        }
+        uint32_t sum;
+        const uint32_t start = block_exclusive_sum<uint32_t, BLOCK>(total, sm.scan, &sum);
+        if (tid < RADIX) {
+#pragma unroll
+            for (int w = 0; w < W; ++w) sm.whist[w][tid] += static_cast<uint16_t>(start);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            if (wbase + i * kWave + lane < m) {
+                const uint32_t dst = sm.whist[wave][digit_of<BITS>(k[i], shift)] + rank[i];
+                sm.keys[dst] = k[i];
+                sm.vals[dst] = v[i];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t p = wbase + i * kWave + lane;
+            if (p < m) {
+                k[i] = sm.keys[p];
+                v[i] = sm.vals[p];
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t p = wbase + i * kWave + lane;
+        if (p < m) {
+            kout[a + p] = k[i];
+            vout[a + p] = v[i];
+        }
+    }
+    __syncthreads();  // the shared arrays may be reused for another segment
+}
+
+// List bucket [start, start + len) for the low passes: reserve its slot and a
+// run of tiles, write the tiles, and clear its digit counts and the look-back
+// rows its first low pass will use.
+template <int BITS, int BLOCK, int ITEMS>
+__device__ __forceinline__ void list_large(const LargeList& L, uint32_t start, uint32_t len, uint32_t* err,
+                           LocalSmem<BITS, BLOCK, ITEMS>& sm) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t tiles = (len + L.tile - 1) / L.tile;
+    if (tid == 0) {
+        uint32_t b = atomicAdd(&L.count[0], 1u);
+        const uint32_t t0 = atomicAdd(&L.count[1], tiles);
+        if (b >= L.max_buckets || t0 > L.max_tiles - tiles) {
+            atomicOr(err, kErrLarge);
+            b = 0xffffffffu;
+        }
+        sm.slot = b;
+        sm.tile0 = t0;
+    }
+    __syncthreads();
+    const uint32_t b = sm.slot, t0 = sm.tile0;
+    if (b == 0xffffffffu) return;
+    if (tid == 0) L.start[b] = start;
+    for (uint32_t t = tid; t < tiles; t += BLOCK)
+        L.tiles[t0 + t] = make_uint4(start + t * L.tile, min(L.tile, len - t * L.tile), t0, b);
+    uint32_t* h = L.hist + static_cast<size_t>(b) * L.stride;
+    for (uint32_t i = tid; i < L.stride; i += BLOCK) h[i] = 0;
+    const size_t w0 = static_cast<size_t>(t0) * L.row_words, w1 = static_cast<size_t>(t0 + tiles) * L.row_words;
+    if (L.wide) {
+        for (size_t i = w0 + tid; i < w1; i += BLOCK) static_cast<uint64_t*>(L.lb)[i] = 0;
+    } else {
+        for (size_t i = w0 + tid; i < w1; i += BLOCK) static_cast<uint32_t*>(L.lb)[i] = 0;
+    }
+}
+
+// Block b: the buckets (runs of equal key >> pshift) that start in keys
+// [b * chunk, (b + 1) * chunk), read from kin / vin, sorted into kout / vout.
+// The block reads its chunk and the look-ahead after it into LDS at once; only
+// a last bucket that runs past the look-ahead is searched for and read again.
+template <int BITS, int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK, 2 * BLOCK / (4 * kWave)) void local_sort_kernel(
+    const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
+    uint32_t* __restrict__ vout, uint32_t n, uint32_t pshift, LargeList large, uint32_t* err) {
+    constexpr uint32_t CAP = BLOCK * ITEMS, CHUNK = kLocalChunk;
+    static_assert(CHUNK < CAP, "the window holds the chunk and a look-ahead");
+    __shared__ LocalSmem<BITS, BLOCK, ITEMS> sm;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lo = blockIdx.x * CHUNK;
+    const uint32_t hi = static_cast<uint32_t>(min(static_cast<uint64_t>(n), static_cast<uint64_t>(lo) + CHUNK));
+    const uint32_t wend = static_cast<uint32_t>(min(static_cast<uint64_t>(n), static_cast<uint64_t>(lo) + CAP));
+    const uint32_t wn = wend - lo, own = hi - lo;
+    if (tid == 0) {
+        sm.first = 0xffffffffu;
+        sm.last = 0u;
+        sm.end = 0xffffffffu;
+    }
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t j = static_cast<uint32_t>(i) * BLOCK + tid;
+        if (j < wn) {
+            sm.keys[j] = kin[lo + j];
+            sm.vals[j] = vin[lo + j];
+        }
+    }
+    const uint64_t before = lo ? kin[lo - 1] >> pshift : ~0ull;  // the same word in every lane
+    __syncthreads();
+    // bucket starts: the first and last in the chunk, the first after it
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t j = static_cast<uint32_t>(i) * BLOCK + tid;
+        if (j < wn) {
+            const uint64_t pj = sm.keys[j] >> pshift;
+            const uint64_t pp = j ? sm.keys[j - 1] >> pshift : before;
+            if (pj != pp) {
+                if (j < own) {
+                    atomicMin(&sm.first, j);
+                    atomicMax(&sm.last, j);
+                } else {
+                    atomicMin(&sm.end, j);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t f = sm.first, l = sm.last;
+    if (f == 0xffffffffu) return;  // no bucket starts here
+    const uint64_t last_prefix = sm.keys[l] >> pshift;
+    uint32_t e = sm.end;
+    if (e == 0xffffffffu && wend == n) e = wn;  // the last bucket ends with the keys
+    if (e != 0xffffffffu) {
+        lds_sort_segment<BITS, BLOCK, ITEMS>(kin, vin, kout, vout, lo + f, e - f, true, lo, sm);
+        return;
+    }
+    // the last bucket runs past the window: the buckets before it from LDS, then it alone
+    if (l > f) lds_sort_segment<BITS, BLOCK, ITEMS>(kin, vin, kout, vout, lo + f, l - f, true, lo, sm);
+    if (tid < kWave) {
+        const uint32_t ee = run_end(kin, n, wend, (last_prefix + 1u) << pshift);
+        if (tid == 0) sm.end = ee;
+    }
+    __syncthreads();
+    const uint32_t start = lo + l, len = sm.end - start;
+    if (len <= CAP)
+        lds_sort_segment<BITS, BLOCK, ITEMS>(kin, vin, kout, vout, start, len, false, lo, sm);
+    else
+        list_large<BITS, BLOCK, ITEMS>(large, start, len, err, sm);
+}
+
+// Counts of the lowest digit in every listed tile, into its bucket's row.
+__global__ __launch_bounds__(512) void large_hist_kernel(const uint64_t* __restrict__ keys, uint32_t n,
+                                                         LargeList L, uint32_t mask) {
+    __shared__ uint32_t h[kMaxRadix];
+    const uint32_t tile = blockIdx.x;
+    if (tile >= L.count[1]) return;
+    const uint4 t = L.tiles[tile];
+    if (t.y == 0 || t.y > L.tile || t.x > n - t.y || t.w >= L.max_buckets) return;
+    for (uint32_t i = threadIdx.x; i <= mask; i += 512) h[i] = 0;
+    __syncthreads();
+    for (uint32_t j = t.x + threadIdx.x; j < t.x + t.y; j += 512) atomicAdd(&h[static_cast<uint32_t>(keys[j]) & mask], 1u);
+    __syncthreads();
+    uint32_t* g = L.hist + static_cast<size_t>(t.w) * L.stride;
+    for (uint32_t i = threadIdx.x; i <= mask; i += 512)
+        if (h[i]) atomicAdd(&g[i], h[i]);
 }
 
 // ---- variants ------------------------------------------------------------------
@@ -436,8 +729,9 @@ void launch_pass_t(const PassArgs& a, bool first, bool with_values, hipStream_t 
 struct SegArgs {
     const uint4* tiles;
     const uint32_t* seg_base;
-    uint32_t n_tiles;
+    uint32_t n_tiles;  // blocks launched
     uint32_t hist_stride;
+    const uint32_t* live_tiles;  // NULL, or the device word holding how many tiles are in use
 };
 
 template <int BITS, int BLOCK, int ITEMS, int WIN, bool FIRST, bool VALS, int XG>
@@ -447,12 +741,12 @@ void launch_one_seg(const PassArgs& a, const SegArgs& g, hipStream_t stream) {
         hipLaunchKernelGGL((onesweep_seg_kernel<BITS, BLOCK, ITEMS, WIN, FIRST, VALS, Lb64, XG>), grid, block, 0, stream,
                            a.keys_in, a.vals_in, a.keys_out, a.vals_out, a.n, a.shift, a.ghist, a.ghist_next,
                            a.shift_next, g.hist_stride, g.tiles, g.seg_base, static_cast<uint64_t*>(a.lb), nullptr,
-                           a.epoch, a.err);
+                           a.epoch, a.err, g.live_tiles);
     else
         hipLaunchKernelGGL((onesweep_seg_kernel<BITS, BLOCK, ITEMS, WIN, FIRST, VALS, Lb32, XG>), grid, block, 0, stream,
                            a.keys_in, a.vals_in, a.keys_out, a.vals_out, a.n, a.shift, a.ghist, a.ghist_next,
                            a.shift_next, g.hist_stride, g.tiles, g.seg_base, static_cast<uint32_t*>(a.lb),
-                           static_cast<uint32_t*>(a.lb_clear), a.epoch, a.err);
+                           static_cast<uint32_t*>(a.lb_clear), a.epoch, a.err, g.live_tiles);
 }
 
 template <int BITS, int BLOCK, int ITEMS, int WIN, int XG>
@@ -496,6 +790,14 @@ int default_variant() {
     return t >= 0 ? t : builtin_variant();
 }
 
+// Split sorts of particle keys: 9-bit digits, the top two first, then five low
+// passes for the listed buckets (63 = 2 * 9 + 45 bits).
+constexpr int kSplitBits = 9;
+constexpr int kSplitTop = 2;
+constexpr int kLowPasses = 5;
+constexpr uint32_t kSplitShift = 63 - kSplitTop * kSplitBits;  // the prefix is key >> 45
+constexpr int kGhistWords = kMaxPasses * kMaxRadix + 64;      // digit counts, then the bucket-list counters
+
 struct SortWs {
     uint64_t* keys_alt;
     uint32_t* vals_alt;
@@ -503,7 +805,13 @@ struct SortWs {
     uint32_t* err;
     void* lb;  // two row sets of 32-bit words, or one of 64-bit words
     size_t lb_bytes;
-    size_t rows;  // tiles of the smallest tile size
+    size_t rows;  // look-back rows: tiles of the smallest tile size, plus the listed buckets' extra tiles
+    // bucket list of a split sort (with_perm only)
+    uint32_t* large_count;
+    uint4* large_tiles;
+    uint32_t* large_start;
+    uint32_t* large_hist;
+    size_t max_buckets, max_tiles_any;
     size_t bytes;
 };
 
@@ -512,22 +820,46 @@ SortWs carve_sort(void* ws, size_t n, bool with_perm) {
     SortWs s{};
     s.keys_alt = c.take<uint64_t>(n);
     s.vals_alt = with_perm ? c.take<uint32_t>(n) : nullptr;
-    s.ghist = c.take<uint32_t>(kMaxPasses * kMaxRadix);
+    s.ghist = c.take<uint32_t>(kGhistWords);
+    s.large_count = s.ghist + kMaxPasses * kMaxRadix;
     s.err = c.take<uint32_t>(1);
-    s.rows = (n + kMinTile - 1) / kMinTile;
+    // a listed bucket holds more than kLocalCap keys; its tiles number at most
+    // its keys / tile + 1
+    s.max_buckets = with_perm ? n / (kLocalCap + 1) : 0;
+    s.max_tiles_any = (n + kMinTile - 1) / kMinTile + s.max_buckets;
+    s.rows = s.max_tiles_any;
     s.lb_bytes = s.rows * kMaxRadix * 8;  // 2 x 32-bit sets, or 1 x 64-bit set
     s.lb = c.take<uint8_t>(s.lb_bytes);
+    if (with_perm) {
+        s.large_tiles = c.take<uint4>(s.max_tiles_any);
+        s.large_start = c.take<uint32_t>(s.max_buckets + 1);
+        s.large_hist = c.take<uint32_t>((s.max_buckets + 1) * kLowPasses * kMaxRadix);
+    }
     s.bytes = c.off;
     return s;
+}
+
+bool split_enabled() {
+    static const bool on = [] {
+        const char* e = std::getenv("CSTONE_SORT_SPLIT");
+        return !(e && e[0] == '0');
+    }();
+    return on;
+}
+
+// Whether a sort of n particle keys takes the split path.
+bool use_split(size_t n, int sig_bits, bool with_perm, const Variant& var) {
+    return split_enabled() && with_perm && sig_bits == 63 && var.bits == kSplitBits && n > 0;
 }
 
 }  // namespace
 
 size_t sort_workspace_bytes(size_t n, bool with_perm) { return carve_sort(nullptr, n, with_perm).bytes; }
 
-int sort_passes(int sig_bits) {
-    const int bits = kVariants[default_variant()].bits;
-    return (sig_bits + bits - 1) / bits;
+int sort_passes(size_t n, int sig_bits, bool with_perm) {
+    const Variant& var = kVariants[default_variant()];
+    if (use_split(n, sig_bits, with_perm, var)) return kSplitTop + 2;  // top passes, buckets, low passes
+    return (sig_bits + var.bits - 1) / var.bits;
 }
 
 cstone_status sort_prepare(void* ws, size_t n, bool with_perm, hipStream_t stream, uint32_t* clear_word,
@@ -542,16 +874,96 @@ cstone_status sort_prepare(void* ws, size_t n, bool with_perm, hipStream_t strea
     const size_t lb_words = std::min(s.lb_bytes / 8, wide ? words : (words + 1) / 2);
     const size_t init_grid = std::max<size_t>(4, std::min<size_t>((lb_words + 255) / 256, 1024));
     hipLaunchKernelGGL(sort_init_kernel, dim3(init_grid), dim3(256), 0, stream, s.ghist,
-                       static_cast<size_t>(kMaxPasses) * kMaxRadix, s.err, static_cast<uint64_t*>(s.lb), lb_words,
-                       clear_word);
+                       static_cast<size_t>(kGhistWords), s.err, static_cast<uint64_t*>(s.lb), lb_words, clear_word);
     CS_HIP(hipGetLastError());
     return CSTONE_OK;
 }
 
-uint32_t* sort_first_histogram(void* ws, size_t n, bool with_perm, uint32_t* mask) {
-    *mask = (1u << kVariants[default_variant()].bits) - 1u;
+uint32_t* sort_first_histogram(void* ws, size_t n, bool with_perm, int sig_bits, uint32_t* mask, uint32_t* shift) {
+    const Variant& var = kVariants[default_variant()];
+    *mask = (1u << var.bits) - 1u;
+    *shift = use_split(n, sig_bits, with_perm, var) ? kSplitShift : 0u;
     return carve_sort(ws, n, with_perm).ghist;
 }
+
+namespace {
+
+// Split sort (see the prefix-split kernels): top passes keys_in -> keys_out ->
+// alt, buckets alt -> keys_out, low passes over the listed buckets alt ->
+// keys_out -> ... -> keys_out (five of them).
+cstone_status launch_split(const uint64_t* keys_in, uint64_t* keys_out, uint32_t* perm_out, size_t n,
+                           const SortWs& s, const Variant& var, bool wide, hipStream_t stream,
+                           hipEvent_t* pass_events) {
+    constexpr int radix = 1 << kSplitBits;
+    uint32_t* lb32[2] = {static_cast<uint32_t*>(s.lb), static_cast<uint32_t*>(s.lb) + s.rows * kMaxRadix};
+    if (pass_events) CS_HIP(hipEventRecord(pass_events[0], stream));
+    for (int p = 0; p < kSplitTop; ++p) {
+        PassArgs a{};
+        a.keys_in = p == 0 ? keys_in : keys_out;
+        a.vals_in = p == 0 ? nullptr : perm_out;
+        a.keys_out = p == 0 ? keys_out : s.keys_alt;
+        a.vals_out = p == 0 ? perm_out : s.vals_alt;
+        a.n = static_cast<uint32_t>(n);
+        a.shift = kSplitShift + p * kSplitBits;
+        a.ghist = s.ghist + p * radix;
+        a.ghist_next = p + 1 < kSplitTop ? s.ghist + (p + 1) * radix : nullptr;
+        a.shift_next = kSplitShift + (p + 1) * kSplitBits;
+        a.wide = wide;
+        a.lb = wide ? s.lb : static_cast<void*>(lb32[p & 1]);
+        a.lb_clear = (!wide && p + 1 < kSplitTop) ? static_cast<void*>(lb32[(p + 1) & 1]) : nullptr;
+        a.epoch = static_cast<uint32_t>(p + 1);
+        a.err = s.err;
+        var.launch(a, p == 0, true, stream);
+        if (pass_events) CS_HIP(hipEventRecord(pass_events[p + 1], stream));
+    }
+    const uint32_t tile = static_cast<uint32_t>(var.block * var.items);
+    LargeList L{};
+    L.count = s.large_count;
+    L.tiles = s.large_tiles;
+    L.start = s.large_start;
+    L.hist = s.large_hist;
+    L.lb = wide ? s.lb : static_cast<void*>(lb32[0]);
+    L.stride = kLowPasses * kMaxRadix;
+    L.row_words = kMaxRadix;
+    L.tile = tile;
+    L.max_buckets = static_cast<uint32_t>(s.max_buckets);
+    L.max_tiles = static_cast<uint32_t>((n + tile - 1) / tile + s.max_buckets);
+    L.wide = wide ? 1u : 0u;
+    const uint32_t chunks = static_cast<uint32_t>((n + kLocalChunk - 1) / kLocalChunk);
+    hipLaunchKernelGGL((local_sort_kernel<kSplitBits, kLocalBlock, kLocalItems>), dim3(chunks), dim3(kLocalBlock), 0,
+                       stream, s.keys_alt, s.vals_alt, keys_out, perm_out, static_cast<uint32_t>(n), kSplitShift, L,
+                       s.err);
+    if (pass_events) CS_HIP(hipEventRecord(pass_events[kSplitTop + 1], stream));
+    if (s.max_buckets > 0) {  // some bucket may be longer than one block sorts
+        hipLaunchKernelGGL(large_hist_kernel, dim3(L.max_tiles), dim3(512), 0, stream, s.keys_alt,
+                           static_cast<uint32_t>(n), L, static_cast<uint32_t>(radix - 1));
+        SegArgs g{s.large_tiles, s.large_start, L.max_tiles, L.stride, s.large_count + 1};
+        for (int p = 0; p < kLowPasses; ++p) {
+            const bool from_alt = (p % 2) == 0;
+            PassArgs a{};
+            a.keys_in = from_alt ? s.keys_alt : keys_out;
+            a.vals_in = from_alt ? s.vals_alt : perm_out;
+            a.keys_out = from_alt ? keys_out : s.keys_alt;
+            a.vals_out = from_alt ? perm_out : s.vals_alt;
+            a.n = static_cast<uint32_t>(n);
+            a.shift = static_cast<uint32_t>(p * kSplitBits);
+            a.ghist = s.large_hist + p * radix;
+            a.ghist_next = p + 1 < kLowPasses ? s.large_hist + (p + 1) * radix : nullptr;
+            a.shift_next = static_cast<uint32_t>((p + 1) * kSplitBits);
+            a.wide = wide;
+            a.lb = wide ? s.lb : static_cast<void*>(lb32[p & 1]);
+            a.lb_clear = (!wide && p + 1 < kLowPasses) ? static_cast<void*>(lb32[(p + 1) & 1]) : nullptr;
+            a.epoch = static_cast<uint32_t>(kSplitTop + 1 + p);
+            a.err = s.err;
+            var.launch_seg(a, g, false, true, stream);
+        }
+    }
+    if (pass_events) CS_HIP(hipEventRecord(pass_events[kSplitTop + 2], stream));
+    CS_HIP(hipGetLastError());
+    return CSTONE_OK;
+}
+
+}  // namespace
 
 cstone_status launch_sort(const uint64_t* keys_in, uint64_t* keys_out, uint32_t* perm_out, size_t n,
                           int sig_bits, void* ws, size_t ws_bytes, hipStream_t stream, hipEvent_t* pass_events,
@@ -569,14 +981,17 @@ cstone_status launch_sort(const uint64_t* keys_in, uint64_t* keys_out, uint32_t*
     if (passes < 1 || passes > kMaxPasses) return CSTONE_ERR_INVALID_ARG;
     const bool wide = n >= (1ull << 30);  // 30-bit look-back values otherwise
 
+    const bool split = use_split(n, sig_bits, with_perm, var);
     if (!prepared) {
         cstone_status st = sort_prepare(ws, n, with_perm, stream, nullptr, variant);
         if (st != CSTONE_OK) return st;
         const size_t hblocks =
             std::max<size_t>(1, std::min<size_t>((n + kHistBlock * 16 - 1) / (kHistBlock * 16), 1024));
         hipLaunchKernelGGL(sort_hist0_kernel, dim3(hblocks), dim3(kHistBlock), 0, stream, keys_in,
-                           static_cast<uint32_t>(n), static_cast<uint32_t>(radix - 1), s.ghist);
+                           static_cast<uint32_t>(n), split ? kSplitShift : 0u, static_cast<uint32_t>(radix - 1),
+                           s.ghist);
     }
+    if (split) return launch_split(keys_in, keys_out, perm_out, n, s, var, wide, stream, pass_events);
 
     uint32_t* lb32[2] = {static_cast<uint32_t*>(s.lb), static_cast<uint32_t*>(s.lb) + s.rows * kMaxRadix};
     if (pass_events) CS_HIP(hipEventRecord(pass_events[0], stream));
@@ -694,7 +1109,7 @@ cstone_status launch_sort_segmented(const uint64_t* keys_in, uint64_t* keys_out,
     if (passes < 1 || static_cast<uint32_t>(passes * radix) > s.stride) return CSTONE_ERR_INVALID_ARG;
     const bool wide = max_set >= (1ull << 30);
     uint32_t* lb32[2] = {static_cast<uint32_t*>(s.lb), static_cast<uint32_t*>(s.lb) + s.rows * kMaxRadix};
-    SegArgs g{tiles, seg_base, n_tiles, s.stride};
+    SegArgs g{tiles, seg_base, n_tiles, s.stride, nullptr};
     const uint64_t* src_k = keys_in;
     const uint32_t* src_v = nullptr;
     for (int p = 0; p < passes; ++p) {
