@@ -397,8 +397,8 @@ __global__ __launch_bounds__(BLOCK, (kMinBlocks<BLOCK, ITEMS>)) void onesweep_se
 
 // ---- prefix split: the top two digits, then every bucket on its own ---------
 //
-// For particle keys the two most significant digits (18 bits: the level-6
-// octant of a key) are sorted first, by two onesweep passes. The keys then
+// For particle keys the three most significant digits (27 bits: the level-9
+// octant of a key) are sorted first, by onesweep passes. The keys then
 // form runs of one prefix ("buckets"), each still in input order. A block
 // owns the buckets that start in its chunk of kLocalChunk keys and sorts each
 // segment of at most kLocalCap keys in LDS, by an LSD sort over only the bits
@@ -413,6 +413,7 @@ constexpr uint32_t kLocalCap = kLocalBlock * kLocalItems;  // keys one block hol
 constexpr uint32_t kLocalLook = 512;                        // look-ahead past the chunk for its last bucket's end
 constexpr uint32_t kLocalChunk = kLocalCap - kLocalLook;    // a block owns the buckets starting in its chunk
 constexpr uint32_t kErrLarge = 2u;                          // bucket list overflow (not reachable by the sizing)
+constexpr uint32_t kCountMax = 160;  // buckets up to this size are ranked by counting, larger ones by LDS passes
 
 struct LargeList {
     uint32_t* count;  // [0] buckets listed, [1] tiles listed
@@ -428,10 +429,24 @@ struct LocalSmem {
     uint64_t keys[BLOCK * ITEMS];
     uint32_t vals[BLOCK * ITEMS];
     uint16_t whist[BLOCK / kWave][1 << BITS];
+    uint16_t starts[BLOCK * ITEMS + 1];  // bucket starts of a segment (window positions), then its end
+    uint32_t cnt[ITEMS * (BLOCK / kWave)];
     uint32_t scan[BLOCK / kWave];
     uint64_t bits[BLOCK / kWave];
-    uint32_t first, last, end, slot, tile0;
+    uint32_t first, last, end, slot, tile0, nb, maxb;
 };
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) v = min(v, static_cast<uint32_t>(__shfl_xor(v, d, kWave)));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) v = max(v, static_cast<uint32_t>(__shfl_xor(v, d, kWave)));
+    return v;
+}
 
 __device__ __forceinline__ uint64_t wave_or64(uint64_t v) {
     uint32_t lo = static_cast<uint32_t>(v), hi = static_cast<uint32_t>(v >> 32);
@@ -447,7 +462,7 @@ __device__ __forceinline__ uint64_t wave_or64(uint64_t v) {
 // bound whose bits below the prefix are zero (so "key < bound" holds on a
 // leading run). One wave: lane l probes from + 2^l - 1, then the bracket the
 // probes leave is searched 64 ways per step. All lanes must call it.
-__device__ __forceinline__ uint32_t run_end(const uint64_t* __restrict__ a, uint32_t n, uint32_t from, uint64_t bound) {
+__device__ __forceinline__ uint32_t run_end(const uint64_t* a, uint32_t n, uint32_t from, uint64_t bound) {
     const uint32_t lane = lane_id();
     const uint64_t probe = static_cast<uint64_t>(from) + ((1ull << (lane & 31u)) - 1u);
     const bool beyond = lane >= 32u || probe >= n || a[probe] >= bound;
@@ -464,8 +479,8 @@ __device__ __forceinline__ uint32_t run_end(const uint64_t* __restrict__ a, uint
 // wave-blocked layout, so the ballot ranks follow input order and every pass
 // is stable.
 template <int BITS, int BLOCK, int ITEMS>
-__device__ __forceinline__ void lds_sort_segment(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-                                                 uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
+__device__ __forceinline__ void lds_sort_segment(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
+                                                 uint32_t* vout,
                                                  uint32_t a, uint32_t m, bool in_lds, uint32_t wlo,
                                                  LocalSmem<BITS, BLOCK, ITEMS>& sm) {
     constexpr int RADIX = 1 << BITS;
@@ -560,6 +575,87 @@ __device__ __forceinline__ void lds_sort_segment(const uint64_t* __restrict__ ki
     __syncthreads();  // the shared arrays may be reused for another segment
 }
 
+// Sort the buckets at window positions [f, e) (f and e bucket starts, or e the
+// window's end at the end of the keys) into kout / vout. If no bucket is
+// longer than kCountMax, every key is ranked inside its bucket by counting
+// the keys that precede it (smaller, or equal and earlier); otherwise the
+// segment goes through the LDS passes.
+template <int BITS, int BLOCK, int ITEMS>
+__device__ __forceinline__ void lds_sort_window(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
+                                                uint32_t* vout,
+                                                uint32_t n, uint32_t lo, uint32_t f, uint32_t e, uint32_t pshift,
+                                                LocalSmem<BITS, BLOCK, ITEMS>& sm) {
+    constexpr int W = BLOCK / kWave;
+    static_assert(ITEMS * W == kWave, "one wave scans the per-(item, wave) start counts");
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    if (tid == 0) sm.maxb = 0;
+    uint64_t k[ITEMS];
+    uint64_t smask[ITEMS];
+    uint32_t start_bits = 0;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t j = static_cast<uint32_t>(i) * BLOCK + tid;
+        const bool in = j >= f && j < e;
+        k[i] = in ? sm.keys[j] : 0ull;
+        const bool st = in && (j == f || (sm.keys[j - 1] >> pshift) != (k[i] >> pshift));
+        smask[i] = __ballot(st);
+        start_bits |= static_cast<uint32_t>(st) << i;
+        if (lane == 0) sm.cnt[i * W + wave] = static_cast<uint32_t>(__popcll(smask[i]));
+    }
+    __syncthreads();
+    if (wave == 0) {  // (item, wave) pieces in window order: exclusive counts of starts before each
+        const uint32_t c = sm.cnt[lane];
+        const uint32_t inc = wave_inclusive_sum(c);
+        sm.cnt[lane] = inc - c;
+        if (lane == kWave - 1) sm.nb = inc;
+    }
+    __syncthreads();
+    uint32_t id[ITEMS];  // bucket of each key: starts at or before it, minus one
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t j = static_cast<uint32_t>(i) * BLOCK + tid;
+        const uint32_t base = sm.cnt[i * W + wave];
+        const uint32_t below = lanes_below(smask[i]);
+        id[i] = base + below + ((start_bits >> i) & 1u) - 1u;
+        if ((start_bits >> i) & 1u) sm.starts[base + below] = static_cast<uint16_t>(j);
+    }
+    if (tid == 0) sm.starts[sm.nb] = static_cast<uint16_t>(e);
+    __syncthreads();
+    uint32_t longest = 0;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i)
+        if ((start_bits >> i) & 1u) {
+            const uint32_t j = static_cast<uint32_t>(i) * BLOCK + tid;
+            longest = max(longest, static_cast<uint32_t>(sm.starts[id[i] + 1]) - j);
+        }
+    longest = wave_max_u32(longest);
+    if (lane == 0) atomicMax(&sm.maxb, longest);
+    __syncthreads();
+    if (sm.maxb > kCountMax) {
+        lds_sort_segment<BITS, BLOCK, ITEMS>(kin, vin, kout, vout, lo + f, e - f, true, lo, sm);
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t j = static_cast<uint32_t>(i) * BLOCK + tid;
+        if (j >= f && j < e) {
+            const uint32_t bs = sm.starts[id[i]], be = sm.starts[id[i] + 1];
+            const uint64_t kp = k[i];
+            uint32_t rank = 0;
+            for (uint32_t q = bs; q < be; ++q) {
+                const uint64_t kq = sm.keys[q];
+                rank += (kq < kp || (kq == kp && q < j)) ? 1u : 0u;
+            }
+            const uint32_t dst = lo + bs + rank;
+            if (dst < n) {  // always true; guards memory against a logic error
+                kout[dst] = kp;
+                vout[dst] = sm.vals[j];
+            }
+        }
+    }
+    __syncthreads();  // the shared arrays may be reused
+}
+
 // List bucket [start, start + len) for the low passes: reserve its slot and a
 // run of tiles, write the tiles, and clear its digit counts and the look-back
 // rows its first low pass will use.
@@ -598,10 +694,18 @@ __device__ __forceinline__ void list_large(const LargeList& L, uint32_t start, u
 // [b * chunk, (b + 1) * chunk), read from kin / vin, sorted into kout / vout.
 // The block reads its chunk and the look-ahead after it into LDS at once; only
 // a last bucket that runs past the look-ahead is searched for and read again.
+//
+// The sort is in place. A block writes only the buckets it owns; what it
+// reads of other blocks' buckets (the look-ahead, the key before its chunk,
+// the run-end search) it uses only for prefixes, which sorting inside a bucket
+// leaves unchanged at every position.
 template <int BITS, int BLOCK, int ITEMS>
 __global__ __launch_bounds__(BLOCK, 2 * BLOCK / (4 * kWave)) void local_sort_kernel(
-    const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
-    uint32_t* __restrict__ vout, uint32_t n, uint32_t pshift, LargeList large, uint32_t* err) {
+    uint64_t* keys, uint32_t* vals, uint32_t n, uint32_t pshift, LargeList large, uint32_t* err) {
+    const uint64_t* kin = keys;
+    const uint32_t* vin = vals;
+    uint64_t* kout = keys;
+    uint32_t* vout = vals;
     constexpr uint32_t CAP = BLOCK * ITEMS, CHUNK = kLocalChunk;
     static_assert(CHUNK < CAP, "the window holds the chunk and a look-ahead");
     __shared__ LocalSmem<BITS, BLOCK, ITEMS> sm;
@@ -626,6 +730,7 @@ __global__ __launch_bounds__(BLOCK, 2 * BLOCK / (4 * kWave)) void local_sort_ker
     const uint64_t before = lo ? kin[lo - 1] >> pshift : ~0ull;  // the same word in every lane
     __syncthreads();
     // bucket starts: the first and last in the chunk, the first after it
+    uint32_t first = 0xffffffffu, last = 0u, after = 0xffffffffu;
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t j = static_cast<uint32_t>(i) * BLOCK + tid;
@@ -634,13 +739,23 @@ __global__ __launch_bounds__(BLOCK, 2 * BLOCK / (4 * kWave)) void local_sort_ker
             const uint64_t pp = j ? sm.keys[j - 1] >> pshift : before;
             if (pj != pp) {
                 if (j < own) {
-                    atomicMin(&sm.first, j);
-                    atomicMax(&sm.last, j);
+                    first = min(first, j);
+                    last = max(last, j);
                 } else {
-                    atomicMin(&sm.end, j);
+                    after = min(after, j);
                 }
             }
         }
+    }
+    first = wave_min_u32(first);
+    last = wave_max_u32(last);
+    after = wave_min_u32(after);
+    if (lane_id() == 0) {
+        if (first != 0xffffffffu) {
+            atomicMin(&sm.first, first);
+            atomicMax(&sm.last, last);
+        }
+        if (after != 0xffffffffu) atomicMin(&sm.end, after);
     }
     __syncthreads();
     const uint32_t f = sm.first, l = sm.last;
@@ -649,11 +764,11 @@ __global__ __launch_bounds__(BLOCK, 2 * BLOCK / (4 * kWave)) void local_sort_ker
     uint32_t e = sm.end;
     if (e == 0xffffffffu && wend == n) e = wn;  // the last bucket ends with the keys
     if (e != 0xffffffffu) {
-        lds_sort_segment<BITS, BLOCK, ITEMS>(kin, vin, kout, vout, lo + f, e - f, true, lo, sm);
+        lds_sort_window<BITS, BLOCK, ITEMS>(kin, vin, kout, vout, n, lo, f, e, pshift, sm);
         return;
     }
     // the last bucket runs past the window: the buckets before it from LDS, then it alone
-    if (l > f) lds_sort_segment<BITS, BLOCK, ITEMS>(kin, vin, kout, vout, lo + f, l - f, true, lo, sm);
+    if (l > f) lds_sort_window<BITS, BLOCK, ITEMS>(kin, vin, kout, vout, n, lo, f, l, pshift, sm);
     if (tid < kWave) {
         const uint32_t ee = run_end(kin, n, wend, (last_prefix + 1u) << pshift);
         if (tid == 0) sm.end = ee;
@@ -790,12 +905,15 @@ int default_variant() {
     return t >= 0 ? t : builtin_variant();
 }
 
-// Split sorts of particle keys: 9-bit digits, the top two first, then five low
-// passes for the listed buckets (63 = 2 * 9 + 45 bits).
+// Split sorts of particle keys: 9-bit digits, the top three first (the
+// level-9 octant), then four low passes for the listed buckets
+// (63 = 3 * 9 + 36 bits). The top passes end in the output arrays, where the
+// buckets are sorted in place and the low passes end too.
 constexpr int kSplitBits = 9;
-constexpr int kSplitTop = 2;
-constexpr int kLowPasses = 5;
-constexpr uint32_t kSplitShift = 63 - kSplitTop * kSplitBits;  // the prefix is key >> 45
+constexpr int kSplitTop = 3;
+constexpr int kLowPasses = 4;
+constexpr uint32_t kSplitShift = 63 - kSplitTop * kSplitBits;  // the prefix is key >> 36
+static_assert(kSplitTop % 2 == 1 && kLowPasses % 2 == 0, "top passes and low passes end in the output arrays");
 constexpr int kGhistWords = kMaxPasses * kMaxRadix + 64;      // digit counts, then the bucket-list counters
 
 struct SortWs {
@@ -889,20 +1007,23 @@ uint32_t* sort_first_histogram(void* ws, size_t n, bool with_perm, int sig_bits,
 namespace {
 
 // Split sort (see the prefix-split kernels): top passes keys_in -> keys_out ->
-// alt, buckets alt -> keys_out, low passes over the listed buckets alt ->
-// keys_out -> ... -> keys_out (five of them).
+// alt -> keys_out, buckets sorted in place in keys_out, low passes over the
+// listed buckets keys_out -> alt -> ... -> keys_out.
 cstone_status launch_split(const uint64_t* keys_in, uint64_t* keys_out, uint32_t* perm_out, size_t n,
                            const SortWs& s, const Variant& var, bool wide, hipStream_t stream,
                            hipEvent_t* pass_events) {
     constexpr int radix = 1 << kSplitBits;
     uint32_t* lb32[2] = {static_cast<uint32_t*>(s.lb), static_cast<uint32_t*>(s.lb) + s.rows * kMaxRadix};
     if (pass_events) CS_HIP(hipEventRecord(pass_events[0], stream));
+    const uint64_t* src_k = keys_in;
+    const uint32_t* src_v = nullptr;
     for (int p = 0; p < kSplitTop; ++p) {
+        const bool to_out = ((kSplitTop - 1 - p) % 2) == 0;
         PassArgs a{};
-        a.keys_in = p == 0 ? keys_in : keys_out;
-        a.vals_in = p == 0 ? nullptr : perm_out;
-        a.keys_out = p == 0 ? keys_out : s.keys_alt;
-        a.vals_out = p == 0 ? perm_out : s.vals_alt;
+        a.keys_in = src_k;
+        a.vals_in = src_v;
+        a.keys_out = to_out ? keys_out : s.keys_alt;
+        a.vals_out = to_out ? perm_out : s.vals_alt;
         a.n = static_cast<uint32_t>(n);
         a.shift = kSplitShift + p * kSplitBits;
         a.ghist = s.ghist + p * radix;
@@ -914,6 +1035,8 @@ cstone_status launch_split(const uint64_t* keys_in, uint64_t* keys_out, uint32_t
         a.epoch = static_cast<uint32_t>(p + 1);
         a.err = s.err;
         var.launch(a, p == 0, true, stream);
+        src_k = a.keys_out;
+        src_v = a.vals_out;
         if (pass_events) CS_HIP(hipEventRecord(pass_events[p + 1], stream));
     }
     const uint32_t tile = static_cast<uint32_t>(var.block * var.items);
@@ -931,15 +1054,14 @@ cstone_status launch_split(const uint64_t* keys_in, uint64_t* keys_out, uint32_t
     L.wide = wide ? 1u : 0u;
     const uint32_t chunks = static_cast<uint32_t>((n + kLocalChunk - 1) / kLocalChunk);
     hipLaunchKernelGGL((local_sort_kernel<kSplitBits, kLocalBlock, kLocalItems>), dim3(chunks), dim3(kLocalBlock), 0,
-                       stream, s.keys_alt, s.vals_alt, keys_out, perm_out, static_cast<uint32_t>(n), kSplitShift, L,
-                       s.err);
+                       stream, keys_out, perm_out, static_cast<uint32_t>(n), kSplitShift, L, s.err);
     if (pass_events) CS_HIP(hipEventRecord(pass_events[kSplitTop + 1], stream));
     if (s.max_buckets > 0) {  // some bucket may be longer than one block sorts
-        hipLaunchKernelGGL(large_hist_kernel, dim3(L.max_tiles), dim3(512), 0, stream, s.keys_alt,
+        hipLaunchKernelGGL(large_hist_kernel, dim3(L.max_tiles), dim3(512), 0, stream, keys_out,
                            static_cast<uint32_t>(n), L, static_cast<uint32_t>(radix - 1));
         SegArgs g{s.large_tiles, s.large_start, L.max_tiles, L.stride, s.large_count + 1};
         for (int p = 0; p < kLowPasses; ++p) {
-            const bool from_alt = (p % 2) == 0;
+            const bool from_alt = (p % 2) == 1;
             PassArgs a{};
             a.keys_in = from_alt ? s.keys_alt : keys_out;
             a.vals_in = from_alt ? s.vals_alt : perm_out;
