@@ -395,6 +395,59 @@ __global__ __launch_bounds__(BLOCK, (kMinBlocks<BLOCK, ITEMS>)) void onesweep_se
             nhist, ddelta, scan_tmp);
 }
 
+// Pass over a tile table written on the device whose length is known only
+// there (*live_tiles): a small grid of blocks takes tiles in order from
+// *counter until none are left, so a tile's predecessors are always taken by
+// running blocks (look-back progress); blocks beyond the table's length leave
+// at once, so an empty table costs no atomics. Tiles carry {first key, key count, first tile of the segment,
+// segment}, as in the segmented pass.
+template <int BITS, int BLOCK, int ITEMS, int WIN, class LB>
+__global__ __launch_bounds__(BLOCK, (kMinBlocks<BLOCK, ITEMS>)) void onesweep_list_kernel(
+    const uint64_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint64_t* __restrict__ keys_out,
+    uint32_t* __restrict__ vals_out, uint32_t n, uint32_t shift, const uint32_t* __restrict__ ghist,
+    uint32_t* __restrict__ ghist_next, uint32_t shift_next, uint32_t hist_stride, const uint4* __restrict__ tiles,
+    const uint32_t* __restrict__ seg_base, typename LB::word* lb, typename LB::word* lb_clear, uint32_t epoch,
+    uint32_t* err, const uint32_t* __restrict__ live_tiles, uint32_t* counter) {
+    constexpr int RADIX = 1 << BITS;
+    constexpr int W = BLOCK / kWave;
+    constexpr int TILE = BLOCK * ITEMS;
+    __shared__ uint64_t stage[TILE];
+    __shared__ uint16_t whist[W][RADIX];
+    __shared__ uint32_t nhist[RADIX];
+    __shared__ uint32_t ddelta[RADIX];
+    __shared__ uint64_t scan_tmp[W];
+    __shared__ uint32_t slot;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t live = *live_tiles;
+    if (blockIdx.x >= live) return;  // more blocks than tiles: the rest stay off the counter
+    for (;;) {
+        if (tid == 0) slot = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t tile = slot;
+        if (tile >= live) break;
+        const uint4 t = tiles[tile];
+        if (t.y == 0 || t.y > static_cast<uint32_t>(TILE) || t.x > n - t.y) {  // never: the table is sized
+            if (tid == 0) atomicOr(err, kErrSpin);
+            break;
+        }
+        if (lb_clear && tid < RADIX) lb_clear[static_cast<size_t>(tile) * RADIX + tid] = 0;
+        for (int i = tid; i < W * RADIX; i += BLOCK) (&whist[0][0])[i] = 0;
+        if (tid < RADIX) nhist[tid] = 0;
+        const TileDesc td{tile, t.x, t.y, t.z, seg_base[t.w]};
+        const uint32_t* gh = ghist + static_cast<size_t>(t.w) * hist_stride;
+        uint32_t* gn = ghist_next ? ghist_next + static_cast<size_t>(t.w) * hist_stride : nullptr;
+        if (td.count == static_cast<uint32_t>(TILE))
+            onesweep_tile<BITS, BLOCK, ITEMS, WIN, false, true, LB, true>(
+                td, keys_in, vals_in, keys_out, vals_out, n, shift, gh, gn, shift_next, lb, epoch, err, stage, whist,
+                nhist, ddelta, scan_tmp);
+        else
+            onesweep_tile<BITS, BLOCK, ITEMS, WIN, false, true, LB, false>(
+                td, keys_in, vals_in, keys_out, vals_out, n, shift, gh, gn, shift_next, lb, epoch, err, stage, whist,
+                nhist, ddelta, scan_tmp);
+        __syncthreads();  // shared state and the slot are reused by the next tile
+    }
+}
+
 // ---- prefix split: the top two digits, then every bucket on its own ---------
 //
 // For particle keys the three most significant digits (27 bits: the level-9
@@ -408,9 +461,10 @@ __global__ __launch_bounds__(BLOCK, (kMinBlocks<BLOCK, ITEMS>)) void onesweep_se
 // table the listing blocks write.
 
 constexpr int kLocalBlock = 512;
-constexpr int kLocalItems = 8;
+constexpr int kLocalItems = 4;
+constexpr int kLocalBlocksPerCU = 4;                        // LDS of a block stays below 40 KB
 constexpr uint32_t kLocalCap = kLocalBlock * kLocalItems;  // keys one block holds and sorts in LDS
-constexpr uint32_t kLocalLook = 512;                        // look-ahead past the chunk for its last bucket's end
+constexpr uint32_t kLocalLook = 256;                        // look-ahead past the chunk for its last bucket's end
 constexpr uint32_t kLocalChunk = kLocalCap - kLocalLook;    // a block owns the buckets starting in its chunk
 constexpr uint32_t kErrLarge = 2u;                          // bucket list overflow (not reachable by the sizing)
 constexpr uint32_t kCountMax = 160;  // buckets up to this size are ranked by counting, larger ones by LDS passes
@@ -576,17 +630,18 @@ __device__ __forceinline__ void lds_sort_segment(const uint64_t* kin, const uint
 }
 
 // Sort the buckets at window positions [f, e) (f and e bucket starts, or e the
-// window's end at the end of the keys) into kout / vout. If no bucket is
-// longer than kCountMax, every key is ranked inside its bucket by counting
-// the keys that precede it (smaller, or equal and earlier); otherwise the
-// segment goes through the LDS passes.
+// window's end at the end of the keys) into kout / vout. The window holds the
+// keys only. If no bucket is longer than kCountMax, every key is ranked inside
+// its bucket by counting the keys that precede it (smaller, or equal and
+// earlier); otherwise the values are staged too and the segment goes through
+// the LDS passes.
 template <int BITS, int BLOCK, int ITEMS>
 __device__ __forceinline__ void lds_sort_window(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
                                                 uint32_t* vout,
                                                 uint32_t n, uint32_t lo, uint32_t f, uint32_t e, uint32_t pshift,
                                                 LocalSmem<BITS, BLOCK, ITEMS>& sm) {
     constexpr int W = BLOCK / kWave;
-    static_assert(ITEMS * W == kWave, "one wave scans the per-(item, wave) start counts");
+    static_assert(ITEMS * W <= kWave, "one wave scans the per-(item, wave) start counts");
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     if (tid == 0) sm.maxb = 0;
     uint64_t k[ITEMS];
@@ -604,9 +659,9 @@ __device__ __forceinline__ void lds_sort_window(const uint64_t* kin, const uint3
     }
     __syncthreads();
     if (wave == 0) {  // (item, wave) pieces in window order: exclusive counts of starts before each
-        const uint32_t c = sm.cnt[lane];
+        const uint32_t c = lane < ITEMS * W ? sm.cnt[lane] : 0u;
         const uint32_t inc = wave_inclusive_sum(c);
-        sm.cnt[lane] = inc - c;
+        if (lane < ITEMS * W) sm.cnt[lane] = inc - c;
         if (lane == kWave - 1) sm.nb = inc;
     }
     __syncthreads();
@@ -632,12 +687,23 @@ __device__ __forceinline__ void lds_sort_window(const uint64_t* kin, const uint3
     if (lane == 0) atomicMax(&sm.maxb, longest);
     __syncthreads();
     if (sm.maxb > kCountMax) {
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t j = static_cast<uint32_t>(i) * BLOCK + tid;
+            if (j >= f && j < e) sm.vals[j] = vin[lo + j];
+        }
+        __syncthreads();
         lds_sort_segment<BITS, BLOCK, ITEMS>(kin, vin, kout, vout, lo + f, e - f, true, lo, sm);
         return;
     }
+    // rank every key in its bucket; only keys whose place changes are written
+    // (a bucket's moved keys fill exactly each other's places)
+    uint32_t dst[ITEMS];
+    uint32_t v[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t j = static_cast<uint32_t>(i) * BLOCK + tid;
+        dst[i] = lo + j;
         if (j >= f && j < e) {
             const uint32_t bs = sm.starts[id[i]], be = sm.starts[id[i] + 1];
             const uint64_t kp = k[i];
@@ -646,11 +712,17 @@ __device__ __forceinline__ void lds_sort_window(const uint64_t* kin, const uint3
                 const uint64_t kq = sm.keys[q];
                 rank += (kq < kp || (kq == kp && q < j)) ? 1u : 0u;
             }
-            const uint32_t dst = lo + bs + rank;
-            if (dst < n) {  // always true; guards memory against a logic error
-                kout[dst] = kp;
-                vout[dst] = sm.vals[j];
-            }
+            dst[i] = lo + bs + rank;
+            if (dst[i] != lo + j) v[i] = vin[lo + j];
+        }
+    }
+    __syncthreads();  // every old value this block moves has been read
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t j = static_cast<uint32_t>(i) * BLOCK + tid;
+        if (j >= f && j < e && dst[i] != lo + j && dst[i] < n) {  // dst < n always; guards memory
+            kout[dst[i]] = k[i];
+            vout[dst[i]] = v[i];
         }
     }
     __syncthreads();  // the shared arrays may be reused
@@ -700,7 +772,7 @@ __device__ __forceinline__ void list_large(const LargeList& L, uint32_t start, u
 // the run-end search) it uses only for prefixes, which sorting inside a bucket
 // leaves unchanged at every position.
 template <int BITS, int BLOCK, int ITEMS>
-__global__ __launch_bounds__(BLOCK, 2 * BLOCK / (4 * kWave)) void local_sort_kernel(
+__global__ __launch_bounds__(BLOCK, kLocalBlocksPerCU * BLOCK / (4 * kWave)) void local_sort_kernel(
     uint64_t* keys, uint32_t* vals, uint32_t n, uint32_t pshift, LargeList large, uint32_t* err) {
     const uint64_t* kin = keys;
     const uint32_t* vin = vals;
@@ -722,10 +794,7 @@ __global__ __launch_bounds__(BLOCK, 2 * BLOCK / (4 * kWave)) void local_sort_ker
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t j = static_cast<uint32_t>(i) * BLOCK + tid;
-        if (j < wn) {
-            sm.keys[j] = kin[lo + j];
-            sm.vals[j] = vin[lo + j];
-        }
+        if (j < wn) sm.keys[j] = kin[lo + j];
     }
     const uint64_t before = lo ? kin[lo - 1] >> pshift : ~0ull;  // the same word in every lane
     __syncthreads();
@@ -785,17 +854,20 @@ __global__ __launch_bounds__(BLOCK, 2 * BLOCK / (4 * kWave)) void local_sort_ker
 __global__ __launch_bounds__(512) void large_hist_kernel(const uint64_t* __restrict__ keys, uint32_t n,
                                                          LargeList L, uint32_t mask) {
     __shared__ uint32_t h[kMaxRadix];
-    const uint32_t tile = blockIdx.x;
-    if (tile >= L.count[1]) return;
-    const uint4 t = L.tiles[tile];
-    if (t.y == 0 || t.y > L.tile || t.x > n - t.y || t.w >= L.max_buckets) return;
-    for (uint32_t i = threadIdx.x; i <= mask; i += 512) h[i] = 0;
-    __syncthreads();
-    for (uint32_t j = t.x + threadIdx.x; j < t.x + t.y; j += 512) atomicAdd(&h[static_cast<uint32_t>(keys[j]) & mask], 1u);
-    __syncthreads();
-    uint32_t* g = L.hist + static_cast<size_t>(t.w) * L.stride;
-    for (uint32_t i = threadIdx.x; i <= mask; i += 512)
-        if (h[i]) atomicAdd(&g[i], h[i]);
+    const uint32_t live = L.count[1];
+    for (uint32_t tile = blockIdx.x; tile < live; tile += gridDim.x) {
+        const uint4 t = L.tiles[tile];
+        if (t.y == 0 || t.y > L.tile || t.x > n - t.y || t.w >= L.max_buckets) continue;  // never: the table is sized
+        for (uint32_t i = threadIdx.x; i <= mask; i += 512) h[i] = 0;
+        __syncthreads();
+        for (uint32_t j = t.x + threadIdx.x; j < t.x + t.y; j += 512)
+            atomicAdd(&h[static_cast<uint32_t>(keys[j]) & mask], 1u);
+        __syncthreads();
+        uint32_t* g = L.hist + static_cast<size_t>(t.w) * L.stride;
+        for (uint32_t i = threadIdx.x; i <= mask; i += 512)
+            if (h[i]) atomicAdd(&g[i], h[i]);
+        __syncthreads();
+    }
 }
 
 // ---- variants ------------------------------------------------------------------
@@ -874,13 +946,32 @@ void launch_seg_t(const PassArgs& a, const SegArgs& g, bool first, bool with_val
         launch_one_seg<BITS, BLOCK, ITEMS, WIN, false, false, XG>(a, g, stream);
 }
 
+constexpr uint32_t kListGrid = 512;  // blocks of a pass over a device-written tile table
+
+template <int BITS, int BLOCK, int ITEMS, int WIN, int XG>
+void launch_list_t(const PassArgs& a, const SegArgs& g, uint32_t* counter, hipStream_t stream) {
+    const dim3 grid(std::min(g.n_tiles, kListGrid)), block(BLOCK);
+    if (a.wide)
+        hipLaunchKernelGGL((onesweep_list_kernel<BITS, BLOCK, ITEMS, WIN, Lb64>), grid, block, 0, stream, a.keys_in,
+                           a.vals_in, a.keys_out, a.vals_out, a.n, a.shift, a.ghist, a.ghist_next, a.shift_next,
+                           g.hist_stride, g.tiles, g.seg_base, static_cast<uint64_t*>(a.lb), nullptr, a.epoch, a.err,
+                           g.live_tiles, counter);
+    else
+        hipLaunchKernelGGL((onesweep_list_kernel<BITS, BLOCK, ITEMS, WIN, Lb32>), grid, block, 0, stream, a.keys_in,
+                           a.vals_in, a.keys_out, a.vals_out, a.n, a.shift, a.ghist, a.ghist_next, a.shift_next,
+                           g.hist_stride, g.tiles, g.seg_base, static_cast<uint32_t*>(a.lb),
+                           static_cast<uint32_t*>(a.lb_clear), a.epoch, a.err, g.live_tiles, counter);
+}
+
 struct Variant {
     int bits, block, items, window, xcd_group;
     void (*launch)(const PassArgs&, bool, bool, hipStream_t);
     void (*launch_seg)(const PassArgs&, const SegArgs&, bool, bool, hipStream_t);
+    void (*launch_list)(const PassArgs&, const SegArgs&, uint32_t*, hipStream_t);
 };
 
-#define CS_VARIANT(B, BL, IT, WI, XG) {B, BL, IT, WI, XG, launch_pass_t<B, BL, IT, WI, XG>, launch_seg_t<B, BL, IT, WI, XG>}
+#define CS_VARIANT(B, BL, IT, WI, XG) \
+    {B, BL, IT, WI, XG, launch_pass_t<B, BL, IT, WI, XG>, launch_seg_t<B, BL, IT, WI, XG>, launch_list_t<B, BL, IT, WI, XG>}
 const Variant kVariants[] = {
     CS_VARIANT(9, 512, 16, 4, 8), CS_VARIANT(9, 512, 16, 4, 1), CS_VARIANT(8, 512, 16, 4, 8),
     CS_VARIANT(9, 512, 12, 4, 8), CS_VARIANT(9, 512, 32, 4, 8), CS_VARIANT(8, 512, 16, 4, 1),
@@ -1057,7 +1148,7 @@ cstone_status launch_split(const uint64_t* keys_in, uint64_t* keys_out, uint32_t
                        stream, keys_out, perm_out, static_cast<uint32_t>(n), kSplitShift, L, s.err);
     if (pass_events) CS_HIP(hipEventRecord(pass_events[kSplitTop + 1], stream));
     if (s.max_buckets > 0) {  // some bucket may be longer than one block sorts
-        hipLaunchKernelGGL(large_hist_kernel, dim3(L.max_tiles), dim3(512), 0, stream, keys_out,
+        hipLaunchKernelGGL(large_hist_kernel, dim3(std::min(L.max_tiles, kListGrid)), dim3(512), 0, stream, keys_out,
                            static_cast<uint32_t>(n), L, static_cast<uint32_t>(radix - 1));
         SegArgs g{s.large_tiles, s.large_start, L.max_tiles, L.stride, s.large_count + 1};
         for (int p = 0; p < kLowPasses; ++p) {
@@ -1077,7 +1168,7 @@ cstone_status launch_split(const uint64_t* keys_in, uint64_t* keys_out, uint32_t
             a.lb_clear = (!wide && p + 1 < kLowPasses) ? static_cast<void*>(lb32[(p + 1) & 1]) : nullptr;
             a.epoch = static_cast<uint32_t>(kSplitTop + 1 + p);
             a.err = s.err;
-            var.launch_seg(a, g, false, true, stream);
+            var.launch_list(a, g, s.large_count + 2 + p, stream);  // a tile counter per pass, cleared at set-up
         }
     }
     if (pass_events) CS_HIP(hipEventRecord(pass_events[kSplitTop + 2], stream));
