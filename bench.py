@@ -48,6 +48,20 @@ def byte_model(n: int, leaves_per_round: list, n_leaves: int) -> dict:
     return dict(keys=keys, sort=sort, rebalance=reb, link=link, total=keys + sort + reb + link)
 
 
+def path_bytes(model: dict, n: int) -> dict:
+    """Algorithmic bytes of the path as built here: the fixed model's keys,
+    rebalance and link, and the split sort of particle keys: 20 N for the
+    first top pass (its histogram comes with the keys, its values are the
+    indices), 24 N for each of the two later top passes, 8 N for the bucket
+    pass (every key read once; keys that move are data-dependent and not
+    counted), and nothing for the low passes when no bucket is listed."""
+    sort = 20 * n + 2 * 24 * n + 8 * n
+    out = dict(model)
+    out["sort"] = sort
+    out["total"] = model["keys"] + sort + model["rebalance"] + model["link"]
+    return out
+
+
 def kernel_source_digest() -> str:
     h = hashlib.sha256()
     for name in ("sort.hip", "common.hpp"):
@@ -311,9 +325,12 @@ def main():
             leaves_hist.append(e.n_leaves)
     model = byte_model(n, leaves_hist, nl_final)
 
-    # dominant kernel: a middle digit pass (keys + permutation in and out)
-    mid = passes[1:] if len(passes) > 1 else passes
+    # dominant kernel: a later top digit pass (keys + permutation in and out).
+    # Sort intervals: the three top passes, the bucket pass, the low passes
+    split = len(passes) == 5
+    mid = passes[1:3] if split else (passes[1:] if len(passes) > 1 else passes)
     pass_ms = sum(mid) / len(mid)
+    path = path_bytes(model, n)
     pass_bytes = 24 * n
     achieved = pass_bytes / (pass_ms * 1e-3) / 1e9
     digest = kernel_source_digest()
@@ -338,12 +355,17 @@ def main():
                    "rounds": r.rounds, "leaves_per_round": leaves_hist},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "onesweep_kernel<false,true> (radix digit pass 2..8 of the particle sort)",
+                     "kernel": "onesweep_kernel<false,true> (top digit passes 2 and 3 of the split particle sort)",
                      "bytes_per_launch": pass_bytes, "avg_launch_ms": pass_ms,
                      "kernel_source_digest": digest},
         "build": {"stage_ms": {"keys": stage[0], "sort": stage[1], "rebalance": stage[2], "link": stage[3]},
-                  "sort_pass_ms": passes, "model_bytes": model,
-                  "model_fraction": model["total"] / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9)},
+                  "sort_pass_ms": passes,
+                  "sort_pass_names": (["top 1 (bits 36-44)", "top 2 (bits 45-53)", "top 3 (bits 54-62)", "buckets", "low passes"]
+                                      if split else [f"digit {i}" for i in range(len(passes))]),
+                  "model_bytes": model,
+                  "model_fraction": model["total"] / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9),
+                  "path_bytes": path,
+                  "path_fraction": path["total"] / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9)},
     }
     if not args.no_batched:
         out["batched"] = bench_batched(args.batch_steps)
