@@ -88,9 +88,13 @@ CSTONE_API cstone_status cstone_compute_keys(const double* x, const double* y, c
 
 /* ------------------------------------------------------------------------
  * Sort (Sec. 4, Table 1: radix sort_by_key with the identity permutation as
- * values). Stable LSD radix sort: keys_out[i] = keys_in[perm_out[i]],
- * keys_out non-decreasing, equal keys in ascending original index.
- *   keys_in   device, n uint64 (not modified; may not alias the outputs)
+ * values). Stable radix sort: keys_out[i] = keys_in[perm_out[i]], keys_out
+ * non-decreasing, equal keys in ascending original index. Keys are particle
+ * keys: 63 significant bits (bit 63 is not sorted on). Three digit passes
+ * order the keys by their top 27 bits; the runs of one 27-bit prefix are then
+ * sorted in place, in LDS, or by four passes over their low 36 bits if longer
+ * than 2048 keys.
+ *   keys_in   device, n uint64 below 2^63 (not modified; may not alias the outputs)
  *   keys_out  device, n uint64;  perm_out  device, n uint32
  *   ws        device workspace of cstone_sort_workspace_bytes(n) bytes
  * Asynchronous. Errors: INVALID_ARG, DEVICE.
@@ -191,7 +195,7 @@ CSTONE_API cstone_status cstone_link_octree_by_sort(const uint64_t* leaves, size
  *   level_offsets            device, 23 uint32 (ignored when node_keys is NULL)
  *   ws                       device workspace, cstone_build_workspace_bytes(n, leaf_capacity)
  *   timings                  host, or NULL: HIP-event times of the stages and of
- *                            every radix-sort pass of the particle keys (events
+ *                            the parts of the particle-key sort (events
  *                            are recorded on `stream` only when this is non-NULL)
  * Synchronises `stream`. Errors: those of the stages; NONFINITE if a
  * coordinate is NaN or infinite (found at the first synchronisation, the
@@ -199,7 +203,8 @@ CSTONE_API cstone_status cstone_link_octree_by_sort(const uint64_t* leaves, size
  */
 typedef struct cstone_timings {
     float stage_ms[4];     /* keys, sort, rebalance loop, link */
-    float sort_pass_ms[8]; /* each digit pass of the particle-key sort */
+    float sort_pass_ms[8]; /* the particle-key sort: its three top passes, the
+                              bucket pass and the low passes (5 entries) */
     uint32_t sort_passes;  /* entries of sort_pass_ms in use */
 } cstone_timings;
 

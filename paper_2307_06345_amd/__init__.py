@@ -273,7 +273,7 @@ class BuildResult:
         self.n_leaves = n_leaves
         self.rounds = rounds
         self.stage_ms = stage_ms          # keys, sort, rebalance, link (timed builds only)
-        self.sort_pass_ms = sort_pass_ms  # every digit pass of the particle sort (timed builds only)
+        self.sort_pass_ms = sort_pass_ms  # top passes, bucket pass, low passes of the particle sort (timed builds only)
 
     @property
     def sorted_keys(self):

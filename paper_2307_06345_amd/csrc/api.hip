@@ -164,8 +164,9 @@ cstone_status cstone_build(const double* x, const double* y, const double* z, si
         s = launch_keys(x, y, z, n, *box, curve, keys, flag, stream, hist0, hist_mask, hist_shift);
         if (s != CSTONE_OK) break;
         if (mark(1) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
+        // the sort reports a failed device-side wait into the same flag word
         s = launch_sort(keys, sorted_keys, perm, n, 63, stage_ws, stage_bytes, stream,
-                        timed && n ? pass_ev : nullptr, /*prepared=*/true);
+                        timed && n ? pass_ev : nullptr, /*prepared=*/true, -1, flag);
         if (s != CSTONE_OK) break;
         if (mark(2) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
         if (nl == 0) nl = 1;  // start from the root leaf {0, 8^L}
@@ -206,6 +207,7 @@ cstone_status cstone_build(const double* x, const double* y, const double* z, si
         *n_leaves = loop.n_leaves;
         if (iters_done) *iters_done = loop.rounds;
         host_flag = loop.input_flags;
+        if (host_flag & ~CSTONE_FLAG_NONFINITE) { s = CSTONE_ERR_DEVICE; break; }  // the sort gave up a wait
         if (host_flag & CSTONE_FLAG_NONFINITE) { s = CSTONE_ERR_NONFINITE; break; }
         if ((s = loop.status) != CSTONE_OK) break;
         if (timed) {

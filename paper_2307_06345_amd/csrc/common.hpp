@@ -15,7 +15,7 @@ constexpr uint64_t kKeyEnd = 1ull << 63;  // 8^21, closes every cornerstone arra
 constexpr int kWave = 64;
 
 // Error word kept in workspaces: a device-side wait that gave up sets it.
-constexpr uint32_t kErrSpin = 1u;
+constexpr uint32_t kErrSpin = 1u << 8;  // internal error bits sit above the public CSTONE_FLAG_* bits
 
 // Spin budget for look-back waits (each spin sleeps ~64 cycles); a wait that
 // exhausts it marks the error word and proceeds, so every wave terminates.

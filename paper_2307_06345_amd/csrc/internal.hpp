@@ -23,9 +23,13 @@ size_t sort_workspace_bytes(size_t n, bool with_perm);
 // workspace and the producer of the keys counted their first digit into
 // sort_first_histogram() (*mask + 1 counters of (key >> *shift) & *mask), so
 // neither step is repeated.
+// err_word: NULL, or a caller word (cleared beforehand) into which the sort's
+// kernels OR their error bits (a look-back wait that gave up, a bucket-list
+// overflow), all above the public CSTONE_FLAG_* bits.
 cstone_status launch_sort(const uint64_t* keys_in, uint64_t* keys_out, uint32_t* perm_out, size_t n,
                           int sig_bits, void* ws, size_t ws_bytes, hipStream_t stream,
-                          hipEvent_t* pass_events = nullptr, bool prepared = false, int variant = -1);
+                          hipEvent_t* pass_events = nullptr, bool prepared = false, int variant = -1,
+                          uint32_t* err_word = nullptr);
 // clear_word: NULL, or one caller word zeroed by the same launch; variant: the
 // sort shape the passes will use (-1: the default)
 cstone_status sort_prepare(void* ws, size_t n, bool with_perm, hipStream_t stream, uint32_t* clear_word = nullptr,

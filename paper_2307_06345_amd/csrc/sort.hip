@@ -466,7 +466,7 @@ constexpr int kLocalBlocksPerCU = 4;                        // LDS of a block st
 constexpr uint32_t kLocalCap = kLocalBlock * kLocalItems;  // keys one block holds and sorts in LDS
 constexpr uint32_t kLocalLook = 256;                        // look-ahead past the chunk for its last bucket's end
 constexpr uint32_t kLocalChunk = kLocalCap - kLocalLook;    // a block owns the buckets starting in its chunk
-constexpr uint32_t kErrLarge = 2u;                          // bucket list overflow (not reachable by the sizing)
+constexpr uint32_t kErrLarge = 1u << 9;                     // bucket list overflow (not reachable by the sizing)
 constexpr uint32_t kCountMax = 160;  // buckets up to this size are ranked by counting, larger ones by LDS passes
 
 struct LargeList {
@@ -487,7 +487,7 @@ struct LocalSmem {
     uint32_t cnt[ITEMS * (BLOCK / kWave)];
     uint32_t scan[BLOCK / kWave];
     uint64_t bits[BLOCK / kWave];
-    uint32_t first, last, end, slot, tile0, nb, maxb;
+    uint32_t first, last, end, run_end, slot, tile0, nb, maxb;
 };
 
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
@@ -838,12 +838,13 @@ __global__ __launch_bounds__(BLOCK, kLocalBlocksPerCU * BLOCK / (4 * kWave)) voi
     }
     // the last bucket runs past the window: the buckets before it from LDS, then it alone
     if (l > f) lds_sort_window<BITS, BLOCK, ITEMS>(kin, vin, kout, vout, n, lo, f, l, pshift, sm);
+    // (its own slot: with l == f no barrier separates this from the reads of sm.end above)
     if (tid < kWave) {
         const uint32_t ee = run_end(kin, n, wend, (last_prefix + 1u) << pshift);
-        if (tid == 0) sm.end = ee;
+        if (tid == 0) sm.run_end = ee;
     }
     __syncthreads();
-    const uint32_t start = lo + l, len = sm.end - start;
+    const uint32_t start = lo + l, len = sm.run_end - start;
     if (len <= CAP)
         lds_sort_segment<BITS, BLOCK, ITEMS>(kin, vin, kout, vout, start, len, false, lo, sm);
     else
@@ -1102,7 +1103,7 @@ namespace {
 // listed buckets keys_out -> alt -> ... -> keys_out.
 cstone_status launch_split(const uint64_t* keys_in, uint64_t* keys_out, uint32_t* perm_out, size_t n,
                            const SortWs& s, const Variant& var, bool wide, hipStream_t stream,
-                           hipEvent_t* pass_events) {
+                           hipEvent_t* pass_events, uint32_t* err) {
     constexpr int radix = 1 << kSplitBits;
     uint32_t* lb32[2] = {static_cast<uint32_t*>(s.lb), static_cast<uint32_t*>(s.lb) + s.rows * kMaxRadix};
     if (pass_events) CS_HIP(hipEventRecord(pass_events[0], stream));
@@ -1124,7 +1125,7 @@ cstone_status launch_split(const uint64_t* keys_in, uint64_t* keys_out, uint32_t
         a.lb = wide ? s.lb : static_cast<void*>(lb32[p & 1]);
         a.lb_clear = (!wide && p + 1 < kSplitTop) ? static_cast<void*>(lb32[(p + 1) & 1]) : nullptr;
         a.epoch = static_cast<uint32_t>(p + 1);
-        a.err = s.err;
+        a.err = err;
         var.launch(a, p == 0, true, stream);
         src_k = a.keys_out;
         src_v = a.vals_out;
@@ -1145,7 +1146,7 @@ cstone_status launch_split(const uint64_t* keys_in, uint64_t* keys_out, uint32_t
     L.wide = wide ? 1u : 0u;
     const uint32_t chunks = static_cast<uint32_t>((n + kLocalChunk - 1) / kLocalChunk);
     hipLaunchKernelGGL((local_sort_kernel<kSplitBits, kLocalBlock, kLocalItems>), dim3(chunks), dim3(kLocalBlock), 0,
-                       stream, keys_out, perm_out, static_cast<uint32_t>(n), kSplitShift, L, s.err);
+                       stream, keys_out, perm_out, static_cast<uint32_t>(n), kSplitShift, L, err);
     if (pass_events) CS_HIP(hipEventRecord(pass_events[kSplitTop + 1], stream));
     if (s.max_buckets > 0) {  // some bucket may be longer than one block sorts
         hipLaunchKernelGGL(large_hist_kernel, dim3(std::min(L.max_tiles, kListGrid)), dim3(512), 0, stream, keys_out,
@@ -1167,7 +1168,7 @@ cstone_status launch_split(const uint64_t* keys_in, uint64_t* keys_out, uint32_t
             a.lb = wide ? s.lb : static_cast<void*>(lb32[p & 1]);
             a.lb_clear = (!wide && p + 1 < kLowPasses) ? static_cast<void*>(lb32[(p + 1) & 1]) : nullptr;
             a.epoch = static_cast<uint32_t>(kSplitTop + 1 + p);
-            a.err = s.err;
+            a.err = err;
             var.launch_list(a, g, s.large_count + 2 + p, stream);  // a tile counter per pass, cleared at set-up
         }
     }
@@ -1180,7 +1181,7 @@ cstone_status launch_split(const uint64_t* keys_in, uint64_t* keys_out, uint32_t
 
 cstone_status launch_sort(const uint64_t* keys_in, uint64_t* keys_out, uint32_t* perm_out, size_t n,
                           int sig_bits, void* ws, size_t ws_bytes, hipStream_t stream, hipEvent_t* pass_events,
-                          bool prepared, int variant) {
+                          bool prepared, int variant, uint32_t* err_word) {
     const bool with_perm = perm_out != nullptr;
     SortWs s = carve_sort(ws, n, with_perm);
     if (ws_bytes < s.bytes) return CSTONE_ERR_INVALID_ARG;
@@ -1204,7 +1205,8 @@ cstone_status launch_sort(const uint64_t* keys_in, uint64_t* keys_out, uint32_t*
                            static_cast<uint32_t>(n), split ? kSplitShift : 0u, static_cast<uint32_t>(radix - 1),
                            s.ghist);
     }
-    if (split) return launch_split(keys_in, keys_out, perm_out, n, s, var, wide, stream, pass_events);
+    uint32_t* err = err_word ? err_word : s.err;
+    if (split) return launch_split(keys_in, keys_out, perm_out, n, s, var, wide, stream, pass_events, err);
 
     uint32_t* lb32[2] = {static_cast<uint32_t*>(s.lb), static_cast<uint32_t*>(s.lb) + s.rows * kMaxRadix};
     if (pass_events) CS_HIP(hipEventRecord(pass_events[0], stream));
@@ -1226,7 +1228,7 @@ cstone_status launch_sort(const uint64_t* keys_in, uint64_t* keys_out, uint32_t*
         a.lb = wide ? s.lb : static_cast<void*>(lb32[p & 1]);
         a.lb_clear = (!wide && p + 1 < passes) ? static_cast<void*>(lb32[(p + 1) & 1]) : nullptr;
         a.epoch = static_cast<uint32_t>(p + 1);
-        a.err = s.err;
+        a.err = err;
         var.launch(a, p == 0, with_perm, stream);
         src_k = a.keys_out;
         src_v = a.vals_out;

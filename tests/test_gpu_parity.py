@@ -96,12 +96,24 @@ def _keys(kind, n, rng):
         return np.sort(rng.integers(0, END, n, dtype=np.uint64))
     if kind == "reversed":
         return np.sort(rng.integers(0, END, n, dtype=np.uint64))[::-1].copy()
+    if kind == "clustered":  # a few hundred level-9 prefixes: buckets of hundreds of keys, all low bits varying
+        pre = rng.choice(1 << 27, 300, replace=False).astype(np.uint64)
+        return (rng.choice(pre, n) << np.uint64(36)) | rng.integers(0, 1 << 36, n, dtype=np.uint64)
+    if kind == "mixed":  # bucket sizes from 1 to beyond one block's window, with repeated low bits
+        sizes = np.minimum((rng.pareto(0.8, n) * 40).astype(np.int64) + 1, 30000)
+        sizes = sizes[: int(np.searchsorted(np.cumsum(sizes), n)) + 1]
+        pre = np.sort(rng.choice(1 << 27, sizes.size, replace=False)).astype(np.uint64)
+        prefix = np.repeat(pre, sizes)[:n]
+        low = rng.integers(0, 1 << 36, n, dtype=np.uint64) >> np.uint64(rng.integers(0, 37))
+        keys = (prefix << np.uint64(36)) | (low & np.uint64((1 << 36) - 1))
+        return keys[rng.permutation(n)]
     raise ValueError(kind)
 
 
 @pytest.mark.parametrize("kind,n", [("uniform", 0), ("uniform", 1), ("uniform", 4095), ("uniform", 4097),
                                     ("uniform", 300001), ("dups", 100000), ("equal", 9000), ("sorted", 70000),
-                                    ("reversed", 70001), ("uniform", (1 << 22) + 5)])
+                                    ("reversed", 70001), ("uniform", (1 << 22) + 5), ("clustered", 200000),
+                                    ("mixed", 300000), ("mixed", (1 << 21) + 3)])
 def test_sort_parity(kind, n):
     rng = np.random.default_rng(n + len(kind))
     keys = _keys(kind, n, rng)
@@ -111,6 +123,25 @@ def test_sort_parity(kind, n):
     rP, rperm = oracle.sort(keys)
     eq(host(P), rP, "sorted keys")
     eq(host(perm), rperm, "perm")
+
+
+def test_sort_buckets_past_the_lookahead_repeatedly():
+    """Level-9 buckets of 1500-2000 keys: most blocks of the bucket pass own a
+    single bucket that runs past their look-ahead and is read again (the path
+    whose end search once shared a word with a value read before it)."""
+    rng = np.random.default_rng(91)
+    n = (1 << 22) + 17
+    sizes = rng.integers(1500, 2001, n // 1500 + 2)
+    pre = np.sort(rng.choice(1 << 27, sizes.size, replace=False)).astype(np.uint64)
+    keys = (np.repeat(pre, sizes)[:n] << np.uint64(36)) | rng.integers(0, 1 << 36, n, dtype=np.uint64)
+    keys = keys[rng.permutation(n)]
+    rP, rperm = oracle.sort(keys)
+    d = dev(keys)
+    for rep in range(8):
+        say("sort, buckets past the look-ahead, rep", rep)
+        P, perm = cs.sort(d)
+        eq(host(P), rP, "sorted keys")
+        eq(host(perm), rperm, "perm")
 
 
 def test_sort_twice_identical():
