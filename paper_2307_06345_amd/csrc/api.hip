@@ -152,18 +152,22 @@ cstone_status cstone_build(const double* x, const double* y, const double* z, si
     size_t nl = *n_leaves;
     do {
         if (mark(0) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
-        // the key kernel counts the sort's first digit as it writes the keys;
-        // the sort's set-up launch also clears the non-finite flag
+        // The key kernel goes first (a long launch, so the host's later
+        // launches overlap it) and stores per-block counts of the sort's first
+        // digit and per-block non-finite flags; the sort's set-up launch sums
+        // them, writes the flag word and clears what the passes need cleared.
         if (n) {
-            if ((s = sort_prepare(stage_ws, n, true, stream, flag)) != CSTONE_OK) break;
+            uint32_t *hist_parts = nullptr, *bad_parts = nullptr, hist_mask = 0, hist_shift = 0, parts = 0;
+            sort_key_parts(stage_ws, n, true, 63, &hist_parts, &bad_parts, &hist_mask, &hist_shift);
+            s = launch_keys(x, y, z, n, *box, curve, keys, nullptr, stream, hist_parts, hist_mask, hist_shift,
+                            bad_parts, &parts);
+            if (s != CSTONE_OK) break;
+            if (mark(1) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
+            if ((s = sort_setup_from_keys(stage_ws, n, true, parts, flag, stream)) != CSTONE_OK) break;
         } else {
             hipLaunchKernelGGL(clear_word_kernel, dim3(1), dim3(1), 0, stream, flag);
+            if (mark(1) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
         }
-        uint32_t hist_mask = 0, hist_shift = 0;
-        uint32_t* hist0 = n ? sort_first_histogram(stage_ws, n, true, 63, &hist_mask, &hist_shift) : nullptr;
-        s = launch_keys(x, y, z, n, *box, curve, keys, flag, stream, hist0, hist_mask, hist_shift);
-        if (s != CSTONE_OK) break;
-        if (mark(1) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
         // the sort reports a failed device-side wait into the same flag word
         s = launch_sort(keys, sorted_keys, perm, n, 63, stage_ws, stage_bytes, stream,
                         timed && n ? pass_ev : nullptr, /*prepared=*/true, -1, flag);

@@ -6,11 +6,16 @@
 namespace cs {
 
 // keys.hip
-// hist0: NULL, or hist_mask + 1 (<= 512) counters to which the count of
-// every key's value of ((key >> hist_shift) & hist_mask) is added
+constexpr uint32_t kKeyBlocksMax = 512;  // blocks of the plain key kernel (grid-stride beyond)
+// flags: NULL, or a word into which CSTONE_FLAG_NONFINITE is OR-ed.
+// hist_parts: NULL, or kKeyBlocksMax rows of 512 words; block b stores the
+// count of every key's ((key >> hist_shift) & hist_mask) into row b.
+// bad_parts: NULL, or kKeyBlocksMax words; block b stores CSTONE_FLAG_NONFINITE
+// or 0. *blocks_used (if not NULL): the rows and words written.
 cstone_status launch_keys(const double* x, const double* y, const double* z, size_t n, const cstone_box& box,
                           cstone_curve curve, uint64_t* keys, uint32_t* flags, hipStream_t stream,
-                          uint32_t* hist0 = nullptr, uint32_t hist_mask = 0, uint32_t hist_shift = 0);
+                          uint32_t* hist_parts = nullptr, uint32_t hist_mask = 0, uint32_t hist_shift = 0,
+                          uint32_t* bad_parts = nullptr, uint32_t* blocks_used = nullptr);
 
 // sort.hip — stable radix sort of 64-bit keys (63 or 64 significant bits)
 // with an optional uint32 permutation; sig_bits selects how many low bits are
@@ -20,9 +25,8 @@ size_t sort_workspace_bytes(size_t n, bool with_perm);
 // pass_events: NULL, or sort_passes() + 1 events recorded before the first
 // pass and after every pass (split path: after each top pass, the bucket
 // sort and the low passes). prepared: sort_prepare() already ran on this
-// workspace and the producer of the keys counted their first digit into
-// sort_first_histogram() (*mask + 1 counters of (key >> *shift) & *mask), so
-// neither step is repeated.
+// workspace, or the key kernel stored its per-block counts of the first digit
+// and sort_setup_from_keys() ran, so neither step is repeated.
 // err_word: NULL, or a caller word (cleared beforehand) into which the sort's
 // kernels OR their error bits (a look-back wait that gave up, a bucket-list
 // overflow), all above the public CSTONE_FLAG_* bits.
@@ -34,7 +38,15 @@ cstone_status launch_sort(const uint64_t* keys_in, uint64_t* keys_out, uint32_t*
 // sort shape the passes will use (-1: the default)
 cstone_status sort_prepare(void* ws, size_t n, bool with_perm, hipStream_t stream, uint32_t* clear_word = nullptr,
                            int variant = -1);
-uint32_t* sort_first_histogram(void* ws, size_t n, bool with_perm, int sig_bits, uint32_t* mask, uint32_t* shift);
+// Per-block first-digit counts and non-finite flags of the key kernel, in the
+// sort workspace: where to store them and which digit to count.
+void sort_key_parts(void* ws, size_t n, bool with_perm, int sig_bits, uint32_t** hist_parts, uint32_t** bad_parts,
+                    uint32_t* mask, uint32_t* shift);
+// Set-up after the key kernel stored its parts (replaces sort_prepare in a
+// build): the first digit's counts are the sum of the `parts` rows, *flag the
+// OR of the blocks' flags, and everything sort_prepare clears is cleared.
+cstone_status sort_setup_from_keys(void* ws, size_t n, bool with_perm, uint32_t parts, uint32_t* flag,
+                                   hipStream_t stream);
 int sort_passes(size_t n, int sig_bits, bool with_perm);
 
 // ---- batched builds: many independent sets in one pass of every stage -------

@@ -150,7 +150,7 @@ constexpr int kKeysBlock = 256;   // batched key kernel: one tile per block
 // histogram flushes (512 global atomics each, all on the same 512 counters)
 // are few; 2 blocks of 1024 per CU still fill every SIMD
 constexpr int kKeysBlockPlain = 1024;
-constexpr size_t kKeysMaxBlocks = 512;
+constexpr size_t kKeysMaxBlocks = kKeyBlocksMax;
 
 template <int CURVE>
 __device__ __forceinline__ uint64_t key_of(double cx, double cy, double cz, double lo0, double lo1, double lo2,
@@ -173,7 +173,8 @@ __global__ __launch_bounds__(kKeysBlockPlain) void keys_kernel(const double* __r
                                                           const double* __restrict__ z, size_t n, double lo0,
                                                           double lo1, double lo2, double s0, double s1, double s2,
                                                           uint64_t* __restrict__ keys, uint32_t* flags,
-                                                          uint32_t* hist0, uint32_t hmask, uint32_t hshift) {
+                                                          uint32_t* hist_parts, uint32_t hmask, uint32_t hshift,
+                                                          uint32_t* bad_parts) {
     __shared__ uint16_t two[kStates * 64];
     __shared__ uint16_t first[8];
     __shared__ uint32_t h[512];
@@ -181,7 +182,7 @@ __global__ __launch_bounds__(kKeysBlockPlain) void keys_kernel(const double* __r
         for (int i = threadIdx.x; i < kStates * 64; i += kKeysBlockPlain) two[i] = d_hilbert.two[i];
         if (threadIdx.x < 8) first[threadIdx.x] = d_hilbert.first[threadIdx.x];
     }
-    if (hist0)
+    if (hist_parts)
         for (int i = threadIdx.x; i < 512; i += kKeysBlockPlain) h[i] = 0;
     __syncthreads();
     bool bad = false;
@@ -200,7 +201,7 @@ __global__ __launch_bounds__(kKeysBlockPlain) void keys_kernel(const double* __r
             k.x = key_of<CURVE>(cx.x, cy.x, cz.x, lo0, lo1, lo2, s0, s1, s2, two, first);
             k.y = key_of<CURVE>(cx.y, cy.y, cz.y, lo0, lo1, lo2, s0, s1, s2, two, first);
             k2[p] = k;
-            if (hist0) {
+            if (hist_parts) {
                 atomicAdd(&h[(k.x >> hshift) & hmask], 1u);
                 atomicAdd(&h[(k.y >> hshift) & hmask], 1u);
             }
@@ -210,7 +211,7 @@ __global__ __launch_bounds__(kKeysBlockPlain) void keys_kernel(const double* __r
             bad |= !finite3(x[p], y[p], z[p]);
             const uint64_t k = key_of<CURVE>(x[p], y[p], z[p], lo0, lo1, lo2, s0, s1, s2, two, first);
             keys[p] = k;
-            if (hist0) atomicAdd(&h[(k >> hshift) & hmask], 1u);
+            if (hist_parts) atomicAdd(&h[(k >> hshift) & hmask], 1u);
         }
     } else {
         for (size_t p = t0; p < n; p += stride) {
@@ -218,23 +219,30 @@ __global__ __launch_bounds__(kKeysBlockPlain) void keys_kernel(const double* __r
             bad |= !finite3(cx, cy, cz);
             const uint64_t k = key_of<CURVE>(cx, cy, cz, lo0, lo1, lo2, s0, s1, s2, two, first);
             keys[p] = k;
-            if (hist0) atomicAdd(&h[(k >> hshift) & hmask], 1u);
+            if (hist_parts) atomicAdd(&h[(k >> hshift) & hmask], 1u);
         }
     }
     if (flags && __ballot(bad) != 0ull && lane_id() == 0) atomicOr(flags, CSTONE_FLAG_NONFINITE);
-    if (hist0) {
+    // per-block results are stored, not accumulated, so nothing has to be
+    // cleared before this kernel
+    if (bad_parts) {
+        const int any = __syncthreads_or(bad ? 1 : 0);
+        if (threadIdx.x == 0) bad_parts[blockIdx.x] = any ? CSTONE_FLAG_NONFINITE : 0u;
+    }
+    if (hist_parts) {
         __syncthreads();
-        for (uint32_t i = threadIdx.x; i <= hmask; i += kKeysBlockPlain)
-            if (h[i]) atomicAdd(&hist0[i], h[i]);
+        uint32_t* mine = hist_parts + static_cast<size_t>(blockIdx.x) * 512;
+        for (uint32_t i = threadIdx.x; i <= hmask; i += kKeysBlockPlain) mine[i] = h[i];
     }
 }
 
 template <int CURVE, bool PAIRED>
 void launch_keys_t(size_t blocks, hipStream_t stream, const double* x, const double* y, const double* z, size_t n,
-                   const cstone_box& box, const double* s, uint64_t* keys, uint32_t* flags, uint32_t* hist0,
-                   uint32_t hmask, uint32_t hshift) {
+                   const cstone_box& box, const double* s, uint64_t* keys, uint32_t* flags, uint32_t* hist_parts,
+                   uint32_t hmask, uint32_t hshift, uint32_t* bad_parts) {
     hipLaunchKernelGGL((keys_kernel<CURVE, PAIRED>), dim3(blocks), dim3(kKeysBlockPlain), 0, stream, x, y, z, n,
-                       box.lo[0], box.lo[1], box.lo[2], s[0], s[1], s[2], keys, flags, hist0, hmask, hshift);
+                       box.lo[0], box.lo[1], box.lo[2], s[0], s[1], s[2], keys, flags, hist_parts, hmask, hshift,
+                       bad_parts);
 }
 
 // Batched keys: block b encodes tile tiles[b] = {first particle, count, -, set}
@@ -293,10 +301,12 @@ cstone_status launch_keys_batch(const double* x, const double* y, const double* 
 }
 
 cstone_status launch_keys(const double* x, const double* y, const double* z, size_t n, const cstone_box& box,
-                          cstone_curve curve, uint64_t* keys, uint32_t* flags, hipStream_t stream, uint32_t* hist0,
-                          uint32_t hist_mask, uint32_t hist_shift) {
+                          cstone_curve curve, uint64_t* keys, uint32_t* flags, hipStream_t stream,
+                          uint32_t* hist_parts, uint32_t hist_mask, uint32_t hist_shift, uint32_t* bad_parts,
+                          uint32_t* blocks_used) {
+    if (blocks_used) *blocks_used = 0;
     if (n == 0) return CSTONE_OK;
-    if (hist0 && (hist_mask >= 512 || hist_shift >= 64)) return CSTONE_ERR_INVALID_ARG;
+    if (hist_parts && (hist_mask >= 512 || hist_shift >= 64)) return CSTONE_ERR_INVALID_ARG;
     double s[3];
     for (int d = 0; d < 3; ++d) s[d] = 2097152.0 / (box.hi[d] - box.lo[d]);
     auto aligned = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; };
@@ -304,16 +314,21 @@ cstone_status launch_keys(const double* x, const double* y, const double* z, siz
     const size_t per_thread = paired ? 2 : 1;
     size_t blocks = (n + kKeysBlockPlain * per_thread - 1) / (kKeysBlockPlain * per_thread);
     if (blocks > kKeysMaxBlocks) blocks = kKeysMaxBlocks;  // grid-stride beyond that
+    if (blocks_used) *blocks_used = static_cast<uint32_t>(blocks);
     if (curve == CSTONE_HILBERT) {
         if (paired)
-            launch_keys_t<CSTONE_HILBERT, true>(blocks, stream, x, y, z, n, box, s, keys, flags, hist0, hist_mask, hist_shift);
+            launch_keys_t<CSTONE_HILBERT, true>(blocks, stream, x, y, z, n, box, s, keys, flags, hist_parts, hist_mask,
+                                                   hist_shift, bad_parts);
         else
-            launch_keys_t<CSTONE_HILBERT, false>(blocks, stream, x, y, z, n, box, s, keys, flags, hist0, hist_mask, hist_shift);
+            launch_keys_t<CSTONE_HILBERT, false>(blocks, stream, x, y, z, n, box, s, keys, flags, hist_parts, hist_mask,
+                                                   hist_shift, bad_parts);
     } else {
         if (paired)
-            launch_keys_t<CSTONE_MORTON, true>(blocks, stream, x, y, z, n, box, s, keys, flags, hist0, hist_mask, hist_shift);
+            launch_keys_t<CSTONE_MORTON, true>(blocks, stream, x, y, z, n, box, s, keys, flags, hist_parts, hist_mask,
+                                                   hist_shift, bad_parts);
         else
-            launch_keys_t<CSTONE_MORTON, false>(blocks, stream, x, y, z, n, box, s, keys, flags, hist0, hist_mask, hist_shift);
+            launch_keys_t<CSTONE_MORTON, false>(blocks, stream, x, y, z, n, box, s, keys, flags, hist_parts, hist_mask,
+                                                   hist_shift, bad_parts);
     }
     CS_HIP(hipGetLastError());
     return CSTONE_OK;

@@ -137,24 +137,47 @@ __global__ __launch_bounds__(kCoarseNodes) void start_check_kernel(const uint32_
     }
 }
 
-__global__ __launch_bounds__(256) void start_fine_kernel(const uint64_t* __restrict__ P,
-                                                         const uint32_t* __restrict__ posc, int lf,
-                                                         const LoopState* st, uint32_t* __restrict__ posf) {
+// Positions of the level-lf nodes: block c searches the nodes inside coarse
+// node c. It first reads kFineSamples evenly spaced keys of the coarse node's
+// range into LDS; each search then runs in LDS and ends with a binary search of
+// P only between the two samples that bracket its key.
+constexpr int kFineBlock = 256;
+constexpr uint32_t kFineSamples = 1024;
+
+__global__ __launch_bounds__(kFineBlock) void start_fine_kernel(const uint64_t* __restrict__ P,
+                                                                const uint32_t* __restrict__ posc, int lf,
+                                                                const LoopState* st, uint32_t* __restrict__ posf) {
+    __shared__ uint64_t samp[kFineSamples];
     if (!st->start_fine) return;
-    const uint32_t nodes = 1u << (3 * lf);
-    const int sub = 3 * (lf - kStartCoarse);  // fine nodes per coarse node: 2^sub
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j <= nodes; j += stride) {
-        const uint32_t p = j >> sub;
-        uint32_t at;
-        if ((j & ((1u << sub) - 1)) == 0) {
-            at = posc[p];  // a coarse boundary
-        } else {
+    const uint32_t per = 1u << (3 * (lf - kStartCoarse));  // fine nodes per coarse node
+    const uint32_t c = blockIdx.x;
+    const uint32_t a = posc[c], b = posc[c + 1];
+    const uint64_t len = b - a;
+    const uint32_t S = static_cast<uint32_t>(min<uint64_t>(len, kFineSamples));
+    // sample i sits at a + floor(len * i / S): strictly increasing, since S <= len
+    for (uint32_t i = threadIdx.x; i < S; i += kFineBlock) samp[i] = P[a + len * i / S];
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < per; t += kFineBlock) {
+        const uint32_t j = c * per + t;
+        uint32_t at = a;
+        if (t != 0 && S != 0) {
             const uint64_t key = static_cast<uint64_t>(j) << (3 * (kL - lf));
-            at = static_cast<uint32_t>(lower_bound_u64(P, posc[p], posc[p + 1], key));
+            uint32_t lo = 0, hi = S;  // first sample >= key
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (samp[mid] < key)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            // the answer lies after the sample below the key and at or before the one above it
+            const uint64_t from = lo == 0 ? a : a + len * (lo - 1) / S + 1;
+            const uint64_t to = lo == S ? b : a + len * lo / S;
+            at = static_cast<uint32_t>(lower_bound_u64(P, from, to, key));
         }
         posf[j] = at;
     }
+    if (c == kCoarseNodes - 1 && threadIdx.x == 0) posf[kCoarseNodes * per] = posc[kCoarseNodes];
 }
 
 // least counts of levels 4 .. lf - 1 from the finer positions (block minima,
@@ -554,8 +577,8 @@ cstone_status RebalanceLoop::begin(const uint64_t* P, size_t n, uint32_t n_crit,
                            un, w.posc);
         hipLaunchKernelGGL(start_check_kernel, dim3(1), dim3(kCoarseNodes), 0, stream, w.posc, n_crit, lf, w.st);
         if (lf > kStartCoarse) {
-            hipLaunchKernelGGL(start_fine_kernel, dim3(clamp_grid(grid_1d((size_t{1} << (3 * lf)) + 1, 256))),
-                               dim3(256), 0, stream, P, w.posc, lf, w.st, w.pos[1]);
+            hipLaunchKernelGGL(start_fine_kernel, dim3(kCoarseNodes), dim3(kFineBlock), 0, stream, P, w.posc, lf, w.st,
+                               w.pos[1]);
             if (lf > kStartCoarse + 1)
                 hipLaunchKernelGGL(start_mins_kernel, dim3(clamp_grid(grid_1d(size_t{1} << (3 * (lf - 1)), 256))),
                                    dim3(256), 0, stream, w.pos[1], lf, w.st);

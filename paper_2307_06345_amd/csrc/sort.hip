@@ -37,6 +37,45 @@ __global__ __launch_bounds__(256) void sort_init_kernel(uint32_t* ghist, size_t 
     }
 }
 
+// Set-up of a build's sort from the key kernel's per-block parts: block d < radix
+// sums digit d over the parts, block radix ORs the blocks' flags into *flag;
+// all blocks clear what sort_init_kernel clears (but the first digit's counts).
+__global__ __launch_bounds__(kKeyBlocksMax) void sort_setup_kernel(uint32_t* ghist, size_t ghist_words, uint32_t* err,
+                                                                  uint64_t* lb, size_t lb_words,
+                                                                  const uint32_t* __restrict__ parts, uint32_t nparts,
+                                                                  uint32_t radix, const uint32_t* __restrict__ bad,
+                                                                  uint32_t* flag) {
+    __shared__ uint32_t red[kKeyBlocksMax / kWave];
+    const uint32_t tid = threadIdx.x;
+    const size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + tid;
+    const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+    for (size_t i = t; i < lb_words; i += stride) lb[i] = 0;
+    for (size_t i = radix + t; i < ghist_words; i += stride) ghist[i] = 0;
+    const uint32_t d = blockIdx.x;
+    if (d <= radix) {  // block-uniform
+        uint32_t v = 0;
+        if (tid < nparts) v = d < radix ? parts[static_cast<size_t>(tid) * kMaxRadix + d] : bad[tid];
+        if (d < radix) {
+            v = wave_inclusive_sum(v);
+            if (lane_id() == kWave - 1) red[tid / kWave] = v;
+        } else {
+            v = __ballot(v != 0) ? CSTONE_FLAG_NONFINITE : 0u;
+            if (lane_id() == 0) red[tid / kWave] = v;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t acc = 0;
+            for (uint32_t w = 0; w < kKeyBlocksMax / kWave; ++w) acc = d < radix ? acc + red[w] : (acc | red[w]);
+            if (d < radix) {
+                ghist[d] = acc;
+            } else {
+                *flag = acc;
+                *err = 0;
+            }
+        }
+    }
+}
+
 // Counts of the first pass's digit ((key >> shift) & mask, mask = radix - 1).
 __global__ __launch_bounds__(kHistBlock) void sort_hist0_kernel(const uint64_t* __restrict__ keys, uint32_t n,
                                                                  uint32_t shift, uint32_t mask,
@@ -630,11 +669,10 @@ __device__ __forceinline__ void lds_sort_segment(const uint64_t* kin, const uint
 }
 
 // Sort the buckets at window positions [f, e) (f and e bucket starts, or e the
-// window's end at the end of the keys) into kout / vout. The window holds the
-// keys only. If no bucket is longer than kCountMax, every key is ranked inside
-// its bucket by counting the keys that precede it (smaller, or equal and
-// earlier); otherwise the values are staged too and the segment goes through
-// the LDS passes.
+// window's end at the end of the keys) into kout / vout; the window's keys and
+// values are in LDS. If no bucket is longer than kCountMax, every key is ranked
+// inside its bucket by counting the keys that precede it (smaller, or equal and
+// earlier); otherwise the segment goes through the LDS passes.
 template <int BITS, int BLOCK, int ITEMS>
 __device__ __forceinline__ void lds_sort_window(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
                                                 uint32_t* vout,
@@ -687,12 +725,6 @@ __device__ __forceinline__ void lds_sort_window(const uint64_t* kin, const uint3
     if (lane == 0) atomicMax(&sm.maxb, longest);
     __syncthreads();
     if (sm.maxb > kCountMax) {
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            const uint32_t j = static_cast<uint32_t>(i) * BLOCK + tid;
-            if (j >= f && j < e) sm.vals[j] = vin[lo + j];
-        }
-        __syncthreads();
         lds_sort_segment<BITS, BLOCK, ITEMS>(kin, vin, kout, vout, lo + f, e - f, true, lo, sm);
         return;
     }
@@ -713,10 +745,9 @@ __device__ __forceinline__ void lds_sort_window(const uint64_t* kin, const uint3
                 rank += (kq < kp || (kq == kp && q < j)) ? 1u : 0u;
             }
             dst[i] = lo + bs + rank;
-            if (dst[i] != lo + j) v[i] = vin[lo + j];
+            if (dst[i] != lo + j) v[i] = sm.vals[j];
         }
     }
-    __syncthreads();  // every old value this block moves has been read
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t j = static_cast<uint32_t>(i) * BLOCK + tid;
@@ -764,8 +795,9 @@ __device__ __forceinline__ void list_large(const LargeList& L, uint32_t start, u
 
 // Block b: the buckets (runs of equal key >> pshift) that start in keys
 // [b * chunk, (b + 1) * chunk), read from kin / vin, sorted into kout / vout.
-// The block reads its chunk and the look-ahead after it into LDS at once; only
-// a last bucket that runs past the look-ahead is searched for and read again.
+// The block reads its chunk and the look-ahead after it (keys and values) into
+// LDS at once; only a last bucket that runs past the look-ahead is searched for
+// and read again.
 //
 // The sort is in place. A block writes only the buckets it owns; what it
 // reads of other blocks' buckets (the look-ahead, the key before its chunk,
@@ -794,7 +826,10 @@ __global__ __launch_bounds__(BLOCK, kLocalBlocksPerCU * BLOCK / (4 * kWave)) voi
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t j = static_cast<uint32_t>(i) * BLOCK + tid;
-        if (j < wn) sm.keys[j] = kin[lo + j];
+        if (j < wn) {
+            sm.keys[j] = kin[lo + j];
+            sm.vals[j] = vin[lo + j];
+        }
     }
     const uint64_t before = lo ? kin[lo - 1] >> pshift : ~0ull;  // the same word in every lane
     __syncthreads();
@@ -1022,6 +1057,9 @@ struct SortWs {
     uint32_t* large_start;
     uint32_t* large_hist;
     size_t max_buckets, max_tiles_any;
+    // per-block first-digit counts and flags of a build's key kernel
+    uint32_t* key_parts;
+    uint32_t* key_bad;
     size_t bytes;
 };
 
@@ -1044,6 +1082,8 @@ SortWs carve_sort(void* ws, size_t n, bool with_perm) {
         s.large_tiles = c.take<uint4>(s.max_tiles_any);
         s.large_start = c.take<uint32_t>(s.max_buckets + 1);
         s.large_hist = c.take<uint32_t>((s.max_buckets + 1) * kLowPasses * kMaxRadix);
+        s.key_parts = c.take<uint32_t>(static_cast<size_t>(kKeyBlocksMax) * kMaxRadix);
+        s.key_bad = c.take<uint32_t>(kKeyBlocksMax);
     }
     s.bytes = c.off;
     return s;
@@ -1089,11 +1129,31 @@ cstone_status sort_prepare(void* ws, size_t n, bool with_perm, hipStream_t strea
     return CSTONE_OK;
 }
 
-uint32_t* sort_first_histogram(void* ws, size_t n, bool with_perm, int sig_bits, uint32_t* mask, uint32_t* shift) {
+void sort_key_parts(void* ws, size_t n, bool with_perm, int sig_bits, uint32_t** hist_parts, uint32_t** bad_parts,
+                    uint32_t* mask, uint32_t* shift) {
     const Variant& var = kVariants[default_variant()];
     *mask = (1u << var.bits) - 1u;
     *shift = use_split(n, sig_bits, with_perm, var) ? kSplitShift : 0u;
-    return carve_sort(ws, n, with_perm).ghist;
+    const SortWs s = carve_sort(ws, n, with_perm);
+    *hist_parts = s.key_parts;
+    *bad_parts = s.key_bad;
+}
+
+cstone_status sort_setup_from_keys(void* ws, size_t n, bool with_perm, uint32_t parts, uint32_t* flag,
+                                   hipStream_t stream) {
+    if (!with_perm || parts == 0 || parts > kKeyBlocksMax) return CSTONE_ERR_INVALID_ARG;
+    SortWs s = carve_sort(ws, n, with_perm);
+    const Variant& var = kVariants[default_variant()];
+    const size_t tile = static_cast<size_t>(var.block) * var.items;
+    const size_t words = ((n + tile - 1) / tile) << var.bits;
+    const bool wide = n >= (1ull << 30);
+    const size_t lb_words = std::min(s.lb_bytes / 8, wide ? words : (words + 1) / 2);
+    const uint32_t radix = 1u << var.bits;
+    hipLaunchKernelGGL(sort_setup_kernel, dim3(radix + 1), dim3(kKeyBlocksMax), 0, stream, s.ghist,
+                       static_cast<size_t>(kGhistWords), s.err, static_cast<uint64_t*>(s.lb), lb_words, s.key_parts,
+                       parts, radix, s.key_bad, flag);
+    CS_HIP(hipGetLastError());
+    return CSTONE_OK;
 }
 
 namespace {
