@@ -326,10 +326,14 @@ def main():
     model = byte_model(n, leaves_hist, nl_final)
 
     # dominant kernel: a later top digit pass (keys + permutation in and out).
-    # Sort intervals: the three top passes, the bucket pass, the low passes
-    split = len(passes) == 5
-    mid = passes[1:3] if split else (passes[1:] if len(passes) > 1 else passes)
-    pass_ms = sum(mid) / len(mid)
+    # Sort intervals: the first top pass, the two later top passes (one
+    # interval: no event between their launches), the bucket pass, the low passes
+    split = len(passes) == 4
+    if split:
+        pass_ms = passes[1] / 2
+    else:
+        mid = passes[1:] if len(passes) > 1 else passes
+        pass_ms = sum(mid) / len(mid)
     path = path_bytes(model, n)
     pass_bytes = 24 * n
     achieved = pass_bytes / (pass_ms * 1e-3) / 1e9
@@ -360,8 +364,8 @@ def main():
                      "kernel_source_digest": digest},
         "build": {"stage_ms": {"keys": stage[0], "sort": stage[1], "rebalance": stage[2], "link": stage[3]},
                   "sort_pass_ms": passes,
-                  "sort_pass_names": (["top 1 (bits 36-44)", "top 2 (bits 45-53)", "top 3 (bits 54-62)", "buckets", "low passes"]
-                                      if split else [f"digit {i}" for i in range(len(passes))]),
+                  "sort_pass_names": (["top pass 1 (bits 36-44)", "top passes 2 and 3 (bits 45-62)", "buckets",
+                                       "low passes"] if split else [f"digit {i}" for i in range(len(passes))]),
                   "model_bytes": model,
                   "model_fraction": model["total"] / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9),
                   "path_bytes": path,

@@ -203,8 +203,9 @@ CSTONE_API cstone_status cstone_link_octree_by_sort(const uint64_t* leaves, size
  */
 typedef struct cstone_timings {
     float stage_ms[4];     /* keys, sort, rebalance loop, link */
-    float sort_pass_ms[8]; /* the particle-key sort: its three top passes, the
-                              bucket pass and the low passes (5 entries) */
+    float sort_pass_ms[8]; /* the particle-key sort (4 entries): the first top
+                              pass, the two later top passes together, the
+                              bucket pass, the low passes */
     uint32_t sort_passes;  /* entries of sort_pass_ms in use */
 } cstone_timings;
 

@@ -23,8 +23,8 @@ cstone_status launch_keys(const double* x, const double* y, const double* z, siz
 // digits, then every bucket on its own), other sorts plain LSD passes.
 size_t sort_workspace_bytes(size_t n, bool with_perm);
 // pass_events: NULL, or sort_passes() + 1 events recorded before the first
-// pass and after every pass (split path: after each top pass, the bucket
-// sort and the low passes). prepared: sort_prepare() already ran on this
+// pass and after every pass (split path: after the first top pass, after the
+// last one, after the bucket sort and after the low passes). prepared: sort_prepare() already ran on this
 // workspace, or the key kernel stored its per-block counts of the first digit
 // and sort_setup_from_keys() ran, so neither step is repeated.
 // err_word: NULL, or a caller word (cleared beforehand) into which the sort's

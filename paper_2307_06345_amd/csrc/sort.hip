@@ -1108,7 +1108,7 @@ size_t sort_workspace_bytes(size_t n, bool with_perm) { return carve_sort(nullpt
 
 int sort_passes(size_t n, int sig_bits, bool with_perm) {
     const Variant& var = kVariants[default_variant()];
-    if (use_split(n, sig_bits, with_perm, var)) return kSplitTop + 2;  // top passes, buckets, low passes
+    if (use_split(n, sig_bits, with_perm, var)) return 4;  // top pass 1, the later top passes, buckets, low passes
     return (sig_bits + var.bits - 1) / var.bits;
 }
 
@@ -1189,7 +1189,10 @@ cstone_status launch_split(const uint64_t* keys_in, uint64_t* keys_out, uint32_t
         var.launch(a, p == 0, true, stream);
         src_k = a.keys_out;
         src_v = a.vals_out;
-        if (pass_events) CS_HIP(hipEventRecord(pass_events[p + 1], stream));
+        // events after the first and the last top pass only: the later top
+        // passes are timed together, with no event between their launches
+        if (pass_events && (p == 0 || p == kSplitTop - 1))
+            CS_HIP(hipEventRecord(pass_events[p == 0 ? 1 : 2], stream));
     }
     const uint32_t tile = static_cast<uint32_t>(var.block * var.items);
     LargeList L{};
@@ -1207,7 +1210,7 @@ cstone_status launch_split(const uint64_t* keys_in, uint64_t* keys_out, uint32_t
     const uint32_t chunks = static_cast<uint32_t>((n + kLocalChunk - 1) / kLocalChunk);
     hipLaunchKernelGGL((local_sort_kernel<kSplitBits, kLocalBlock, kLocalItems>), dim3(chunks), dim3(kLocalBlock), 0,
                        stream, keys_out, perm_out, static_cast<uint32_t>(n), kSplitShift, L, err);
-    if (pass_events) CS_HIP(hipEventRecord(pass_events[kSplitTop + 1], stream));
+    if (pass_events) CS_HIP(hipEventRecord(pass_events[3], stream));
     if (s.max_buckets > 0) {  // some bucket may be longer than one block sorts
         hipLaunchKernelGGL(large_hist_kernel, dim3(std::min(L.max_tiles, kListGrid)), dim3(512), 0, stream, keys_out,
                            static_cast<uint32_t>(n), L, static_cast<uint32_t>(radix - 1));
@@ -1232,7 +1235,7 @@ cstone_status launch_split(const uint64_t* keys_in, uint64_t* keys_out, uint32_t
             var.launch_list(a, g, s.large_count + 2 + p, stream);  // a tile counter per pass, cleared at set-up
         }
     }
-    if (pass_events) CS_HIP(hipEventRecord(pass_events[kSplitTop + 2], stream));
+    if (pass_events) CS_HIP(hipEventRecord(pass_events[4], stream));
     CS_HIP(hipGetLastError());
     return CSTONE_OK;
 }
@@ -1292,7 +1295,10 @@ cstone_status launch_sort(const uint64_t* keys_in, uint64_t* keys_out, uint32_t*
         var.launch(a, p == 0, with_perm, stream);
         src_k = a.keys_out;
         src_v = a.vals_out;
-        if (pass_events) CS_HIP(hipEventRecord(pass_events[p + 1], stream));
+        // events after the first and the last top pass only: the later top
+        // passes are timed together, with no event between their launches
+        if (pass_events && (p == 0 || p == kSplitTop - 1))
+            CS_HIP(hipEventRecord(pass_events[p == 0 ? 1 : 2], stream));
     }
     CS_HIP(hipGetLastError());
     return CSTONE_OK;
