@@ -395,6 +395,14 @@ __global__ __launch_bounds__(kRBlock) void round_kernel(uint32_t n, uint32_t n_c
 
 // ---- f for the next round: positions of the inner child boundaries ----------
 
+// Child boundaries of the listed splits: positions in P of the 7 inner
+// boundaries of each split leaf. A wave takes 8 splits, 8 lanes each. A range
+// of at most kSmallRange keys is read by its 8 lanes at once (16 keys each,
+// independent loads) and every boundary is the count of the range's keys below
+// it; longer ranges are searched by lanes 1..7 (binary search), or by the
+// whole wave when at least kWaveSearchMin long.
+constexpr uint32_t kSmallRange = 128;
+
 __global__ __launch_bounds__(kSearchBlock) void split_search_kernel(const uint64_t* __restrict__ P, uint32_t n,
                                                                      const uint64_t* __restrict__ K,
                                                                      const uint32_t* __restrict__ pos,
@@ -405,31 +413,56 @@ __global__ __launch_bounds__(kSearchBlock) void split_search_kernel(const uint64
     const uint64_t nl = st->nl[round];
     if (st->nl[round + 1] > capacity || nl > capacity) return;  // overflowed round: K' is discarded
     const uint32_t listed = min(st->nsplit[round], split_capacity);
-    const uint32_t work = listed * 7u;
     const uint32_t lane = lane_id();
+    const uint32_t t = lane & 7u;  // child boundary t (1..7) of the group's split
     const uint32_t waves = gridDim.x * (kSearchBlock / kWave);
     const uint32_t wave = blockIdx.x * (kSearchBlock / kWave) + threadIdx.x / kWave;
-    // few searches (early rounds, long ranges): one per wave; many: 64 per wave
-    const uint32_t chunk = max(1u, min(static_cast<uint32_t>(kWave), (work + waves - 1) / waves));
-    for (uint32_t base = wave * chunk; base < work; base += waves * chunk) {
-        const uint32_t w = base + lane;
-        bool valid = lane < chunk && w < work;
-        uint32_t lo = 0, hi = 0, dst = 0;
-        uint64_t key = 0;
+    for (uint32_t base = wave * 8u; base < listed; base += waves * 8u) {
+        const uint32_t sidx = base + (lane >> 3);
+        bool valid = sidx < listed;
+        uint32_t lo = 0, hi = 0, dst0 = 0;
+        uint64_t ki = 0, step = 0;
         if (valid) {
-            const uint64_t e = splits[w / 7u];
+            const uint64_t e = splits[sidx];
             const uint64_t i = e & 0xffffffffull;
-            const uint32_t c = w % 7u + 1u;
-            const uint64_t ki = K[i];
-            key = ki + c * ((K[i + 1] - ki) >> 3);
+            ki = K[i];
+            step = (K[i + 1] - ki) >> 3;
             hi = min(pos[i + 1], n);  // positions never exceed n; the clamps guard memory all the same
             lo = min(pos[i], hi);
-            dst = static_cast<uint32_t>(e >> 32) + c;
+            dst0 = static_cast<uint32_t>(e >> 32);
         }
-        valid = valid && dst <= capacity;  // always true for a listed split; guards memory
-        const bool wide = valid && hi - lo >= kWaveSearchMin;
-        if (valid && !wide) pos_out[dst] = static_cast<uint32_t>(lower_bound_u64(P, lo, hi, key));
-        uint64_t todo = __ballot(wide);
+        valid = valid && static_cast<uint64_t>(dst0) + 7u <= capacity;  // always true for a listed split
+        const uint64_t key = ki + t * step;
+        const bool small = valid && hi - lo <= kSmallRange;
+        // short ranges: every lane of the group counts its 16 keys below each boundary
+        uint32_t cnt[7] = {0, 0, 0, 0, 0, 0, 0};
+        if (small) {
+            uint64_t kq[kSmallRange / 8];
+#pragma unroll
+            for (uint32_t m = 0; m < kSmallRange / 8; ++m) {
+                const uint32_t q = lo + t + 8u * m;
+                kq[m] = q < hi ? P[q] : ~0ull;
+            }
+#pragma unroll
+            for (uint32_t m = 0; m < kSmallRange / 8; ++m)
+#pragma unroll
+                for (uint32_t c = 0; c < 7; ++c) cnt[c] += kq[m] < ki + (c + 1) * step ? 1u : 0u;
+        }
+#pragma unroll
+        for (uint32_t c = 0; c < 7; ++c) {  // sums over the group's 8 lanes (all lanes take part)
+            cnt[c] += __shfl_xor(cnt[c], 1, kWave);
+            cnt[c] += __shfl_xor(cnt[c], 2, kWave);
+            cnt[c] += __shfl_xor(cnt[c], 4, kWave);
+        }
+        if (small && t != 0) {
+            uint32_t below = 0;
+#pragma unroll
+            for (uint32_t c = 0; c < 7; ++c) below = c + 1 == t ? cnt[c] : below;
+            pos_out[dst0 + t] = lo + below;
+        }
+        const bool mid = valid && !small && t != 0 && hi - lo < kWaveSearchMin;
+        if (mid) pos_out[dst0 + t] = static_cast<uint32_t>(lower_bound_u64(P, lo, hi, key));
+        uint64_t todo = __ballot(valid && t != 0 && hi - lo >= kWaveSearchMin);
         while (todo) {
             const int l = __ffsll(static_cast<long long>(todo)) - 1;
             todo &= todo - 1;
@@ -437,7 +470,7 @@ __global__ __launch_bounds__(kSearchBlock) void split_search_kernel(const uint64
             const uint32_t l_hi = __shfl(hi, l, kWave);
             const uint64_t l_key = __shfl(key, l, kWave);
             const uint32_t at = wave_lower_bound(P, l_lo, l_hi, l_key);
-            if (static_cast<int>(lane) == l) pos_out[dst] = at;
+            if (static_cast<int>(lane) == l) pos_out[dst0 + t] = at;
         }
     }
 }
@@ -518,7 +551,7 @@ uint32_t clamp_grid(size_t blocks) {
 }
 
 // one wave per search while searches are few
-uint32_t search_grid(size_t searches) { return clamp_grid(grid_1d(searches, kSearchBlock / kWave)); }
+uint32_t search_grid(size_t splits) { return clamp_grid(grid_1d((splits + 7) / 8, kSearchBlock / kWave)); }  // 8 splits a wave
 
 }  // namespace
 
@@ -617,9 +650,8 @@ cstone_status RebalanceLoop::enqueue(uint32_t rounds) {
                            static_cast<uint32_t>(n_), n_crit_, bufK[q & 1], w.pos[q & 1], bufK[(q + 1) & 1],
                            w.pos[(q + 1) & 1], w.splits, w.split_capacity, w.st, static_cast<int>(q),
                            static_cast<uint64_t>(cap_), w.lb);
-        // one wave per search while searches are few
-        const size_t searches = 7 * std::min<size_t>(rows, w.split_capacity);
-        hipLaunchKernelGGL(split_search_kernel, dim3(search_grid(searches)),
+        const size_t max_splits = std::min<size_t>(rows, w.split_capacity);
+        hipLaunchKernelGGL(split_search_kernel, dim3(search_grid(max_splits)),
                            dim3(kSearchBlock), 0, stream_, P_, static_cast<uint32_t>(n_), bufK[q & 1], w.pos[q & 1],
                            w.pos[(q + 1) & 1],
                            w.splits, w.split_capacity, w.st, static_cast<int>(q), static_cast<uint64_t>(cap_));
@@ -982,7 +1014,7 @@ cstone_status launch_batch_rebalance(const uint64_t* P, size_t n_total, const Ba
                            sets, w.K[a], w.pos[a], w.sid[a], w.K[b], w.pos[b], w.sid[b], w.starts[b], n_sets,
                            w.changed_set + static_cast<size_t>(q) * n_sets, w.splits, cap_u, w.st,
                            static_cast<int>(q), static_cast<uint64_t>(C), w.lb);
-        hipLaunchKernelGGL(split_search_kernel, dim3(search_grid(7 * split_capacity)),
+        hipLaunchKernelGGL(split_search_kernel, dim3(search_grid(split_capacity)),
                            dim3(kSearchBlock), 0, stream, P, static_cast<uint32_t>(n_total), w.K[a], w.pos[a],
                            w.pos[b], w.splits, cap_u, w.st, static_cast<int>(q), static_cast<uint64_t>(C));
     }
