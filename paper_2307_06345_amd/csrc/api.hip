@@ -103,6 +103,7 @@ size_t cstone_build_workspace_bytes(size_t n, size_t leaf_capacity) {
     Carve c(nullptr);
     c.take<uint64_t>(n);  // unsorted keys
     c.take<uint32_t>(1);  // non-finite flag
+    c.take<uint32_t>(kLevel6Cells);  // first positions of the level-6 nodes (sort to loop)
     // the sort runs before the loop; the loop and the link share the stream
     // without a host check in between, so they get separate parts (the split
     // list of the loop is largest for n_crit = 1)
@@ -127,6 +128,8 @@ cstone_status cstone_build(const double* x, const double* y, const double* z, si
     Carve c(ws);
     uint64_t* keys = c.take<uint64_t>(n);
     uint32_t* flag = c.take<uint32_t>(1);
+    uint32_t* level6_table = c.take<uint32_t>(kLevel6Cells);
+    uint32_t* level6 = n && sort_uses_split(n, 63, true) ? level6_table : nullptr;
     void* stage_ws = static_cast<char*>(ws) + c.off;
     const size_t stage_bytes = ws_bytes - c.off;
 
@@ -163,14 +166,15 @@ cstone_status cstone_build(const double* x, const double* y, const double* z, si
                             bad_parts, &parts);
             if (s != CSTONE_OK) break;
             if (mark(1) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
-            if ((s = sort_setup_from_keys(stage_ws, n, true, parts, flag, stream)) != CSTONE_OK) break;
+            if ((s = sort_setup_from_keys(stage_ws, n, true, parts, flag, level6, stream)) != CSTONE_OK) break;
         } else {
             hipLaunchKernelGGL(clear_word_kernel, dim3(1), dim3(1), 0, stream, flag);
             if (mark(1) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
         }
-        // the sort reports a failed device-side wait into the same flag word
+        // the sort reports a failed device-side wait into the same flag word,
+        // and (split sort) hands the level-6 node positions to the loop's start
         s = launch_sort(keys, sorted_keys, perm, n, 63, stage_ws, stage_bytes, stream,
-                        timed && n ? pass_ev : nullptr, /*prepared=*/true, -1, flag);
+                        timed && n ? pass_ev : nullptr, /*prepared=*/true, -1, flag, level6);
         if (s != CSTONE_OK) break;
         if (mark(2) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
         if (nl == 0) nl = 1;  // start from the root leaf {0, 8^L}
@@ -181,7 +185,7 @@ cstone_status cstone_build(const double* x, const double* y, const double* z, si
         const size_t link_bytes = stage_bytes - reb_bytes;
         RebalanceLoop loop;
         s = loop.begin(sorted_keys, n, n_crit, leaves, nl, leaf_capacity, counts, max_iters, stage_ws, reb_bytes,
-                       stream, flag);
+                       stream, flag, level6);
         if (s != CSTONE_OK) break;
         // The link is enqueued behind the first batch of rounds (usually the
         // last one), so one synchronisation serves both; if more rounds are

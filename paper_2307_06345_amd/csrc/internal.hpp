@@ -7,6 +7,10 @@ namespace cs {
 
 // keys.hip
 constexpr uint32_t kKeyBlocksMax = 512;  // blocks of the plain key kernel (grid-stride beyond)
+
+// First positions of the level-6 nodes, handed from the sort to the loop's start
+constexpr uint32_t kLevel6Cells = 1u << 18;
+constexpr uint32_t kCellEmpty = 0xffffffffu;
 // flags: NULL, or a word into which CSTONE_FLAG_NONFINITE is OR-ed.
 // hist_parts: NULL, or kKeyBlocksMax rows of 512 words; block b stores the
 // count of every key's ((key >> hist_shift) & hist_mask) into row b.
@@ -30,10 +34,13 @@ size_t sort_workspace_bytes(size_t n, bool with_perm);
 // err_word: NULL, or a caller word (cleared beforehand) into which the sort's
 // kernels OR their error bits (a look-back wait that gave up, a bucket-list
 // overflow), all above the public CSTONE_FLAG_* bits.
+// level6: NULL, or kLevel6Cells words set to kCellEmpty by the set-up; the
+// split sort stores there the first position of every non-empty level-6 node.
 cstone_status launch_sort(const uint64_t* keys_in, uint64_t* keys_out, uint32_t* perm_out, size_t n,
                           int sig_bits, void* ws, size_t ws_bytes, hipStream_t stream,
                           hipEvent_t* pass_events = nullptr, bool prepared = false, int variant = -1,
-                          uint32_t* err_word = nullptr);
+                          uint32_t* err_word = nullptr, uint32_t* level6 = nullptr);
+bool sort_uses_split(size_t n, int sig_bits, bool with_perm);
 // clear_word: NULL, or one caller word zeroed by the same launch; variant: the
 // sort shape the passes will use (-1: the default)
 cstone_status sort_prepare(void* ws, size_t n, bool with_perm, hipStream_t stream, uint32_t* clear_word = nullptr,
@@ -46,7 +53,7 @@ void sort_key_parts(void* ws, size_t n, bool with_perm, int sig_bits, uint32_t**
 // build): the first digit's counts are the sum of the `parts` rows, *flag the
 // OR of the blocks' flags, and everything sort_prepare clears is cleared.
 cstone_status sort_setup_from_keys(void* ws, size_t n, bool with_perm, uint32_t parts, uint32_t* flag,
-                                   hipStream_t stream);
+                                   uint32_t* level6, hipStream_t stream);
 int sort_passes(size_t n, int sig_bits, bool with_perm);
 
 // ---- batched builds: many independent sets in one pass of every stage -------
@@ -133,7 +140,8 @@ class RebalanceLoop {
 public:
     cstone_status begin(const uint64_t* sorted_keys, size_t n, uint32_t n_crit, uint64_t* leaves, size_t n_leaves,
                         size_t leaf_capacity, uint32_t* counts, uint32_t max_iters, void* ws, size_t ws_bytes,
-                        hipStream_t stream, const uint32_t* input_flags);
+                        hipStream_t stream, const uint32_t* input_flags,
+                        const uint32_t* level6 = nullptr);
     // enqueue the next batch of rounds (0: the expected number) and the finalize step
     cstone_status enqueue(uint32_t rounds = 0);
     // device word holding the leaf count of the array left in `leaves`

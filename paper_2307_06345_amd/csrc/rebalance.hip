@@ -137,6 +137,33 @@ __global__ __launch_bounds__(kCoarseNodes) void start_check_kernel(const uint32_
     }
 }
 
+// Level-3 and level-lf positions from the sort's level-6 table: the first
+// position at or after node j's start is that of the first non-empty level-6
+// node at or after it; up to 64 entries are scanned, then P is searched.
+__global__ __launch_bounds__(256) void start_table_kernel(const uint64_t* __restrict__ P, uint32_t n,
+                                                          const uint32_t* __restrict__ level6, int lf,
+                                                          uint32_t* __restrict__ posc, uint32_t* __restrict__ posf) {
+    const uint32_t nodes = 1u << (3 * lf);
+    const int sh = 3 * (kStartFine - lf);   // level-6 nodes per level-lf node: 2^sh
+    const int up = 3 * (lf - kStartCoarse);  // level-lf nodes per level-3 node: 2^up
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j <= nodes; j += stride) {
+        const uint32_t c0 = j << sh;
+        uint32_t at = n;
+        if (c0 < kLevel6Cells) {
+            const uint32_t c1 = min(c0 + 64u, kLevel6Cells);
+            uint32_t c = c0;
+            while (c < c1 && level6[c] == kCellEmpty) ++c;
+            if (c < c1)
+                at = level6[c];
+            else if (c < kLevel6Cells)  // a long empty run: search
+                at = static_cast<uint32_t>(lower_bound_u64(P, 0, n, static_cast<uint64_t>(c0) << (3 * (kL - kStartFine))));
+        }
+        posf[j] = at;
+        if ((j & ((1u << up) - 1)) == 0) posc[j >> up] = at;
+    }
+}
+
 // Positions of the level-lf nodes: block c searches the nodes inside coarse
 // node c. It first reads kFineSamples evenly spaced keys of the coarse node's
 // range into LDS; each search then runs in LDS and ends with a binary search of
@@ -570,7 +597,7 @@ size_t rebalance_workspace_bytes(size_t n, uint32_t n_crit, size_t leaf_capacity
 
 cstone_status RebalanceLoop::begin(const uint64_t* P, size_t n, uint32_t n_crit, uint64_t* leaves, size_t nl0,
                                    size_t cap, uint32_t* counts, uint32_t max_iters, void* ws, size_t ws_bytes,
-                                   hipStream_t stream, const uint32_t* input_flags) {
+                                   hipStream_t stream, const uint32_t* input_flags, const uint32_t* level6) {
     RebalanceWs w = carve_rebalance(ws, n, n_crit, cap);
     if (ws_bytes < w.bytes) return CSTONE_ERR_INVALID_ARG;
     if (nl0 < 1 || nl0 > cap || cap >= 0xffffffffull) return CSTONE_ERR_INVALID_ARG;
@@ -606,12 +633,19 @@ cstone_status RebalanceLoop::begin(const uint64_t* P, size_t n, uint32_t n_crit,
     if (start_top_) {
         const int lf = start_top_;
         const uint32_t un = static_cast<uint32_t>(n);
-        hipLaunchKernelGGL(start_coarse_kernel, dim3(grid_1d(kCoarseNodes + 1, 256 / kWave)), dim3(256), 0, stream, P,
-                           un, w.posc);
+        // positions of the level-3 and level-lf nodes: from the sort's level-6
+        // table when there is one, else by searching P
+        if (level6)
+            hipLaunchKernelGGL(start_table_kernel, dim3(clamp_grid(grid_1d((size_t{1} << (3 * lf)) + 1, 256))),
+                               dim3(256), 0, stream, P, un, level6, lf, w.posc, w.pos[1]);
+        else
+            hipLaunchKernelGGL(start_coarse_kernel, dim3(grid_1d(kCoarseNodes + 1, 256 / kWave)), dim3(256), 0, stream,
+                               P, un, w.posc);
         hipLaunchKernelGGL(start_check_kernel, dim3(1), dim3(kCoarseNodes), 0, stream, w.posc, n_crit, lf, w.st);
         if (lf > kStartCoarse) {
-            hipLaunchKernelGGL(start_fine_kernel, dim3(kCoarseNodes), dim3(kFineBlock), 0, stream, P, w.posc, lf, w.st,
-                               w.pos[1]);
+            if (!level6)
+                hipLaunchKernelGGL(start_fine_kernel, dim3(kCoarseNodes), dim3(kFineBlock), 0, stream, P, w.posc, lf,
+                                   w.st, w.pos[1]);
             if (lf > kStartCoarse + 1)
                 hipLaunchKernelGGL(start_mins_kernel, dim3(clamp_grid(grid_1d(size_t{1} << (3 * (lf - 1)), 256))),
                                    dim3(256), 0, stream, w.pos[1], lf, w.st);

@@ -44,12 +44,14 @@ __global__ __launch_bounds__(kKeyBlocksMax) void sort_setup_kernel(uint32_t* ghi
                                                                   uint64_t* lb, size_t lb_words,
                                                                   const uint32_t* __restrict__ parts, uint32_t nparts,
                                                                   uint32_t radix, const uint32_t* __restrict__ bad,
-                                                                  uint32_t* flag) {
+                                                                  uint32_t* flag, uint32_t* level6) {
     __shared__ uint32_t red[kKeyBlocksMax / kWave];
     const uint32_t tid = threadIdx.x;
     const size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + tid;
     const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
     for (size_t i = t; i < lb_words; i += stride) lb[i] = 0;
+    if (level6)
+        for (size_t i = t; i < kLevel6Cells; i += stride) level6[i] = kCellEmpty;
     for (size_t i = radix + t; i < ghist_words; i += stride) ghist[i] = 0;
     const uint32_t d = blockIdx.x;
     if (d <= radix) {  // block-uniform
@@ -803,9 +805,12 @@ __device__ __forceinline__ void list_large(const LargeList& L, uint32_t start, u
 // reads of other blocks' buckets (the look-ahead, the key before its chunk,
 // the run-end search) it uses only for prefixes, which sorting inside a bucket
 // leaves unchanged at every position.
+//
+// level6 (NULL, or kLevel6Cells words set to kCellEmpty): the first position
+// of every non-empty level-6 node (key >> 45), found with the bucket starts.
 template <int BITS, int BLOCK, int ITEMS>
 __global__ __launch_bounds__(BLOCK, kLocalBlocksPerCU * BLOCK / (4 * kWave)) void local_sort_kernel(
-    uint64_t* keys, uint32_t* vals, uint32_t n, uint32_t pshift, LargeList large, uint32_t* err) {
+    uint64_t* keys, uint32_t* vals, uint32_t n, uint32_t pshift, LargeList large, uint32_t* err, uint32_t* level6) {
     const uint64_t* kin = keys;
     const uint32_t* vin = vals;
     uint64_t* kout = keys;
@@ -845,6 +850,9 @@ __global__ __launch_bounds__(BLOCK, kLocalBlocksPerCU * BLOCK / (4 * kWave)) voi
                 if (j < own) {
                     first = min(first, j);
                     last = max(last, j);
+                    // a level-6 node starts here too if the key's top 18 bits changed
+                    const uint32_t up = 45u - pshift;
+                    if (level6 && (pj >> up) != (pp >> up)) level6[pj >> up] = lo + j;
                 } else {
                     after = min(after, j);
                 }
@@ -1140,7 +1148,7 @@ void sort_key_parts(void* ws, size_t n, bool with_perm, int sig_bits, uint32_t**
 }
 
 cstone_status sort_setup_from_keys(void* ws, size_t n, bool with_perm, uint32_t parts, uint32_t* flag,
-                                   hipStream_t stream) {
+                                   uint32_t* level6, hipStream_t stream) {
     if (!with_perm || parts == 0 || parts > kKeyBlocksMax) return CSTONE_ERR_INVALID_ARG;
     SortWs s = carve_sort(ws, n, with_perm);
     const Variant& var = kVariants[default_variant()];
@@ -1151,9 +1159,13 @@ cstone_status sort_setup_from_keys(void* ws, size_t n, bool with_perm, uint32_t 
     const uint32_t radix = 1u << var.bits;
     hipLaunchKernelGGL(sort_setup_kernel, dim3(radix + 1), dim3(kKeyBlocksMax), 0, stream, s.ghist,
                        static_cast<size_t>(kGhistWords), s.err, static_cast<uint64_t*>(s.lb), lb_words, s.key_parts,
-                       parts, radix, s.key_bad, flag);
+                       parts, radix, s.key_bad, flag, level6);
     CS_HIP(hipGetLastError());
     return CSTONE_OK;
+}
+
+bool sort_uses_split(size_t n, int sig_bits, bool with_perm) {
+    return use_split(n, sig_bits, with_perm, kVariants[default_variant()]);
 }
 
 namespace {
@@ -1163,7 +1175,7 @@ namespace {
 // listed buckets keys_out -> alt -> ... -> keys_out.
 cstone_status launch_split(const uint64_t* keys_in, uint64_t* keys_out, uint32_t* perm_out, size_t n,
                            const SortWs& s, const Variant& var, bool wide, hipStream_t stream,
-                           hipEvent_t* pass_events, uint32_t* err) {
+                           hipEvent_t* pass_events, uint32_t* err, uint32_t* level6) {
     constexpr int radix = 1 << kSplitBits;
     uint32_t* lb32[2] = {static_cast<uint32_t*>(s.lb), static_cast<uint32_t*>(s.lb) + s.rows * kMaxRadix};
     if (pass_events) CS_HIP(hipEventRecord(pass_events[0], stream));
@@ -1209,7 +1221,7 @@ cstone_status launch_split(const uint64_t* keys_in, uint64_t* keys_out, uint32_t
     L.wide = wide ? 1u : 0u;
     const uint32_t chunks = static_cast<uint32_t>((n + kLocalChunk - 1) / kLocalChunk);
     hipLaunchKernelGGL((local_sort_kernel<kSplitBits, kLocalBlock, kLocalItems>), dim3(chunks), dim3(kLocalBlock), 0,
-                       stream, keys_out, perm_out, static_cast<uint32_t>(n), kSplitShift, L, err);
+                       stream, keys_out, perm_out, static_cast<uint32_t>(n), kSplitShift, L, err, level6);
     if (pass_events) CS_HIP(hipEventRecord(pass_events[3], stream));
     if (s.max_buckets > 0) {  // some bucket may be longer than one block sorts
         hipLaunchKernelGGL(large_hist_kernel, dim3(std::min(L.max_tiles, kListGrid)), dim3(512), 0, stream, keys_out,
@@ -1244,7 +1256,7 @@ cstone_status launch_split(const uint64_t* keys_in, uint64_t* keys_out, uint32_t
 
 cstone_status launch_sort(const uint64_t* keys_in, uint64_t* keys_out, uint32_t* perm_out, size_t n,
                           int sig_bits, void* ws, size_t ws_bytes, hipStream_t stream, hipEvent_t* pass_events,
-                          bool prepared, int variant, uint32_t* err_word) {
+                          bool prepared, int variant, uint32_t* err_word, uint32_t* level6) {
     const bool with_perm = perm_out != nullptr;
     SortWs s = carve_sort(ws, n, with_perm);
     if (ws_bytes < s.bytes) return CSTONE_ERR_INVALID_ARG;
@@ -1269,7 +1281,7 @@ cstone_status launch_sort(const uint64_t* keys_in, uint64_t* keys_out, uint32_t*
                            s.ghist);
     }
     uint32_t* err = err_word ? err_word : s.err;
-    if (split) return launch_split(keys_in, keys_out, perm_out, n, s, var, wide, stream, pass_events, err);
+    if (split) return launch_split(keys_in, keys_out, perm_out, n, s, var, wide, stream, pass_events, err, level6);
 
     uint32_t* lb32[2] = {static_cast<uint32_t*>(s.lb), static_cast<uint32_t*>(s.lb) + s.rows * kMaxRadix};
     if (pass_events) CS_HIP(hipEventRecord(pass_events[0], stream));

@@ -319,6 +319,24 @@ def test_build_nonfinite_reported():
     assert e.value.name == "NONFINITE"
 
 
+def test_build_start_from_sort_table_empty_cells():
+    """Builds from the root whose start reads the sort's level-6 table: one
+    with empty cells in the last x slab (the start stops between levels), one
+    clustered in a corner (runs of more than 64 empty level-6 cells, found by
+    searching P instead)."""
+    rng = np.random.default_rng(61)
+    n = 1 << 20
+    x, y, z = rng.random((3, n))
+    cases = [("slab", wl.ParticleSet(x * 0.9, y, z, wl.UNIT_BOX, wl.HILBERT, 8, "uniform")),
+             ("corner", wl.ParticleSet(np.where(np.arange(n) % 97 == 0, x, x * 0.02), y * 0.03, z, wl.UNIT_BOX,
+                                       wl.MORTON, 16, "clustered"))]
+    for what, s in cases:
+        say("build from the level-6 table,", what)
+        r = cs.build(*coords(s), s.box, s.curve, s.n_crit)
+        ref = _check_build(s, r, what)
+        assert r.rounds == oracle.rebalance_iterate(ref["P"], np.array([0, END], np.uint64), s.n_crit)[2]
+
+
 def test_build_uniform_2_24_full_parity():
     s = wl.config_uniform_2_24()
     say("build 2^24 uniform Hilbert N_crit 64")
