@@ -119,6 +119,8 @@ constexpr int kMaxRounds = 64;
 struct LoopState {
     uint64_t nl[kMaxRounds + 1];    // leaves entering round r (batched: entries, closing keys included)
     uint32_t changed[kMaxRounds];   // some O_i != 1 in round r
+    uint32_t merged[kMaxRounds];    // some O_i == 0 in round r
+    uint32_t over[kMaxRounds];      // a child of a leaf split in round r holds more than n_crit (and can split)
     uint32_t counters[kMaxRounds];  // dynamic tile counter of round r
     uint32_t nsplit[kMaxRounds];    // split leaves listed in round r
     uint32_t err;

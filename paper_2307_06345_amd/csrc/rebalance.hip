@@ -68,6 +68,8 @@ __global__ __launch_bounds__(256) void loop_init_kernel(LoopState* st, uint64_t 
     for (size_t i = t; i < lb_words; i += stride) lb[i] = 0;
     if (t < kMaxRounds) {
         st->changed[t] = 0;
+        st->merged[t] = 0;
+        st->over[t] = 0;
         st->counters[t] = 0;
         st->nsplit[t] = 0;
     }
@@ -275,16 +277,24 @@ __global__ __launch_bounds__(kRBlock) void round_kernel(uint32_t n, uint32_t n_c
     __shared__ uint64_t tile_prefix;
     __shared__ uint32_t split_base;
     __shared__ uint32_t any_change;
+    __shared__ uint32_t any_merge;
     __shared__ uint64_t sK[kRSpan];  // K[base - kRHalo ...], then the tile's new entries
     __shared__ uint32_t sP[kRSpan];
 
-    if (round > 0 && st->changed[round - 1] == 0) return;  // converged in an earlier round
+    // Converged in an earlier round; or the last round only split, and no new
+    // child can split (this round would copy every leaf: merges need 8 leaves
+    // whose sum is at most n_crit, and no such group was made or changed)
+    if (round > 0 && (st->changed[round - 1] == 0 || (st->merged[round - 1] == 0 && st->over[round - 1] == 0)))
+        return;
     const uint64_t nl = st->nl[round];
     if (nl == 0 || nl > capacity) return;  // an earlier round overflowed
     const uint32_t tiles = static_cast<uint32_t>((nl + kRTile - 1) / kRTile);
     const uint32_t tid = threadIdx.x;
     const uint32_t epoch = static_cast<uint32_t>(round + 1);
-    if (tid == 0) any_change = 0;
+    if (tid == 0) {
+        any_change = 0;
+        any_merge = 0;
+    }
 
     for (;;) {
         const uint32_t tile = take_tile(&st->counters[round], &slot);
@@ -306,7 +316,7 @@ __global__ __launch_bounds__(kRBlock) void round_kernel(uint32_t n, uint32_t n_c
         uint64_t kk[kRItems + 1];
         uint32_t pp[kRItems];
         uint32_t osum = 0, nsplit = 0;
-        bool changed = false;
+        bool changed = false, merged = false;
 #pragma unroll
         for (int j = 0; j <= kRItems; ++j) kk[j] = sK[kRHalo + lfirst + j];
 #pragma unroll
@@ -330,11 +340,13 @@ __global__ __launch_bounds__(kRBlock) void round_kernel(uint32_t n, uint32_t n_c
                         o = 0;  // 8 sibling leaves with at most n_crit particles: merge
                 }
                 changed |= (o != 1);
+                merged |= (o == 0);
             }
             op[j] = o;
             osum += o;
             nsplit += o == 8;
         }
+        if (merged) any_merge = 1;
 
         // g2: exclusive scan of O (low word) and of the split count (high word)
         uint64_t block_total;
@@ -418,6 +430,7 @@ __global__ __launch_bounds__(kRBlock) void round_kernel(uint32_t n, uint32_t n_c
         __syncthreads();
     }
     if (tid == 0 && any_change) atomicOr(&st->changed[round], 1u);
+    if (tid == 0 && any_merge) atomicOr(&st->merged[round], 1u);
 }
 
 // ---- f for the next round: positions of the inner child boundaries ----------
@@ -435,8 +448,8 @@ __global__ __launch_bounds__(kSearchBlock) void split_search_kernel(const uint64
                                                                      const uint32_t* __restrict__ pos,
                                                                      uint32_t* __restrict__ pos_out,
                                                                      const uint64_t* __restrict__ splits,
-                                                                     uint32_t split_capacity, const LoopState* st,
-                                                                     int round, uint64_t capacity) {
+                                                                     uint32_t split_capacity, LoopState* st,
+                                                                     int round, uint64_t capacity, uint32_t n_crit) {
     const uint64_t nl = st->nl[round];
     if (st->nl[round + 1] > capacity || nl > capacity) return;  // overflowed round: K' is discarded
     const uint32_t listed = min(st->nsplit[round], split_capacity);
@@ -481,14 +494,19 @@ __global__ __launch_bounds__(kSearchBlock) void split_search_kernel(const uint64
             cnt[c] += __shfl_xor(cnt[c], 2, kWave);
             cnt[c] += __shfl_xor(cnt[c], 4, kWave);
         }
+        uint32_t b = lo;  // this lane's boundary (lane 0 of a group: the range's start)
         if (small && t != 0) {
             uint32_t below = 0;
 #pragma unroll
             for (uint32_t c = 0; c < 7; ++c) below = c + 1 == t ? cnt[c] : below;
-            pos_out[dst0 + t] = lo + below;
+            b = lo + below;
+            pos_out[dst0 + t] = b;
         }
         const bool mid = valid && !small && t != 0 && hi - lo < kWaveSearchMin;
-        if (mid) pos_out[dst0 + t] = static_cast<uint32_t>(lower_bound_u64(P, lo, hi, key));
+        if (mid) {
+            b = static_cast<uint32_t>(lower_bound_u64(P, lo, hi, key));
+            pos_out[dst0 + t] = b;
+        }
         uint64_t todo = __ballot(valid && t != 0 && hi - lo >= kWaveSearchMin);
         while (todo) {
             const int l = __ffsll(static_cast<long long>(todo)) - 1;
@@ -497,8 +515,15 @@ __global__ __launch_bounds__(kSearchBlock) void split_search_kernel(const uint64
             const uint32_t l_hi = __shfl(hi, l, kWave);
             const uint64_t l_key = __shfl(key, l, kWave);
             const uint32_t at = wave_lower_bound(P, l_lo, l_hi, l_key);
-            if (static_cast<int>(lane) == l) pos_out[dst0 + t] = at;
+            if (static_cast<int>(lane) == l) {
+                pos_out[dst0 + t] = at;
+                b = at;
+            }
         }
+        // does a new child hold more than n_crit (and could split: span above 1)?
+        const uint32_t before = __shfl(b, static_cast<int>(lane) - 1, kWave);  // lane 0's value is not used
+        const bool over = valid && t != 0 && step > 1 && (b - before > n_crit || (t == 7 && hi - b > n_crit));
+        if (__ballot(over) != 0ull && lane == 0) atomicOr(&st->over[round], 1u);
     }
 }
 
@@ -508,14 +533,19 @@ struct Outcome {
     uint32_t last;     // rounds completed (the array after them is the result)
     uint32_t code;     // 0 running, 1 converged, 2 capacity exceeded
     uint64_t nl;       // leaves of that array
+    uint32_t buf;      // which of the two arrays holds it (the parity of the rounds that ran)
 };
 
-__device__ __forceinline__ Outcome loop_outcome(const LoopState* st, uint32_t enqueued, uint64_t capacity) {
+__device__ __forceinline__ Outcome loop_outcome(const LoopState* st, uint32_t enqueued, uint64_t capacity,
+                                                bool settle = true) {
     for (uint32_t q = 0; q < enqueued; ++q) {
-        if (st->nl[q + 1] > capacity) return {q, 2u, st->nl[q]};
-        if (st->changed[q] == 0) return {q + 1, 1u, st->nl[q + 1]};  // round q copied every leaf
+        if (st->nl[q + 1] > capacity) return {q, 2u, st->nl[q], q & 1u};
+        if (st->changed[q] == 0) return {q + 1, 1u, st->nl[q + 1], (q + 1) & 1u};  // round q copied every leaf
+        // round q + 1 (enqueued) would copy every leaf: it did not run, and counts
+        if (settle && q + 1 < enqueued && st->merged[q] == 0 && st->over[q] == 0)
+            return {q + 2, 1u, st->nl[q + 1], (q + 1) & 1u};
     }
-    return {enqueued, 0u, st->nl[enqueued]};
+    return {enqueued, 0u, st->nl[enqueued], enqueued & 1u};
 }
 
 // Leaves the result array in K[0] (copied from K[1] when an odd number of
@@ -527,7 +557,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(LoopState* st, uint32_t e
                                                        uint32_t* __restrict__ counts) {
     const Outcome o = loop_outcome(st, enqueued, capacity);
     const uint64_t nl = o.nl <= capacity ? o.nl : 0;
-    const bool odd = o.last & 1u;
+    const bool odd = o.buf != 0;
     const uint32_t* pos = odd ? pos1 : pos0;
     const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
     for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i <= nl; i += stride) {
@@ -687,8 +717,8 @@ cstone_status RebalanceLoop::enqueue(uint32_t rounds) {
         const size_t max_splits = std::min<size_t>(rows, w.split_capacity);
         hipLaunchKernelGGL(split_search_kernel, dim3(search_grid(max_splits)),
                            dim3(kSearchBlock), 0, stream_, P_, static_cast<uint32_t>(n_), bufK[q & 1], w.pos[q & 1],
-                           w.pos[(q + 1) & 1],
-                           w.splits, w.split_capacity, w.st, static_cast<int>(q), static_cast<uint64_t>(cap_));
+                           w.pos[(q + 1) & 1], w.splits, w.split_capacity, w.st, static_cast<int>(q),
+                           static_cast<uint64_t>(cap_), n_crit_);
     }
     enqueued_ += rounds;
     hipLaunchKernelGGL(finalize_kernel, dim3(clamp_grid(grid_1d(cap_ + 1, 256))), dim3(256), 0, stream_, w.st,
@@ -779,6 +809,8 @@ __global__ __launch_bounds__(256) void batch_init_kernel(LoopState* st, const Ba
     }
     if (t < kMaxRounds) {
         st->changed[t] = 0;
+        st->merged[t] = 0;
+        st->over[t] = 0;
         st->counters[t] = 0;
         st->nsplit[t] = 0;
     }
@@ -939,7 +971,7 @@ __global__ __launch_bounds__(256) void batch_finalize_kernel(LoopState* st, uint
                                                              const uint32_t* __restrict__ set_flags,
                                                              uint64_t* __restrict__ leaves, uint32_t* __restrict__ counts,
                                                              BatchResult* __restrict__ results) {
-    const Outcome o = loop_outcome(st, enqueued, capacity);
+    const Outcome o = loop_outcome(st, enqueued, capacity, false);  // batched rounds do not record merges
     const uint64_t M = o.nl <= capacity ? o.nl : 0;
     const bool odd = o.last & 1u;
     const uint64_t* K = odd ? K1 : K0;
@@ -1050,7 +1082,8 @@ cstone_status launch_batch_rebalance(const uint64_t* P, size_t n_total, const Ba
                            static_cast<int>(q), static_cast<uint64_t>(C), w.lb);
         hipLaunchKernelGGL(split_search_kernel, dim3(search_grid(split_capacity)),
                            dim3(kSearchBlock), 0, stream, P, static_cast<uint32_t>(n_total), w.K[a], w.pos[a],
-                           w.pos[b], w.splits, cap_u, w.st, static_cast<int>(q), static_cast<uint64_t>(C));
+                           w.pos[b], w.splits, cap_u, w.st, static_cast<int>(q), static_cast<uint64_t>(C),
+                           0xffffffffu);  // batched rounds do not use the over flag
     }
     hipLaunchKernelGGL(batch_finalize_kernel, dim3(clamp_grid(grid_1d(C + 1, 256))), dim3(256), 0, stream, w.st,
                        rounds, static_cast<uint64_t>(C), sets, n_sets, w.K[0], w.K[1], w.pos[0], w.pos[1], w.sid[0],
