@@ -822,7 +822,7 @@ __global__ __launch_bounds__(256) void batch_init_kernel(LoopState* st, const Ba
     }
 }
 
-__global__ __launch_bounds__(kRBlock) void batch_round_kernel(const BatchSet* __restrict__ sets,
+__global__ __launch_bounds__(kRBlock, 4) void batch_round_kernel(const BatchSet* __restrict__ sets,
                                                                const uint64_t* __restrict__ K,
                                                                const uint32_t* __restrict__ pos,
                                                                const uint32_t* __restrict__ sid,
@@ -839,6 +839,9 @@ __global__ __launch_bounds__(kRBlock) void batch_round_kernel(const BatchSet* __
     __shared__ uint64_t tile_prefix;
     __shared__ uint32_t split_base;
     __shared__ uint32_t any_change;
+    __shared__ uint64_t sK[kRSpan];  // entries base-8 .., then the tile's new entries
+    __shared__ uint32_t sP[kRSpan];
+    __shared__ uint32_t sS[kRSpan];
 
     if (round > 0 && st->changed[round - 1] == 0) return;  // every set converged earlier
     const uint64_t M = st->nl[round];
@@ -851,30 +854,48 @@ __global__ __launch_bounds__(kRBlock) void batch_round_kernel(const BatchSet* __
     for (;;) {
         const uint32_t tile = take_tile(&st->counters[round], &slot);
         if (tile >= tiles) break;
-        const uint64_t first = static_cast<uint64_t>(tile) * kRTile + static_cast<uint64_t>(tid) * kRItems;
+        const int64_t base = static_cast<int64_t>(tile) * kRTile;
+        for (int j = tid; j < kRSpan; j += kRBlock) {  // coalesced: entries base-8 .. base+2055 that exist
+            const int64_t g = base - kRHalo + j;
+            if (g >= 0 && g < static_cast<int64_t>(M)) {
+                sK[j] = K[g];
+                sP[j] = pos[g];
+                sS[j] = sid[g];
+            }
+        }
+        __syncthreads();
+        const uint32_t lfirst = tid * kRItems;
+        const uint64_t first = static_cast<uint64_t>(base) + lfirst;
 
         uint32_t op[kRItems];
+        uint64_t kk[kRItems + 1];  // this thread's entries and the next one
+        uint32_t pp[kRItems], ss[kRItems];
         uint32_t osum = 0, nsplit = 0;
         bool changed = false;
         uint32_t flagged = 0xffffffffu;  // last set whose change this thread reported
 #pragma unroll
+        for (int j = 0; j <= kRItems; ++j) kk[j] = sK[kRHalo + lfirst + j];
+#pragma unroll
         for (int j = 0; j < kRItems; ++j) {
             const uint64_t e = first + j;
+            const int li = kRHalo + static_cast<int>(lfirst) + j;
             uint32_t o = 0;
+            pp[j] = sP[li];
+            ss[j] = sS[li];
             if (e < M) {
-                const uint64_t ke = K[e];
+                const uint64_t ke = kk[j];
                 o = 1;
                 if (ke != kKeyEnd) {  // a leaf (closing entries are kept)
-                    const uint32_t s = sid[e];
+                    const uint32_t s = ss[j];
                     const uint32_t nc = sets[s].n_crit;
-                    const uint64_t delta = K[e + 1] - ke;
-                    const uint32_t cnt = pos[e + 1] - pos[e];
+                    const uint64_t delta = kk[j + 1] - ke;
+                    const uint32_t cnt = sP[li + 1] - pp[j];
                     if (cnt > nc && delta > 1) {
                         o = 8;
                     } else if (delta < kKeyEnd) {
                         const uint64_t js = (ke >> (63 - clz64(delta))) & 7u;
-                        if (js >= 1 && e >= js && e - js + 8 < M && sid[e - js] == s && sid[e - js + 8] == s &&
-                            K[e - js] + 8 * delta == K[e - js + 8] && pos[e - js + 8] - pos[e - js] <= nc)
+                        if (js >= 1 && e >= js && e - js + 8 < M && sS[li - js] == s && sS[li - js + 8] == s &&
+                            sK[li - js] + 8 * delta == sK[li - js + 8] && sP[li - js + 8] - sP[li - js] <= nc)
                             o = 0;
                     }
                     if (o != 1) {
@@ -912,44 +933,70 @@ __global__ __launch_bounds__(kRBlock) void batch_round_kernel(const BatchSet* __
             }
         }
         if (changed) any_change = 1;
-        __syncthreads();
+        __syncthreads();  // every thread has read the staged entries it needs
         const uint64_t tp = tile_prefix;
+        const uint32_t out_total = static_cast<uint32_t>(block_total);  // new entries of this tile
+        const bool staged = out_total <= static_cast<uint32_t>(kRSpan);  // block-uniform
 
-        uint64_t o_prime = tp + (excl & 0xffffffffull);
+        uint32_t lo = static_cast<uint32_t>(excl);  // this thread's first new entry, relative to tp
         uint32_t s_at = split_base + static_cast<uint32_t>(excl >> 32);
 #pragma unroll
         for (int j = 0; j < kRItems; ++j) {
             const uint64_t e = first + j;
             if (e < M) {
-                const uint64_t ke = K[e];
-                const uint32_t s = sid[e];
+                const uint64_t ke = kk[j];
+                const uint32_t s = ss[j];
+                const uint64_t o_prime = tp + lo;
                 if (op[j] == 1) {
-                    if (o_prime <= capacity) {
+                    if (staged) {
+                        sK[lo] = ke;
+                        sP[lo] = pp[j];
+                        sS[lo] = s;
+                    } else if (o_prime <= capacity) {
                         K_out[o_prime] = ke;
-                        pos_out[o_prime] = pos[e];
+                        pos_out[o_prime] = pp[j];
                         sid_out[o_prime] = s;
-                        if (ke == 0) starts_out[s] = static_cast<uint32_t>(o_prime);
                     }
+                    if (ke == 0 && o_prime <= capacity) starts_out[s] = static_cast<uint32_t>(o_prime);
                     if (e + 1 == M) {  // the last closing key: size of the next array
                         st->nl[round + 1] = o_prime + 1;
                         starts_out[n_sets] = static_cast<uint32_t>(o_prime + 1);
                     }
                 } else if (op[j] == 8) {
-                    if (o_prime + 7 <= capacity) {
-                        const uint64_t child = (K[e + 1] - ke) >> 3;
+                    const uint64_t ch = (kk[j + 1] - ke) >> 3;
+                    if (staged) {
 #pragma unroll
                         for (int c = 0; c < 8; ++c) {
-                            K_out[o_prime + c] = ke + c * child;
+                            sK[lo + c] = ke + c * ch;
+                            sS[lo + c] = s;
+                        }
+                        sP[lo] = pp[j];  // the other 7 come from the split search
+                    } else if (o_prime + 7 <= capacity) {
+#pragma unroll
+                        for (int c = 0; c < 8; ++c) {
+                            K_out[o_prime + c] = ke + c * ch;
                             sid_out[o_prime + c] = s;
                         }
-                        pos_out[o_prime] = pos[e];
+                        pos_out[o_prime] = pp[j];
+                    }
+                    if (o_prime + 7 <= capacity) {
                         if (ke == 0) starts_out[s] = static_cast<uint32_t>(o_prime);
                         if (s_at < split_capacity) splits[s_at] = e | (o_prime << 32);
                     }
                     ++s_at;
                 }
             }
-            o_prime += op[j];
+            lo += op[j];
+        }
+        if (staged) {  // the writes above went to LDS (free after g1): store them coalesced
+            __syncthreads();
+            for (uint32_t j = tid; j < out_total; j += kRBlock) {
+                if (tp + j <= capacity) {
+                    K_out[tp + j] = sK[j];
+                    pos_out[tp + j] = sP[j];  // split children 1..7 are overwritten by the split search
+                    sid_out[tp + j] = sS[j];
+                }
+            }
         }
         __syncthreads();
     }
