@@ -32,7 +32,6 @@ constexpr int kRItems = 8;
 constexpr int kRTile = kRBlock * kRItems;
 constexpr uint32_t kMaxGrid = 2048;
 constexpr uint32_t kSearchBlock = 256;
-constexpr uint32_t kWaveSearchMin = 1024;  // ranges at least this long use a whole wave
 
 
 // ---- f as a standalone operation -----------------------------------------
@@ -436,11 +435,12 @@ __global__ __launch_bounds__(kRBlock) void round_kernel(uint32_t n, uint32_t n_c
 // ---- f for the next round: positions of the inner child boundaries ----------
 
 // Child boundaries of the listed splits: positions in P of the 7 inner
-// boundaries of each split leaf. A wave takes 8 splits, 8 lanes each. A range
-// of at most kSmallRange keys is read by its 8 lanes at once (16 keys each,
-// independent loads) and every boundary is the count of the range's keys below
-// it; longer ranges are searched by lanes 1..7 (binary search), or by the
-// whole wave when at least kWaveSearchMin long.
+// boundaries of each split leaf. With at most one search per wave (early
+// rounds: few splits, long ranges) every search gets a whole wave (63 probes
+// per step). Otherwise a wave takes 8 splits, 8 lanes each: a range of at most
+// kSmallRange keys is read by its 8 lanes at once (16 keys each, independent
+// loads) and every boundary is the count of the range's keys below it; a
+// longer range is searched by lanes 1..7, one binary search each, in parallel.
 constexpr uint32_t kSmallRange = 128;
 
 __global__ __launch_bounds__(kSearchBlock) void split_search_kernel(const uint64_t* __restrict__ P, uint32_t n,
@@ -457,6 +457,23 @@ __global__ __launch_bounds__(kSearchBlock) void split_search_kernel(const uint64
     const uint32_t t = lane & 7u;  // child boundary t (1..7) of the group's split
     const uint32_t waves = gridDim.x * (kSearchBlock / kWave);
     const uint32_t wave = blockIdx.x * (kSearchBlock / kWave) + threadIdx.x / kWave;
+    if (static_cast<uint64_t>(listed) * 7u <= waves) {  // one search per wave (wave-uniform branch)
+        for (uint32_t w = wave; w < listed * 7u; w += waves) {
+            const uint64_t e = splits[w / 7u];
+            const uint32_t c = w % 7u + 1u;
+            const uint64_t i = e & 0xffffffffull;
+            const uint64_t ki = K[i];
+            const uint64_t key = ki + c * ((K[i + 1] - ki) >> 3);
+            const uint32_t hi = min(pos[i + 1], n);
+            const uint32_t lo = min(pos[i], hi);
+            const uint32_t dst = static_cast<uint32_t>(e >> 32) + c;
+            const uint32_t at = wave_lower_bound(P, lo, hi, key);
+            if (lane == 0 && dst <= capacity) pos_out[dst] = at;
+        }
+        // the children's counts are not gathered here: let the next round run
+        if (listed != 0 && wave == 0 && lane == 0) atomicOr(&st->over[round], 1u);
+        return;
+    }
     for (uint32_t base = wave * 8u; base < listed; base += waves * 8u) {
         const uint32_t sidx = base + (lane >> 3);
         bool valid = sidx < listed;
@@ -502,23 +519,9 @@ __global__ __launch_bounds__(kSearchBlock) void split_search_kernel(const uint64
             b = lo + below;
             pos_out[dst0 + t] = b;
         }
-        const bool mid = valid && !small && t != 0 && hi - lo < kWaveSearchMin;
-        if (mid) {
+        if (valid && !small && t != 0) {
             b = static_cast<uint32_t>(lower_bound_u64(P, lo, hi, key));
             pos_out[dst0 + t] = b;
-        }
-        uint64_t todo = __ballot(valid && t != 0 && hi - lo >= kWaveSearchMin);
-        while (todo) {
-            const int l = __ffsll(static_cast<long long>(todo)) - 1;
-            todo &= todo - 1;
-            const uint32_t l_lo = __shfl(lo, l, kWave);
-            const uint32_t l_hi = __shfl(hi, l, kWave);
-            const uint64_t l_key = __shfl(key, l, kWave);
-            const uint32_t at = wave_lower_bound(P, l_lo, l_hi, l_key);
-            if (static_cast<int>(lane) == l) {
-                pos_out[dst0 + t] = at;
-                b = at;
-            }
         }
         // does a new child hold more than n_crit (and could split: span above 1)?
         const uint32_t before = __shfl(b, static_cast<int>(lane) - 1, kWave);  // lane 0's value is not used
