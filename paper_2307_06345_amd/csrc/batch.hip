@@ -138,10 +138,10 @@ cstone_status enqueue_build(const cstone_batch& p, const double* x, const double
                        static_cast<size_t>(ns), 0u);
     if (p.n_total) {
         if ((st = sort_seg_prepare(w.stage, p.n_total, nt, ns, p.variant, stream)) != CSTONE_OK) return st;
-        uint32_t stride = 0, mask = 0;
-        uint32_t* hist0 = sort_seg_first_histogram(w.stage, p.n_total, nt, ns, p.variant, &stride, &mask);
-        if ((st = launch_keys_batch(x, y, z, w.tiles, nt, w.sets, w.keys, w.flags, hist0, stride, mask, stream)) !=
-            CSTONE_OK)
+        uint32_t stride = 0, mask = 0, shift = 0;
+        uint32_t* hist0 = sort_seg_first_histogram(w.stage, p.n_total, nt, ns, p.variant, &stride, &mask, &shift);
+        if ((st = launch_keys_batch(x, y, z, w.tiles, nt, w.sets, w.keys, w.flags, hist0, stride, mask, shift,
+                                    stream)) != CSTONE_OK)
             return st;
         if ((st = launch_sort_segmented(w.keys, sorted_keys, perm, p.n_total, w.tiles, nt, w.seg_base, ns,
                                         p.max_set, 63, p.variant, w.stage, w.stage_bytes, stream)) != CSTONE_OK)

@@ -85,7 +85,8 @@ struct BatchResult {
 // digit (key & hist_mask) is counted into hist0 + set * hist_stride.
 cstone_status launch_keys_batch(const double* x, const double* y, const double* z, const uint4* tiles,
                                 uint32_t n_tiles, const BatchSet* sets, uint64_t* keys, uint32_t* set_flags,
-                                uint32_t* hist0, uint32_t hist_stride, uint32_t hist_mask, hipStream_t stream);
+                                uint32_t* hist0, uint32_t hist_stride, uint32_t hist_mask, uint32_t hist_shift,
+                                hipStream_t stream);
 
 // sort.hip — segmented sort: tiles[b] = {first key, count, first tile of its
 // set, set}, never straddling two sets; seg_base[s] = first key of set s.
@@ -102,7 +103,7 @@ cstone_status sort_seg_prepare(void* ws, size_t n_total, size_t n_tiles, uint32_
                                hipStream_t stream);
 // first-digit counters of the segmented sort (set s at + s * *stride)
 uint32_t* sort_seg_first_histogram(void* ws, size_t n_total, size_t n_tiles, uint32_t n_sets, int variant,
-                                   uint32_t* stride, uint32_t* mask);
+                                   uint32_t* stride, uint32_t* mask, uint32_t* shift);
 cstone_status launch_sort_segmented(const uint64_t* keys_in, uint64_t* keys_out, uint32_t* perm_out,
                                     size_t n_total, const uint4* tiles, uint32_t n_tiles, const uint32_t* seg_base,
                                     uint32_t n_sets, size_t max_set, int sig_bits, int variant, void* ws,

@@ -255,7 +255,7 @@ __global__ __launch_bounds__(kKeysBlock) void keys_batch_kernel(const double* __
                                                                 const BatchSet* __restrict__ sets,
                                                                 uint64_t* __restrict__ keys, uint32_t* set_flags,
                                                                 uint32_t* hist0, uint32_t hist_stride,
-                                                                uint32_t hmask) {
+                                                                uint32_t hmask, uint32_t hshift) {
     __shared__ uint16_t two[kStates * 64];
     __shared__ uint16_t first[8];
     __shared__ uint32_t h[512];
@@ -278,7 +278,7 @@ __global__ __launch_bounds__(kKeysBlock) void keys_batch_kernel(const double* __
         const uint64_t k = hilbert ? key_of<CSTONE_HILBERT>(cx, cy, cz, lo0, lo1, lo2, s0, s1, s2, two, first)
                                    : key_of<CSTONE_MORTON>(cx, cy, cz, lo0, lo1, lo2, s0, s1, s2, two, first);
         keys[p] = k;
-        atomicAdd(&h[k & hmask], 1u);
+        atomicAdd(&h[static_cast<uint32_t>(k >> hshift) & hmask], 1u);
     }
     if (__ballot(bad) != 0ull && lane_id() == 0) atomicOr(&set_flags[t.w], CSTONE_FLAG_NONFINITE);
     __syncthreads();
@@ -291,11 +291,12 @@ __global__ __launch_bounds__(kKeysBlock) void keys_batch_kernel(const double* __
 
 cstone_status launch_keys_batch(const double* x, const double* y, const double* z, const uint4* tiles,
                                 uint32_t n_tiles, const BatchSet* sets, uint64_t* keys, uint32_t* set_flags,
-                                uint32_t* hist0, uint32_t hist_stride, uint32_t hist_mask, hipStream_t stream) {
+                                uint32_t* hist0, uint32_t hist_stride, uint32_t hist_mask, uint32_t hist_shift,
+                                hipStream_t stream) {
     if (n_tiles == 0) return CSTONE_OK;
-    if (hist_mask >= 512) return CSTONE_ERR_INVALID_ARG;
+    if (hist_mask >= 512 || hist_shift >= 64) return CSTONE_ERR_INVALID_ARG;
     hipLaunchKernelGGL(keys_batch_kernel, dim3(n_tiles), dim3(kKeysBlock), 0, stream, x, y, z, tiles, sets, keys,
-                       set_flags, hist0, hist_stride, hist_mask);
+                       set_flags, hist0, hist_stride, hist_mask, hist_shift);
     CS_HIP(hipGetLastError());
     return CSTONE_OK;
 }

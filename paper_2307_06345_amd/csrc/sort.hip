@@ -528,7 +528,8 @@ struct LocalSmem {
     uint32_t cnt[ITEMS * (BLOCK / kWave)];
     uint32_t scan[BLOCK / kWave];
     uint64_t bits[BLOCK / kWave];
-    uint32_t first, last, end, run_end, slot, tile0, nb, maxb;
+    uint32_t setbits[BLOCK * ITEMS / 32];  // segmented sorts: window positions where a key set starts
+    uint32_t first, last, end, run_end, slot, tile0, nb, maxb, next_set;
 };
 
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
@@ -566,6 +567,17 @@ __device__ __forceinline__ uint32_t run_end(const uint64_t* a, uint32_t n, uint3
     const uint64_t pf = static_cast<uint64_t>(from) + ((1ull << f) - 1u);
     const uint64_t hi = f < 32u && pf < n ? pf : n;  // probe f (or the end) is past it
     return wave_lower_bound(a, static_cast<uint32_t>(lo), static_cast<uint32_t>(hi), bound);
+}
+
+// Smallest window position in [j, e) where a key set starts, else e (the
+// same value in every lane).
+__device__ __forceinline__ uint32_t next_set_start(const uint32_t* setbits, uint32_t j, uint32_t e) {
+    while (j < e) {
+        const uint32_t w = setbits[j >> 5] >> (j & 31u);
+        if (w) return min(j + static_cast<uint32_t>(__builtin_ctz(w)), e);
+        j = (j | 31u) + 1u;
+    }
+    return e;
 }
 
 // Sort keys [a, a + m) with their values (1 <= m <= BLOCK * ITEMS) into the
@@ -674,8 +686,10 @@ __device__ __forceinline__ void lds_sort_segment(const uint64_t* kin, const uint
 // window's end at the end of the keys) into kout / vout; the window's keys and
 // values are in LDS. If no bucket is longer than kCountMax, every key is ranked
 // inside its bucket by counting the keys that precede it (smaller, or equal and
-// earlier); otherwise the segment goes through the LDS passes.
-template <int BITS, int BLOCK, int ITEMS>
+// earlier); otherwise the segment goes through the LDS passes. With SEG, a
+// key set's first key also starts a bucket, and the LDS passes take each
+// set's part of the segment on its own.
+template <int BITS, int BLOCK, int ITEMS, bool SEG>
 __device__ __forceinline__ void lds_sort_window(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
                                                 uint32_t* vout,
                                                 uint32_t n, uint32_t lo, uint32_t f, uint32_t e, uint32_t pshift,
@@ -692,7 +706,8 @@ __device__ __forceinline__ void lds_sort_window(const uint64_t* kin, const uint3
         const uint32_t j = static_cast<uint32_t>(i) * BLOCK + tid;
         const bool in = j >= f && j < e;
         k[i] = in ? sm.keys[j] : 0ull;
-        const bool st = in && (j == f || (sm.keys[j - 1] >> pshift) != (k[i] >> pshift));
+        bool st = in && (j == f || (sm.keys[j - 1] >> pshift) != (k[i] >> pshift));
+        if constexpr (SEG) st = st || (in && ((sm.setbits[j >> 5] >> (j & 31u)) & 1u));
         smask[i] = __ballot(st);
         start_bits |= static_cast<uint32_t>(st) << i;
         if (lane == 0) sm.cnt[i * W + wave] = static_cast<uint32_t>(__popcll(smask[i]));
@@ -727,7 +742,21 @@ __device__ __forceinline__ void lds_sort_window(const uint64_t* kin, const uint3
     if (lane == 0) atomicMax(&sm.maxb, longest);
     __syncthreads();
     if (sm.maxb > kCountMax) {
-        lds_sort_segment<BITS, BLOCK, ITEMS>(kin, vin, kout, vout, lo + f, e - f, true, lo, sm);
+        if constexpr (SEG) {
+            // one set's keys at a time; the first part is read from the window,
+            // the rest from memory (the LDS passes overwrite the window, and
+            // the parts this block wrote lie before the part being read)
+            uint32_t a = f;
+            bool in_lds = true;
+            while (a < e) {
+                const uint32_t b = next_set_start(sm.setbits, a + 1u, e);
+                lds_sort_segment<BITS, BLOCK, ITEMS>(kin, vin, kout, vout, lo + a, b - a, in_lds, lo, sm);
+                in_lds = false;
+                a = b;
+            }
+        } else {
+            lds_sort_segment<BITS, BLOCK, ITEMS>(kin, vin, kout, vout, lo + f, e - f, true, lo, sm);
+        }
         return;
     }
     // rank every key in its bucket; only keys whose place changes are written
@@ -808,9 +837,15 @@ __device__ __forceinline__ void list_large(const LargeList& L, uint32_t start, u
 //
 // level6 (NULL, or kLevel6Cells words set to kCellEmpty): the first position
 // of every non-empty level-6 node (key >> 45), found with the bucket starts.
-template <int BITS, int BLOCK, int ITEMS>
+//
+// SEG: the keys are n_sets key sets back to back, set s starting at
+// seg_base[s] (non-decreasing), each ordered by prefix on its own; every set's
+// first key starts a bucket and no bucket runs past its set. chunk_set[b] is
+// the first set starting at or after block b's first key.
+template <int BITS, int BLOCK, int ITEMS, bool SEG>
 __global__ __launch_bounds__(BLOCK, kLocalBlocksPerCU * BLOCK / (4 * kWave)) void local_sort_kernel(
-    uint64_t* keys, uint32_t* vals, uint32_t n, uint32_t pshift, LargeList large, uint32_t* err, uint32_t* level6) {
+    uint64_t* keys, uint32_t* vals, uint32_t n, uint32_t pshift, LargeList large, uint32_t* err, uint32_t* level6,
+    const uint32_t* seg_base, uint32_t n_sets, const uint32_t* chunk_set) {
     const uint64_t* kin = keys;
     const uint32_t* vin = vals;
     uint64_t* kout = keys;
@@ -827,6 +862,10 @@ __global__ __launch_bounds__(BLOCK, kLocalBlocksPerCU * BLOCK / (4 * kWave)) voi
         sm.first = 0xffffffffu;
         sm.last = 0u;
         sm.end = 0xffffffffu;
+        sm.next_set = n_sets;
+    }
+    if constexpr (SEG) {
+        for (uint32_t i = tid; i < CAP / 32; i += BLOCK) sm.setbits[i] = 0;
     }
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
@@ -837,6 +876,20 @@ __global__ __launch_bounds__(BLOCK, kLocalBlocksPerCU * BLOCK / (4 * kWave)) voi
         }
     }
     const uint64_t before = lo ? kin[lo - 1] >> pshift : ~0ull;  // the same word in every lane
+    if constexpr (SEG) {
+        // mark the set starts in the window; the first set starting at or
+        // after the window's end gives the end of a last bucket that runs past it
+        __syncthreads();
+        const uint32_t s0 = chunk_set[blockIdx.x];
+        for (uint32_t q = s0 + tid; q < n_sets; q += BLOCK) {
+            const uint32_t at = seg_base[q];
+            if (at >= wend) {
+                atomicMin(&sm.next_set, q);
+                break;
+            }
+            if (at >= lo) atomicOr(&sm.setbits[(at - lo) >> 5], 1u << ((at - lo) & 31u));
+        }
+    }
     __syncthreads();
     // bucket starts: the first and last in the chunk, the first after it
     uint32_t first = 0xffffffffu, last = 0u, after = 0xffffffffu;
@@ -846,7 +899,9 @@ __global__ __launch_bounds__(BLOCK, kLocalBlocksPerCU * BLOCK / (4 * kWave)) voi
         if (j < wn) {
             const uint64_t pj = sm.keys[j] >> pshift;
             const uint64_t pp = j ? sm.keys[j - 1] >> pshift : before;
-            if (pj != pp) {
+            bool st = pj != pp;
+            if constexpr (SEG) st = st || ((sm.setbits[j >> 5] >> (j & 31u)) & 1u);
+            if (st) {
                 if (j < own) {
                     first = min(first, j);
                     last = max(last, j);
@@ -873,17 +928,21 @@ __global__ __launch_bounds__(BLOCK, kLocalBlocksPerCU * BLOCK / (4 * kWave)) voi
     const uint32_t f = sm.first, l = sm.last;
     if (f == 0xffffffffu) return;  // no bucket starts here
     const uint64_t last_prefix = sm.keys[l] >> pshift;
+    // where the last bucket's keys end at the latest: the keys' end, or the
+    // next set's start
+    uint32_t bound_end = n;
+    if constexpr (SEG) bound_end = sm.next_set < n_sets ? seg_base[sm.next_set] : n;
     uint32_t e = sm.end;
-    if (e == 0xffffffffu && wend == n) e = wn;  // the last bucket ends with the keys
+    if (e == 0xffffffffu && wend == bound_end) e = wn;  // the last bucket ends with the window
     if (e != 0xffffffffu) {
-        lds_sort_window<BITS, BLOCK, ITEMS>(kin, vin, kout, vout, n, lo, f, e, pshift, sm);
+        lds_sort_window<BITS, BLOCK, ITEMS, SEG>(kin, vin, kout, vout, n, lo, f, e, pshift, sm);
         return;
     }
     // the last bucket runs past the window: the buckets before it from LDS, then it alone
-    if (l > f) lds_sort_window<BITS, BLOCK, ITEMS>(kin, vin, kout, vout, n, lo, f, l, pshift, sm);
+    if (l > f) lds_sort_window<BITS, BLOCK, ITEMS, SEG>(kin, vin, kout, vout, n, lo, f, l, pshift, sm);
     // (its own slot: with l == f no barrier separates this from the reads of sm.end above)
     if (tid < kWave) {
-        const uint32_t ee = run_end(kin, n, wend, (last_prefix + 1u) << pshift);
+        const uint32_t ee = run_end(kin, bound_end, wend, (last_prefix + 1u) << pshift);
         if (tid == 0) sm.run_end = ee;
     }
     __syncthreads();
@@ -1220,8 +1279,9 @@ cstone_status launch_split(const uint64_t* keys_in, uint64_t* keys_out, uint32_t
     L.max_tiles = static_cast<uint32_t>((n + tile - 1) / tile + s.max_buckets);
     L.wide = wide ? 1u : 0u;
     const uint32_t chunks = static_cast<uint32_t>((n + kLocalChunk - 1) / kLocalChunk);
-    hipLaunchKernelGGL((local_sort_kernel<kSplitBits, kLocalBlock, kLocalItems>), dim3(chunks), dim3(kLocalBlock), 0,
-                       stream, keys_out, perm_out, static_cast<uint32_t>(n), kSplitShift, L, err, level6);
+    hipLaunchKernelGGL((local_sort_kernel<kSplitBits, kLocalBlock, kLocalItems, false>), dim3(chunks),
+                       dim3(kLocalBlock), 0, stream, keys_out, perm_out, static_cast<uint32_t>(n), kSplitShift, L, err,
+                       level6, static_cast<const uint32_t*>(nullptr), 0u, static_cast<const uint32_t*>(nullptr));
     if (pass_events) CS_HIP(hipEventRecord(pass_events[3], stream));
     if (s.max_buckets > 0) {  // some bucket may be longer than one block sorts
         hipLaunchKernelGGL(large_hist_kernel, dim3(std::min(L.max_tiles, kListGrid)), dim3(512), 0, stream, keys_out,
@@ -1335,29 +1395,71 @@ namespace {
 struct SegWs {
     uint64_t* keys_alt;
     uint32_t* vals_alt;
-    uint32_t* ghist;  // [set][pass][digit]
+    uint32_t* ghist;  // [set][pass][digit], then the bucket-list counters
     uint32_t stride;  // words per set
     uint32_t* err;
     void* lb;
     size_t lb_bytes;
     size_t rows;
+    // split sorts (9-bit variants): the bucket list and each chunk's first set
+    bool split;
+    uint32_t* large_count;
+    uint4* large_tiles;
+    uint32_t* large_start;
+    uint32_t* large_hist;
+    uint32_t* chunk_set;
+    size_t max_buckets, max_list_tiles, chunks;
     size_t bytes;
 };
+
+bool seg_split(int variant) { return split_enabled() && kVariants[variant].bits == kSplitBits; }
 
 SegWs carve_seg(void* ws, size_t n_total, size_t n_tiles, uint32_t n_sets, int variant) {
     const Variant& var = kVariants[variant];
     Carve c(ws);
     SegWs s{};
+    s.split = seg_split(variant);
     s.keys_alt = c.take<uint64_t>(n_total);
     s.vals_alt = c.take<uint32_t>(n_total);
     s.stride = static_cast<uint32_t>(((64 + var.bits - 1) / var.bits) << var.bits);
-    s.ghist = c.take<uint32_t>(static_cast<size_t>(n_sets) * s.stride);
+    s.ghist = c.take<uint32_t>(static_cast<size_t>(n_sets) * s.stride + 64);
+    s.large_count = s.ghist + static_cast<size_t>(n_sets) * s.stride;  // [0] buckets, [1] tiles, [2..] pass counters
     s.err = c.take<uint32_t>(1);
     s.rows = n_tiles;
+    if (s.split) {
+        // a listed bucket holds more than kLocalCap keys of one set; its tiles
+        // number at most its keys / tile + 1
+        const size_t tile = static_cast<size_t>(var.block) * var.items;
+        s.max_buckets = n_total / (kLocalCap + 1);
+        s.max_list_tiles = (n_total + tile - 1) / tile + s.max_buckets;
+        s.rows = std::max(s.rows, s.max_list_tiles);
+        s.chunks = (n_total + kLocalChunk - 1) / kLocalChunk;
+    }
     s.lb_bytes = s.rows * kMaxRadix * 8;  // 2 x 32-bit sets, or 1 x 64-bit set
     s.lb = c.take<uint8_t>(s.lb_bytes);
+    if (s.split) {
+        s.large_tiles = c.take<uint4>(s.max_list_tiles);
+        s.large_start = c.take<uint32_t>(s.max_buckets + 1);
+        s.large_hist = c.take<uint32_t>((s.max_buckets + 1) * kLowPasses * kMaxRadix);
+        s.chunk_set = c.take<uint32_t>(s.chunks + 1);
+    }
     s.bytes = c.off;
     return s;
+}
+
+// chunk_set[b] = first set whose start is at or after b * kLocalChunk (n_sets if none).
+__global__ __launch_bounds__(256) void chunk_set_kernel(const uint32_t* __restrict__ seg_base, uint32_t n_sets,
+                                                        uint32_t* __restrict__ chunk_set, uint32_t chunks) {
+    const uint32_t b = blockIdx.x * 256u + threadIdx.x;
+    if (b >= chunks) return;
+    const uint64_t at = static_cast<uint64_t>(b) * kLocalChunk;
+    uint32_t lo = 0, hi = n_sets;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (seg_base[mid] < at) lo = mid + 1;
+        else hi = mid;
+    }
+    chunk_set[b] = lo;
 }
 
 }  // namespace
@@ -1369,8 +1471,10 @@ size_t sort_seg_workspace_bytes(size_t n_total, size_t n_tiles, uint32_t n_sets,
 cstone_status sort_seg_prepare(void* ws, size_t n_total, size_t n_tiles, uint32_t n_sets, int variant,
                                hipStream_t stream) {
     SegWs s = carve_seg(ws, n_total, n_tiles, n_sets, variant);
-    const size_t lb_words = s.lb_bytes / 8;
-    const size_t gwords = static_cast<size_t>(n_sets) * s.stride;
+    // the first pass's rows (one per tile); each pass clears the next's, or
+    // 64-bit words carry the pass's epoch
+    const size_t lb_words = std::min(s.lb_bytes / 8, n_tiles * kMaxRadix);
+    const size_t gwords = static_cast<size_t>(n_sets) * s.stride + 64;  // with the bucket-list counters
     const size_t init_grid =
         std::max<size_t>(4, std::min<size_t>((std::max(lb_words, gwords) + 255) / 256, 2048));
     hipLaunchKernelGGL(sort_init_kernel, dim3(init_grid), dim3(256), 0, stream, s.ghist, gwords, s.err,
@@ -1380,12 +1484,97 @@ cstone_status sort_seg_prepare(void* ws, size_t n_total, size_t n_tiles, uint32_
 }
 
 uint32_t* sort_seg_first_histogram(void* ws, size_t n_total, size_t n_tiles, uint32_t n_sets, int variant,
-                                   uint32_t* stride, uint32_t* mask) {
+                                   uint32_t* stride, uint32_t* mask, uint32_t* shift) {
     SegWs s = carve_seg(ws, n_total, n_tiles, n_sets, variant);
     *stride = s.stride;
     *mask = (1u << kVariants[variant].bits) - 1u;
+    *shift = s.split ? kSplitShift : 0u;
     return s.ghist;
 }
+
+namespace {
+
+// Segmented split sort: the top passes per set (keys_in -> keys_out -> alt ->
+// keys_out), the buckets of every set in place, then the low passes over the
+// listed buckets, as in the split sort of one key set.
+cstone_status launch_split_seg(const uint64_t* keys_in, uint64_t* keys_out, uint32_t* perm_out, size_t n_total,
+                               const uint4* tiles, uint32_t n_tiles, const uint32_t* seg_base, uint32_t n_sets,
+                               bool wide, const SegWs& s, const Variant& var, hipStream_t stream) {
+    constexpr int radix = 1 << kSplitBits;
+    uint32_t* lb32[2] = {static_cast<uint32_t*>(s.lb), static_cast<uint32_t*>(s.lb) + s.rows * kMaxRadix};
+    const uint32_t chunks = static_cast<uint32_t>(s.chunks);
+    hipLaunchKernelGGL(chunk_set_kernel, dim3((chunks + 255) / 256), dim3(256), 0, stream, seg_base, n_sets,
+                       s.chunk_set, chunks);
+    SegArgs g{tiles, seg_base, n_tiles, s.stride, nullptr};
+    const uint64_t* src_k = keys_in;
+    const uint32_t* src_v = nullptr;
+    for (int p = 0; p < kSplitTop; ++p) {
+        const bool to_out = ((kSplitTop - 1 - p) % 2) == 0;
+        PassArgs a{};
+        a.keys_in = src_k;
+        a.vals_in = src_v;
+        a.keys_out = to_out ? keys_out : s.keys_alt;
+        a.vals_out = to_out ? perm_out : s.vals_alt;
+        a.n = static_cast<uint32_t>(n_total);
+        a.shift = kSplitShift + p * kSplitBits;
+        a.ghist = s.ghist + p * radix;
+        a.ghist_next = p + 1 < kSplitTop ? s.ghist + (p + 1) * radix : nullptr;
+        a.shift_next = kSplitShift + (p + 1) * kSplitBits;
+        a.wide = wide;
+        a.lb = wide ? s.lb : static_cast<void*>(lb32[p & 1]);
+        a.lb_clear = (!wide && p + 1 < kSplitTop) ? static_cast<void*>(lb32[(p + 1) & 1]) : nullptr;
+        a.epoch = static_cast<uint32_t>(p + 1);
+        a.err = s.err;
+        var.launch_seg(a, g, p == 0, true, stream);
+        src_k = a.keys_out;
+        src_v = a.vals_out;
+    }
+    const uint32_t tile = static_cast<uint32_t>(var.block * var.items);
+    LargeList L{};
+    L.count = s.large_count;
+    L.tiles = s.large_tiles;
+    L.start = s.large_start;
+    L.hist = s.large_hist;
+    L.lb = wide ? s.lb : static_cast<void*>(lb32[0]);
+    L.stride = kLowPasses * kMaxRadix;
+    L.row_words = kMaxRadix;
+    L.tile = tile;
+    L.max_buckets = static_cast<uint32_t>(s.max_buckets);
+    L.max_tiles = static_cast<uint32_t>(s.max_list_tiles);
+    L.wide = wide ? 1u : 0u;
+    hipLaunchKernelGGL((local_sort_kernel<kSplitBits, kLocalBlock, kLocalItems, true>), dim3(chunks),
+                       dim3(kLocalBlock), 0, stream, keys_out, perm_out, static_cast<uint32_t>(n_total), kSplitShift,
+                       L, s.err, static_cast<uint32_t*>(nullptr), seg_base, n_sets,
+                       static_cast<const uint32_t*>(s.chunk_set));
+    if (s.max_buckets > 0) {  // some bucket may be longer than one block sorts
+        hipLaunchKernelGGL(large_hist_kernel, dim3(std::min(L.max_tiles, kListGrid)), dim3(512), 0, stream, keys_out,
+                           static_cast<uint32_t>(n_total), L, static_cast<uint32_t>(radix - 1));
+        SegArgs gl{s.large_tiles, s.large_start, L.max_tiles, L.stride, s.large_count + 1};
+        for (int p = 0; p < kLowPasses; ++p) {
+            const bool from_alt = (p % 2) == 1;
+            PassArgs a{};
+            a.keys_in = from_alt ? s.keys_alt : keys_out;
+            a.vals_in = from_alt ? s.vals_alt : perm_out;
+            a.keys_out = from_alt ? keys_out : s.keys_alt;
+            a.vals_out = from_alt ? perm_out : s.vals_alt;
+            a.n = static_cast<uint32_t>(n_total);
+            a.shift = static_cast<uint32_t>(p * kSplitBits);
+            a.ghist = s.large_hist + p * radix;
+            a.ghist_next = p + 1 < kLowPasses ? s.large_hist + (p + 1) * radix : nullptr;
+            a.shift_next = static_cast<uint32_t>((p + 1) * kSplitBits);
+            a.wide = wide;
+            a.lb = wide ? s.lb : static_cast<void*>(lb32[p & 1]);
+            a.lb_clear = (!wide && p + 1 < kLowPasses) ? static_cast<void*>(lb32[(p + 1) & 1]) : nullptr;
+            a.epoch = static_cast<uint32_t>(kSplitTop + 1 + p);
+            a.err = s.err;
+            var.launch_list(a, gl, s.large_count + 2 + p, stream);  // a tile counter per pass, cleared at set-up
+        }
+    }
+    CS_HIP(hipGetLastError());
+    return CSTONE_OK;
+}
+
+}  // namespace
 
 cstone_status launch_sort_segmented(const uint64_t* keys_in, uint64_t* keys_out, uint32_t* perm_out,
                                     size_t n_total, const uint4* tiles, uint32_t n_tiles, const uint32_t* seg_base,
@@ -1401,6 +1590,10 @@ cstone_status launch_sort_segmented(const uint64_t* keys_in, uint64_t* keys_out,
     const int passes = (sig_bits + var.bits - 1) / var.bits;
     if (passes < 1 || static_cast<uint32_t>(passes * radix) > s.stride) return CSTONE_ERR_INVALID_ARG;
     const bool wide = max_set >= (1ull << 30);
+    if (s.split && sig_bits == 63)
+        return launch_split_seg(keys_in, keys_out, perm_out, n_total, tiles, n_tiles, seg_base, n_sets, wide, s, var,
+                                stream);
+    if (s.split) return CSTONE_ERR_INVALID_ARG;  // its first histogram was taken on the top digit
     uint32_t* lb32[2] = {static_cast<uint32_t*>(s.lb), static_cast<uint32_t*>(s.lb) + s.rows * kMaxRadix};
     SegArgs g{tiles, seg_base, n_tiles, s.stride, nullptr};
     const uint64_t* src_k = keys_in;

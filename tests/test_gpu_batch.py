@@ -150,6 +150,49 @@ def test_batch_every_sort_shape_bit_exact():
         check_against_oracle(b, sets)
 
 
+def point_set(n, points, seed, curve, n_crit):
+    """n particles on `points` distinct points, in a seeded shuffled order."""
+    s = duplicate_set(n, points, seed, curve, n_crit)
+    order = np.random.default_rng(seed).permutation(n)
+    return wl.ParticleSet(s.x[order].copy(), s.y[order].copy(), s.z[order].copy(), s.box, curve, n_crit, "points")
+
+
+def boundary_sets():
+    """Sets placed so that set starts fall where the sorted keys alone would
+    not start a bucket: equal sets back to back (equal key prefixes across the
+    boundary), a set ending exactly at the end of a 2048-key window, buckets
+    longer than 2048 keys in neighbouring sets, a bucket running past a
+    window up to its set's end, and many short sets in one window with
+    buckets over 160 keys."""
+    H, M = wl.HILBERT, wl.MORTON
+    u = wl.make_set("uniform", 700, 41, 1, H, 16)
+    sets = [point_set(2048, 1, 42, H, 8),        # one bucket of exactly 2048 keys, set end at 2048
+            point_set(2049, 1, 42, H, 8),        # the same point: a listed bucket, equal keys across the start
+            point_set(2049, 1, 42, H, 8),
+            u, u, u,                             # equal sets: equal prefixes at every boundary
+            point_set(4000, 3, 43, M, 4),        # buckets of 1333 keys, the last runs past its window
+            point_set(300, 1, 43, M, 4),         # the same first point as the set before it
+            ]
+    sets += [point_set(250, 1, 44, H, 8) for _ in range(12)]  # 12 sets of one 250-key bucket each
+    sets += [wl.make_set("plummer", 9000, 41, 2, H, 8), point_set(1793, 2, 45, H, 8), point_set(5, 1, 45, H, 8)]
+    return sets
+
+
+def test_batch_set_starts_split_buckets():
+    sets = boundary_sets()
+    say("batch set boundaries", [s.n for s in sets])
+    b = cs.Batch(specs(sets))
+    x, y, z = coords(sets)
+    for v in range(len(cs.sort_variants())):
+        say("batch set boundaries, sort shape", v, cs.sort_variants()[v])
+        b.set_variant(v)
+        for k in ("sorted_keys", "perm", "leaves", "node_keys"):
+            getattr(b, k).fill_(-1)
+        b.build(x, y, z)
+        torch.cuda.synchronize()
+        check_against_oracle(b, sets)
+
+
 def test_batch_autotune_keeps_results():
     sets = mixed_sets()
     b = cs.Batch(specs(sets))
