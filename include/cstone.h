@@ -241,7 +241,10 @@ CSTONE_API cstone_status cstone_sort_autotune(const uint64_t* keys_in, size_t n,
  * all sets: per-tile set tables for the keys and the segmented sort, the sets'
  * cornerstone arrays kept back to back through the rebalance rounds with one
  * scan per round and per-set convergence flags, one linking pass). The
- * sequence can be captured once into a hipGraph and replayed.
+ * sequence can be captured once into a hipGraph and replayed. With a 9-bit
+ * sort shape the segmented sort is the split sort of cstone_sort applied per
+ * set (every set's first key starts a bucket); 8-bit shapes take LSD passes.
+ * Both are stable, so the results do not depend on the shape.
  *
  * Layout. Particles of set s occupy [particle_offsets[s], particle_offsets[s+1])
  * of x, y, z, sorted_keys and perm (perm values count from the set's first

@@ -228,6 +228,22 @@ __device__ __forceinline__ uint32_t take_tile(uint32_t* counter, uint32_t* lds_s
     return t;
 }
 
+// Grouped dynamic tile index: blocks of group g (block index mod the number
+// of groups) take tiles g, g + groups, g + 2 groups, ... in order from their
+// group's counter (counter + g * stride), so the same-address atomics of one
+// counter are spread over the groups. A tile's predecessor belongs to a group
+// that has a resident block and takes its tiles in order (look-back progress).
+__device__ __forceinline__ uint32_t take_group_tile(uint32_t* counter, uint32_t stride, uint32_t groups,
+                                                    uint32_t* lds_slot) {
+    const uint32_t g_count = min(groups, gridDim.x);
+    const uint32_t g = blockIdx.x % g_count;
+    if (threadIdx.x == 0) *lds_slot = atomicAdd(counter + g * stride, 1u) * g_count + g;
+    __syncthreads();
+    uint32_t t = *lds_slot;
+    __syncthreads();
+    return t;
+}
+
 __device__ __forceinline__ int clz64(uint64_t v) { return v ? __clzll(static_cast<long long>(v)) : 64; }
 
 // First index in [lo, hi) whose key is >= k (hi if none).

@@ -115,6 +115,10 @@ cstone_status launch_node_counts(const uint64_t* sorted_keys, size_t n, const ui
 size_t rebalance_workspace_bytes(size_t n, uint32_t n_crit, size_t leaf_capacity);
 
 constexpr int kMaxRounds = 64;
+// Tiles of a round are taken from kTileGroups counters (group g = block mod
+// groups takes tiles g, g + groups, ...), each in a 128-byte line of its own.
+constexpr int kTileGroups = 8;
+constexpr int kCounterWords = 32;
 
 // Device-side loop state.
 struct LoopState {
@@ -122,7 +126,6 @@ struct LoopState {
     uint32_t changed[kMaxRounds];   // some O_i != 1 in round r
     uint32_t merged[kMaxRounds];    // some O_i == 0 in round r
     uint32_t over[kMaxRounds];      // a child of a leaf split in round r holds more than n_crit (and can split)
-    uint32_t counters[kMaxRounds];  // dynamic tile counter of round r
     uint32_t nsplit[kMaxRounds];    // split leaves listed in round r
     uint32_t err;
     uint32_t input_flags;  // copy of the caller's key-stage flag word
@@ -132,6 +135,8 @@ struct LoopState {
     uint32_t start_level;  // from the root: rounds skipped by starting at the uniform grid of this level
     uint32_t start_fine;   // the start-level search went finer than level 3
     uint32_t mins[kL + 1]; // least node count of every level (start-level search)
+    // last, and not copied to the host: the tile counters of every round
+    alignas(128) uint32_t counters[kMaxRounds][kTileGroups * kCounterWords];
 };
 
 // The rebalance loop, driven from the device: rounds are enqueued ahead of

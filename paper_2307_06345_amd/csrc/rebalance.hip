@@ -18,6 +18,7 @@
 // finalize kernel leaves the last complete round's array in place with its
 // counts and its leaf count in device memory.
 #include <algorithm>
+#include <cstddef>
 #include <cstring>
 
 #include "common.hpp"
@@ -69,7 +70,7 @@ __global__ __launch_bounds__(256) void loop_init_kernel(LoopState* st, uint64_t 
         st->changed[t] = 0;
         st->merged[t] = 0;
         st->over[t] = 0;
-        st->counters[t] = 0;
+        for (int g = 0; g < kTileGroups; ++g) st->counters[t][g * kCounterWords] = 0;
         st->nsplit[t] = 0;
     }
     if (t <= kMaxRounds) st->nl[t] = t == 0 ? nl0 : 0;
@@ -296,7 +297,7 @@ __global__ __launch_bounds__(kRBlock) void round_kernel(uint32_t n, uint32_t n_c
     }
 
     for (;;) {
-        const uint32_t tile = take_tile(&st->counters[round], &slot);
+        const uint32_t tile = take_group_tile(st->counters[round], kCounterWords, kTileGroups, &slot);
         if (tile >= tiles) break;
         const int64_t base = static_cast<int64_t>(tile) * kRTile;
         for (int j = tid; j < kRSpan; j += kRBlock) {  // K and positions of entries base-8 .. base+2055
@@ -474,6 +475,7 @@ __global__ __launch_bounds__(kSearchBlock) void split_search_kernel(const uint64
         if (listed != 0 && wave == 0 && lane == 0) atomicOr(&st->over[round], 1u);
         return;
     }
+    bool wave_over = false;  // one flag write per wave, not per group of splits
     for (uint32_t base = wave * 8u; base < listed; base += waves * 8u) {
         const uint32_t sidx = base + (lane >> 3);
         bool valid = sidx < listed;
@@ -526,8 +528,9 @@ __global__ __launch_bounds__(kSearchBlock) void split_search_kernel(const uint64
         // does a new child hold more than n_crit (and could split: span above 1)?
         const uint32_t before = __shfl(b, static_cast<int>(lane) - 1, kWave);  // lane 0's value is not used
         const bool over = valid && t != 0 && step > 1 && (b - before > n_crit || (t == 7 && hi - b > n_crit));
-        if (__ballot(over) != 0ull && lane == 0) atomicOr(&st->over[round], 1u);
+        wave_over = wave_over || __ballot(over) != 0ull;
     }
+    if (wave_over && lane == 0) atomicOr(&st->over[round], 1u);
 }
 
 // ---- pick the array of the last complete round --------------------------------
@@ -734,7 +737,7 @@ const uint64_t* RebalanceLoop::device_leaf_count() const { return &st_->final_nl
 
 cstone_status RebalanceLoop::wait(bool* finished) {
     LoopState host;
-    CS_HIP(hipMemcpyAsync(&host, st_, sizeof(LoopState), hipMemcpyDeviceToHost, stream_));
+    CS_HIP(hipMemcpyAsync(&host, st_, offsetof(LoopState, counters), hipMemcpyDeviceToHost, stream_));
     CS_HIP(hipStreamSynchronize(stream_));
     input_flags = host.input_flags;
     rounds = host.final_last + host.start_level;
@@ -814,7 +817,7 @@ __global__ __launch_bounds__(256) void batch_init_kernel(LoopState* st, const Ba
         st->changed[t] = 0;
         st->merged[t] = 0;
         st->over[t] = 0;
-        st->counters[t] = 0;
+        for (int g = 0; g < kTileGroups; ++g) st->counters[t][g * kCounterWords] = 0;
         st->nsplit[t] = 0;
     }
     if (t <= kMaxRounds) st->nl[t] = t == 0 ? 2ull * n_sets : 0ull;
@@ -845,6 +848,12 @@ __global__ __launch_bounds__(kRBlock, 4) void batch_round_kernel(const BatchSet*
     __shared__ uint64_t sK[kRSpan];  // entries base-8 .., then the tile's new entries
     __shared__ uint32_t sP[kRSpan];
     __shared__ uint32_t sS[kRSpan];
+    // sets that changed in this tile, by set id mod kSetFlags: a set holds at
+    // least two entries, so a tile spans at most kRTile / 2 + 1 consecutive
+    // sets, and they take distinct slots
+    constexpr uint32_t kSetFlags = kRTile;
+    static_assert((kSetFlags & (kSetFlags - 1)) == 0 && kSetFlags > kRTile / 2 + 1, "distinct slots");
+    __shared__ uint8_t sflag[kSetFlags];
 
     if (round > 0 && st->changed[round - 1] == 0) return;  // every set converged earlier
     const uint64_t M = st->nl[round];
@@ -855,7 +864,7 @@ __global__ __launch_bounds__(kRBlock, 4) void batch_round_kernel(const BatchSet*
     if (tid == 0) any_change = 0;
 
     for (;;) {
-        const uint32_t tile = take_tile(&st->counters[round], &slot);
+        const uint32_t tile = take_group_tile(st->counters[round], kCounterWords, kTileGroups, &slot);
         if (tile >= tiles) break;
         const int64_t base = static_cast<int64_t>(tile) * kRTile;
         for (int j = tid; j < kRSpan; j += kRBlock) {  // coalesced: entries base-8 .. base+2055 that exist
@@ -866,6 +875,7 @@ __global__ __launch_bounds__(kRBlock, 4) void batch_round_kernel(const BatchSet*
                 sS[j] = sid[g];
             }
         }
+        for (uint32_t j = tid; j < kSetFlags; j += kRBlock) sflag[j] = 0;
         __syncthreads();
         const uint32_t lfirst = tid * kRItems;
         const uint64_t first = static_cast<uint64_t>(base) + lfirst;
@@ -875,7 +885,6 @@ __global__ __launch_bounds__(kRBlock, 4) void batch_round_kernel(const BatchSet*
         uint32_t pp[kRItems], ss[kRItems];
         uint32_t osum = 0, nsplit = 0;
         bool changed = false;
-        uint32_t flagged = 0xffffffffu;  // last set whose change this thread reported
 #pragma unroll
         for (int j = 0; j <= kRItems; ++j) kk[j] = sK[kRHalo + lfirst + j];
 #pragma unroll
@@ -903,10 +912,7 @@ __global__ __launch_bounds__(kRBlock, 4) void batch_round_kernel(const BatchSet*
                     }
                     if (o != 1) {
                         changed = true;
-                        if (s != flagged) {
-                            atomicOr(&changed_set[s], 1u);
-                            flagged = s;
-                        }
+                        sflag[s & (kSetFlags - 1)] = 1;
                     }
                 }
             }
@@ -936,7 +942,10 @@ __global__ __launch_bounds__(kRBlock, 4) void batch_round_kernel(const BatchSet*
             }
         }
         if (changed) any_change = 1;
+        const uint32_t s_lo = sS[kRHalo];  // set of the tile's first entry (sS is rewritten after the barrier)
         __syncthreads();  // every thread has read the staged entries it needs
+        for (uint32_t j = tid; j < kSetFlags; j += kRBlock)  // one flag per set and tile
+            if (sflag[j]) atomicOr(&changed_set[s_lo + ((j - s_lo) & (kSetFlags - 1))], 1u);
         const uint64_t tp = tile_prefix;
         const uint32_t out_total = static_cast<uint32_t>(block_total);  // new entries of this tile
         const bool staged = out_total <= static_cast<uint32_t>(kRSpan);  // block-uniform

@@ -864,8 +864,13 @@ __global__ __launch_bounds__(BLOCK, kLocalBlocksPerCU * BLOCK / (4 * kWave)) voi
         sm.end = 0xffffffffu;
         sm.next_set = n_sets;
     }
+    // the chunk's first set and this thread's first set start, read before
+    // the window so that their round trips overlap its load
+    uint32_t s0 = 0, at0 = 0;
     if constexpr (SEG) {
         for (uint32_t i = tid; i < CAP / 32; i += BLOCK) sm.setbits[i] = 0;
+        s0 = chunk_set[blockIdx.x];
+        if (s0 + tid < n_sets) at0 = seg_base[s0 + tid];
     }
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
@@ -880,9 +885,8 @@ __global__ __launch_bounds__(BLOCK, kLocalBlocksPerCU * BLOCK / (4 * kWave)) voi
         // mark the set starts in the window; the first set starting at or
         // after the window's end gives the end of a last bucket that runs past it
         __syncthreads();
-        const uint32_t s0 = chunk_set[blockIdx.x];
         for (uint32_t q = s0 + tid; q < n_sets; q += BLOCK) {
-            const uint32_t at = seg_base[q];
+            const uint32_t at = q == s0 + tid ? at0 : seg_base[q];
             if (at >= wend) {
                 atomicMin(&sm.next_set, q);
                 break;
