@@ -300,7 +300,7 @@ __global__ __launch_bounds__(kRBlock) void round_kernel(uint32_t n, uint32_t n_c
         const uint32_t tile = take_group_tile(st->counters[round], kCounterWords, kTileGroups, &slot);
         if (tile >= tiles) break;
         const int64_t base = static_cast<int64_t>(tile) * kRTile;
-        for (int j = tid; j < kRSpan; j += kRBlock) {  // K and positions of entries base-8 .. base+2055
+        for (int j = tid; j < kRSpan; j += kRBlock) {  // K and positions of entries base-8 .. base+kRTile+7
             const int64_t g = base - kRHalo + j;
             if (g >= 0 && g <= static_cast<int64_t>(nl)) {
                 sK[j] = K[g];
@@ -796,6 +796,12 @@ cstone_status run_rebalance(const uint64_t* P, size_t n, uint32_t n_crit, uint64
 
 namespace {
 
+// Batched round tiles: 256 threads of kRItems entries (with the per-entry set
+// ids, 512-thread blocks at 4 waves per SIMD would spill).
+constexpr int kBBlock = 256;
+constexpr int kBTile = kBBlock * kRItems;
+constexpr int kBSpan = kBTile + 2 * kRHalo;
+
 __global__ __launch_bounds__(256) void batch_init_kernel(LoopState* st, const BatchSet* __restrict__ sets,
                                                          uint32_t n_sets, uint64_t* K, uint32_t* pos, uint32_t* sid,
                                                          uint32_t* starts, uint64_t* lb, size_t lb_words,
@@ -828,7 +834,7 @@ __global__ __launch_bounds__(256) void batch_init_kernel(LoopState* st, const Ba
     }
 }
 
-__global__ __launch_bounds__(kRBlock, 4) void batch_round_kernel(const BatchSet* __restrict__ sets,
+__global__ __launch_bounds__(kBBlock, 4) void batch_round_kernel(const BatchSet* __restrict__ sets,
                                                                const uint64_t* __restrict__ K,
                                                                const uint32_t* __restrict__ pos,
                                                                const uint32_t* __restrict__ sid,
@@ -841,24 +847,24 @@ __global__ __launch_bounds__(kRBlock, 4) void batch_round_kernel(const BatchSet*
                                                                LoopState* st, int round, uint64_t capacity,
                                                                uint64_t* lb) {
     __shared__ uint32_t slot;
-    __shared__ uint64_t scan_tmp[kRBlock / kWave];
+    __shared__ uint64_t scan_tmp[kBBlock / kWave];
     __shared__ uint64_t tile_prefix;
     __shared__ uint32_t split_base;
     __shared__ uint32_t any_change;
-    __shared__ uint64_t sK[kRSpan];  // entries base-8 .., then the tile's new entries
-    __shared__ uint32_t sP[kRSpan];
-    __shared__ uint32_t sS[kRSpan];
+    __shared__ uint64_t sK[kBSpan];  // entries base-8 .., then the tile's new entries
+    __shared__ uint32_t sP[kBSpan];
+    __shared__ uint32_t sS[kBSpan];
     // sets that changed in this tile, by set id mod kSetFlags: a set holds at
-    // least two entries, so a tile spans at most kRTile / 2 + 1 consecutive
+    // least two entries, so a tile spans at most kBTile / 2 + 1 consecutive
     // sets, and they take distinct slots
-    constexpr uint32_t kSetFlags = kRTile;
-    static_assert((kSetFlags & (kSetFlags - 1)) == 0 && kSetFlags > kRTile / 2 + 1, "distinct slots");
+    constexpr uint32_t kSetFlags = kBTile;
+    static_assert((kSetFlags & (kSetFlags - 1)) == 0 && kSetFlags > kBTile / 2 + 1, "distinct slots");
     __shared__ uint8_t sflag[kSetFlags];
 
     if (round > 0 && st->changed[round - 1] == 0) return;  // every set converged earlier
     const uint64_t M = st->nl[round];
     if (M == 0 || M > capacity) return;  // an earlier round overflowed
-    const uint32_t tiles = static_cast<uint32_t>((M + kRTile - 1) / kRTile);
+    const uint32_t tiles = static_cast<uint32_t>((M + kBTile - 1) / kBTile);
     const uint32_t tid = threadIdx.x;
     const uint32_t epoch = static_cast<uint32_t>(round + 1);
     if (tid == 0) any_change = 0;
@@ -866,8 +872,8 @@ __global__ __launch_bounds__(kRBlock, 4) void batch_round_kernel(const BatchSet*
     for (;;) {
         const uint32_t tile = take_group_tile(st->counters[round], kCounterWords, kTileGroups, &slot);
         if (tile >= tiles) break;
-        const int64_t base = static_cast<int64_t>(tile) * kRTile;
-        for (int j = tid; j < kRSpan; j += kRBlock) {  // coalesced: entries base-8 .. base+2055 that exist
+        const int64_t base = static_cast<int64_t>(tile) * kBTile;
+        for (int j = tid; j < kBSpan; j += kBBlock) {  // coalesced: entries base-8 .. base+kBTile+7 that exist
             const int64_t g = base - kRHalo + j;
             if (g >= 0 && g < static_cast<int64_t>(M)) {
                 sK[j] = K[g];
@@ -875,7 +881,7 @@ __global__ __launch_bounds__(kRBlock, 4) void batch_round_kernel(const BatchSet*
                 sS[j] = sid[g];
             }
         }
-        for (uint32_t j = tid; j < kSetFlags; j += kRBlock) sflag[j] = 0;
+        for (uint32_t j = tid; j < kSetFlags; j += kBBlock) sflag[j] = 0;
         __syncthreads();
         const uint32_t lfirst = tid * kRItems;
         const uint64_t first = static_cast<uint64_t>(base) + lfirst;
@@ -922,7 +928,7 @@ __global__ __launch_bounds__(kRBlock, 4) void batch_round_kernel(const BatchSet*
         }
 
         uint64_t block_total;
-        const uint64_t excl = block_exclusive_sum<uint64_t, kRBlock>(
+        const uint64_t excl = block_exclusive_sum<uint64_t, kBBlock>(
             (static_cast<uint64_t>(nsplit) << 32) | osum, scan_tmp, &block_total);
         if (tid < kWave) {
             uint64_t prefix = 0;
@@ -944,11 +950,11 @@ __global__ __launch_bounds__(kRBlock, 4) void batch_round_kernel(const BatchSet*
         if (changed) any_change = 1;
         const uint32_t s_lo = sS[kRHalo];  // set of the tile's first entry (sS is rewritten after the barrier)
         __syncthreads();  // every thread has read the staged entries it needs
-        for (uint32_t j = tid; j < kSetFlags; j += kRBlock)  // one flag per set and tile
+        for (uint32_t j = tid; j < kSetFlags; j += kBBlock)  // one flag per set and tile
             if (sflag[j]) atomicOr(&changed_set[s_lo + ((j - s_lo) & (kSetFlags - 1))], 1u);
         const uint64_t tp = tile_prefix;
         const uint32_t out_total = static_cast<uint32_t>(block_total);  // new entries of this tile
-        const bool staged = out_total <= static_cast<uint32_t>(kRSpan);  // block-uniform
+        const bool staged = out_total <= static_cast<uint32_t>(kBSpan);  // block-uniform
 
         uint32_t lo = static_cast<uint32_t>(excl);  // this thread's first new entry, relative to tp
         uint32_t s_at = split_base + static_cast<uint32_t>(excl >> 32);
@@ -1002,7 +1008,7 @@ __global__ __launch_bounds__(kRBlock, 4) void batch_round_kernel(const BatchSet*
         }
         if (staged) {  // the writes above went to LDS (free after g1): store them coalesced
             __syncthreads();
-            for (uint32_t j = tid; j < out_total; j += kRBlock) {
+            for (uint32_t j = tid; j < out_total; j += kBBlock) {
                 if (tp + j <= capacity) {
                     K_out[tp + j] = sK[j];
                     pos_out[tp + j] = sP[j];  // split children 1..7 are overwritten by the split search
@@ -1100,7 +1106,7 @@ BatchRebalanceWs carve_batch_rebalance(void* ws, uint32_t n_sets, size_t C, size
     r.splits = c.take<uint64_t>(split_capacity);
     r.changed_set = c.take<uint32_t>(static_cast<size_t>(kMaxRounds) * n_sets);
     r.st = c.take<LoopState>(1);
-    r.lb_words = (C + kRTile - 1) / kRTile + 1;
+    r.lb_words = (C + kBTile - 1) / kBTile + 1;
     r.lb = c.take<uint64_t>(r.lb_words);
     r.bytes = c.off;
     return r;
@@ -1135,7 +1141,7 @@ cstone_status launch_batch_rebalance(const uint64_t* P, size_t n_total, const Ba
     const uint32_t cap_u = static_cast<uint32_t>(split_capacity);
     for (uint32_t q = 0; q < rounds; ++q) {
         const int a = q & 1, b = (q + 1) & 1;
-        hipLaunchKernelGGL(batch_round_kernel, dim3(clamp_grid(grid_1d(C + 1, kRTile))), dim3(kRBlock), 0, stream,
+        hipLaunchKernelGGL(batch_round_kernel, dim3(clamp_grid(grid_1d(C + 1, kBTile))), dim3(kBBlock), 0, stream,
                            sets, w.K[a], w.pos[a], w.sid[a], w.K[b], w.pos[b], w.sid[b], w.starts[b], n_sets,
                            w.changed_set + static_cast<size_t>(q) * n_sets, w.splits, cap_u, w.st,
                            static_cast<int>(q), static_cast<uint64_t>(C), w.lb);
