@@ -841,7 +841,8 @@ __device__ __forceinline__ void list_large(const LargeList& L, uint32_t start, u
 // SEG: the keys are n_sets key sets back to back, set s starting at
 // seg_base[s] (non-decreasing), each ordered by prefix on its own; every set's
 // first key starts a bucket and no bucket runs past its set. chunk_set[b] is
-// the first set starting at or after block b's first key.
+// the first set starting at or after block b's first key, chunk_set[chunks +
+// 1 + b] where that set starts (n if none).
 template <int BITS, int BLOCK, int ITEMS, bool SEG>
 __global__ __launch_bounds__(BLOCK, kLocalBlocksPerCU * BLOCK / (4 * kWave)) void local_sort_kernel(
     uint64_t* keys, uint32_t* vals, uint32_t n, uint32_t pshift, LargeList large, uint32_t* err, uint32_t* level6,
@@ -864,13 +865,13 @@ __global__ __launch_bounds__(BLOCK, kLocalBlocksPerCU * BLOCK / (4 * kWave)) voi
         sm.end = 0xffffffffu;
         sm.next_set = n_sets;
     }
-    // the chunk's first set and this thread's first set start, read before
-    // the window so that their round trips overlap its load
-    uint32_t s0 = 0, at0 = 0;
+    // the chunk's first set and where it starts, read before the window so
+    // that the round trip overlaps its load
+    uint32_t s0 = 0, first_at = 0;
     if constexpr (SEG) {
         for (uint32_t i = tid; i < CAP / 32; i += BLOCK) sm.setbits[i] = 0;
         s0 = chunk_set[blockIdx.x];
-        if (s0 + tid < n_sets) at0 = seg_base[s0 + tid];
+        first_at = chunk_set[gridDim.x + 1 + blockIdx.x];
     }
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
@@ -882,16 +883,19 @@ __global__ __launch_bounds__(BLOCK, kLocalBlocksPerCU * BLOCK / (4 * kWave)) voi
     }
     const uint64_t before = lo ? kin[lo - 1] >> pshift : ~0ull;  // the same word in every lane
     if constexpr (SEG) {
-        // mark the set starts in the window; the first set starting at or
-        // after the window's end gives the end of a last bucket that runs past it
-        __syncthreads();
-        for (uint32_t q = s0 + tid; q < n_sets; q += BLOCK) {
-            const uint32_t at = q == s0 + tid ? at0 : seg_base[q];
-            if (at >= wend) {
-                atomicMin(&sm.next_set, q);
-                break;
+        // mark the set starts in the window (none in most windows); the first
+        // set starting at or after the window's end gives the end of a last
+        // bucket that runs past it
+        if (first_at < wend) {  // block-uniform
+            __syncthreads();
+            for (uint32_t q = s0 + tid; q < n_sets; q += BLOCK) {
+                const uint32_t at = seg_base[q];
+                if (at >= wend) {
+                    atomicMin(&sm.next_set, q);
+                    break;
+                }
+                if (at >= lo) atomicOr(&sm.setbits[(at - lo) >> 5], 1u << ((at - lo) & 31u));
             }
-            if (at >= lo) atomicOr(&sm.setbits[(at - lo) >> 5], 1u << ((at - lo) & 31u));
         }
     }
     __syncthreads();
@@ -935,7 +939,8 @@ __global__ __launch_bounds__(BLOCK, kLocalBlocksPerCU * BLOCK / (4 * kWave)) voi
     // where the last bucket's keys end at the latest: the keys' end, or the
     // next set's start
     uint32_t bound_end = n;
-    if constexpr (SEG) bound_end = sm.next_set < n_sets ? seg_base[sm.next_set] : n;
+    if constexpr (SEG)
+        bound_end = first_at >= wend ? first_at : (sm.next_set < n_sets ? seg_base[sm.next_set] : n);
     uint32_t e = sm.end;
     if (e == 0xffffffffu && wend == bound_end) e = wn;  // the last bucket ends with the window
     if (e != 0xffffffffu) {
@@ -1445,15 +1450,17 @@ SegWs carve_seg(void* ws, size_t n_total, size_t n_tiles, uint32_t n_sets, int v
         s.large_tiles = c.take<uint4>(s.max_list_tiles);
         s.large_start = c.take<uint32_t>(s.max_buckets + 1);
         s.large_hist = c.take<uint32_t>((s.max_buckets + 1) * kLowPasses * kMaxRadix);
-        s.chunk_set = c.take<uint32_t>(s.chunks + 1);
+        s.chunk_set = c.take<uint32_t>(2 * (s.chunks + 1));
     }
     s.bytes = c.off;
     return s;
 }
 
-// chunk_set[b] = first set whose start is at or after b * kLocalChunk (n_sets if none).
+// chunk_set[b] = first set whose start is at or after b * kLocalChunk (n_sets
+// if none), chunk_set[chunks + 1 + b] = that start (n if none).
 __global__ __launch_bounds__(256) void chunk_set_kernel(const uint32_t* __restrict__ seg_base, uint32_t n_sets,
-                                                        uint32_t* __restrict__ chunk_set, uint32_t chunks) {
+                                                        uint32_t* __restrict__ chunk_set, uint32_t chunks,
+                                                        uint32_t n) {
     const uint32_t b = blockIdx.x * 256u + threadIdx.x;
     if (b >= chunks) return;
     const uint64_t at = static_cast<uint64_t>(b) * kLocalChunk;
@@ -1464,6 +1471,7 @@ __global__ __launch_bounds__(256) void chunk_set_kernel(const uint32_t* __restri
         else hi = mid;
     }
     chunk_set[b] = lo;
+    chunk_set[chunks + 1 + b] = lo < n_sets ? seg_base[lo] : n;
 }
 
 }  // namespace
@@ -1508,7 +1516,7 @@ cstone_status launch_split_seg(const uint64_t* keys_in, uint64_t* keys_out, uint
     uint32_t* lb32[2] = {static_cast<uint32_t*>(s.lb), static_cast<uint32_t*>(s.lb) + s.rows * kMaxRadix};
     const uint32_t chunks = static_cast<uint32_t>(s.chunks);
     hipLaunchKernelGGL(chunk_set_kernel, dim3((chunks + 255) / 256), dim3(256), 0, stream, seg_base, n_sets,
-                       s.chunk_set, chunks);
+                       s.chunk_set, chunks, static_cast<uint32_t>(n_total));
     SegArgs g{tiles, seg_base, n_tiles, s.stride, nullptr};
     const uint64_t* src_k = keys_in;
     const uint32_t* src_v = nullptr;
