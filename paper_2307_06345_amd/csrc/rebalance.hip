@@ -890,6 +890,7 @@ __global__ __launch_bounds__(kBBlock, 4) void batch_round_kernel(const BatchSet*
         uint64_t kk[kRItems + 1];  // this thread's entries and the next one
         uint32_t pp[kRItems], ss[kRItems];
         uint32_t osum = 0, nsplit = 0;
+        uint32_t nc = 0, nc_set = 0xffffffffu;  // n_crit of set nc_set
         bool changed = false;
 #pragma unroll
         for (int j = 0; j <= kRItems; ++j) kk[j] = sK[kRHalo + lfirst + j];
@@ -905,7 +906,10 @@ __global__ __launch_bounds__(kBBlock, 4) void batch_round_kernel(const BatchSet*
                 o = 1;
                 if (ke != kKeyEnd) {  // a leaf (closing entries are kept)
                     const uint32_t s = ss[j];
-                    const uint32_t nc = sets[s].n_crit;
+                    if (s != nc_set) {  // a thread's entries nearly always share one set
+                        nc = sets[s].n_crit;
+                        nc_set = s;
+                    }
                     const uint64_t delta = kk[j + 1] - ke;
                     const uint32_t cnt = sP[li + 1] - pp[j];
                     if (cnt > nc && delta > 1) {
