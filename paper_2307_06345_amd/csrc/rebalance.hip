@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <cstddef>
 #include <cstring>
+#include <memory>
 
 #include "common.hpp"
 #include "internal.hpp"
@@ -736,7 +737,8 @@ cstone_status RebalanceLoop::enqueue(uint32_t rounds) {
 const uint64_t* RebalanceLoop::device_leaf_count() const { return &st_->final_nl; }
 
 cstone_status RebalanceLoop::wait(bool* finished) {
-    LoopState host;
+    std::unique_ptr<LoopState> held(new LoopState);  // large (the device-only tile counters at its end)
+    LoopState& host = *held;
     CS_HIP(hipMemcpyAsync(&host, st_, offsetof(LoopState, counters), hipMemcpyDeviceToHost, stream_));
     CS_HIP(hipStreamSynchronize(stream_));
     input_flags = host.input_flags;
