@@ -371,19 +371,28 @@ __global__ __launch_bounds__(kBfBlock) void batch_bf_write_kernel(BatchTreeView 
             for (int w = 0; w < kBfWaves; ++w) before += w < static_cast<int>(wave) ? wtot[l][w] : 0u;
             run[l][tid] = tile_offsets[static_cast<size_t>(l) * stride + tile] + before + inc[l] - c[l];
         }
+        // a thread's entries nearly always share one set: its node region is
+        // read once per set, not per entry
+        uint32_t cur = 0xffffffffu;
+        uint64_t node_off = 0, node_cap = 0;
+        const uint32_t* rs = rel;
 #pragma unroll
         for (int it = 0; it < kBfItems; ++it) {
             const size_t j = first + it;
             if (j >= src.M || r.lam[it] < 0) continue;
             const uint64_t kj = src.K[j];
             const uint32_t s = src.sid[j];
-            const BatchSet& S = sets[s];
-            const uint32_t* rs = rel + static_cast<size_t>(s) * kLevels;
+            if (s != cur) {
+                cur = s;
+                node_off = sets[s].node_off;
+                node_cap = sets[s].node_cap;
+                rs = rel + static_cast<size_t>(s) * kLevels;
+            }
             for (int l = r.a[it] + 1; l <= r.lam[it]; ++l) {
                 const uint32_t p = rs[l] + run[l][tid]++;  // index within the set's node array
-                if (p >= S.node_cap) continue;            // never for a cornerstone array; guards memory
-                nk[S.node_off + p] = (1ull << (3 * l)) | (kj >> (3 * (kL - l)));
-                co[S.node_off + p] = l < r.lam[it] ? rs[l + 1] + run[l + 1][tid] : 0u;
+                if (p >= node_cap) continue;              // never for a cornerstone array; guards memory
+                nk[node_off + p] = (1ull << (3 * l)) | (kj >> (3 * (kL - l)));
+                co[node_off + p] = l < r.lam[it] ? rs[l + 1] + run[l + 1][tid] : 0u;
             }
         }
         __syncthreads();
