@@ -705,9 +705,18 @@ cstone_status RebalanceLoop::enqueue(uint32_t rounds) {
                 ratio /= 8.0;
                 ++rounds;
             }
-            // less the rounds a uniform start skips, with one level to spare (a
-            // start coarser than that needs a later batch)
-            if (start_top_ > 1) rounds = std::max<uint32_t>(2, rounds - static_cast<uint32_t>(start_top_ - 1));
+            // less the rounds a uniform start skips. One level is kept to spare
+            // when the start may come out a level coarser (the level above it
+            // holds under 2 (n_crit + 1) particles per node on average, so
+            // some node may not exceed n_crit); a start coarser than that, or
+            // a deeper tree, needs a later batch. The last round, the check,
+            // costs only its launch when the round before it settles the tree.
+            if (start_top_ > 1) {
+                const double above = static_cast<double>(n_) / (static_cast<double>(n_crit_) + 1.0) /
+                                     static_cast<double>(size_t{1} << (3 * (start_top_ - 1)));
+                const uint32_t skip = static_cast<uint32_t>(start_top_) - (above < 2.0 ? 1u : 0u);
+                rounds = std::max<uint32_t>(2, rounds - skip);
+            }
         }
     }
     rounds = std::min(rounds, max_iters_ - enqueued_);
