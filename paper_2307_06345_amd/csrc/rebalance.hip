@@ -210,13 +210,18 @@ __global__ __launch_bounds__(kFineBlock) void start_fine_kernel(const uint64_t* 
     if (c == kCoarseNodes - 1 && threadIdx.x == 0) posf[kCoarseNodes * per] = posc[kCoarseNodes];
 }
 
-// least counts of levels 4 .. lf - 1 from the finer positions (block minima,
-// then one atomic per block and level)
-__global__ __launch_bounds__(256) void start_mins_kernel(const uint32_t* __restrict__ posf, int lf, LoopState* st) {
+// least counts of levels k0 .. lf - 1 from the finer positions (block minima,
+// then one atomic per block and level). With `all` (positions from the sort's
+// level-6 table, complete at every level up to lf) it covers levels 0 .. lf - 1
+// and marks the start search fine; otherwise levels 4 .. lf - 1, once the
+// coarse check found every level-3 node over n_crit.
+__global__ __launch_bounds__(256) void start_mins_kernel(const uint32_t* __restrict__ posf, int lf, LoopState* st,
+                                                         int all) {
     __shared__ uint32_t red[256 / kWave];
-    if (!st->start_fine) return;
+    if (!all && !st->start_fine) return;
+    if (all && blockIdx.x == 0 && threadIdx.x == 0) st->start_fine = 1;
     const uint32_t stride = gridDim.x * blockDim.x;
-    for (int k = kStartCoarse + 1; k < lf; ++k) {
+    for (int k = all ? 0 : kStartCoarse + 1; k < lf; ++k) {
         const uint32_t nodes = 1u << (3 * k);
         const uint32_t span = 1u << (3 * (lf - k));
         uint32_t c = 0xffffffffu;
@@ -678,14 +683,19 @@ cstone_status RebalanceLoop::begin(const uint64_t* P, size_t n, uint32_t n_crit,
         else
             hipLaunchKernelGGL(start_coarse_kernel, dim3(grid_1d(kCoarseNodes + 1, 256 / kWave)), dim3(256), 0, stream,
                                P, un, w.posc);
-        hipLaunchKernelGGL(start_check_kernel, dim3(1), dim3(kCoarseNodes), 0, stream, w.posc, n_crit, lf, w.st);
-        if (lf > kStartCoarse) {
-            if (!level6)
+        if (level6) {  // positions at every level up to lf: all minima in one pass
+            hipLaunchKernelGGL(start_mins_kernel, dim3(clamp_grid(grid_1d(size_t{1} << (3 * (lf - 1)), 256))),
+                               dim3(256), 0, stream, w.pos[1], lf, w.st, 1);
+        } else {
+            hipLaunchKernelGGL(start_check_kernel, dim3(1), dim3(kCoarseNodes), 0, stream, w.posc, n_crit, lf, w.st);
+            if (lf > kStartCoarse) {
                 hipLaunchKernelGGL(start_fine_kernel, dim3(kCoarseNodes), dim3(kFineBlock), 0, stream, P, w.posc, lf,
                                    w.st, w.pos[1]);
-            if (lf > kStartCoarse + 1)
-                hipLaunchKernelGGL(start_mins_kernel, dim3(clamp_grid(grid_1d(size_t{1} << (3 * (lf - 1)), 256))),
-                                   dim3(256), 0, stream, w.pos[1], lf, w.st);
+                if (lf > kStartCoarse + 1)
+                    hipLaunchKernelGGL(start_mins_kernel,
+                                       dim3(clamp_grid(grid_1d(size_t{1} << (3 * (lf - 1)), 256))), dim3(256), 0,
+                                       stream, w.pos[1], lf, w.st, 0);
+            }
         }
         hipLaunchKernelGGL(start_write_kernel, dim3(clamp_grid(grid_1d((size_t{1} << (3 * lf)) + 1, 256))), dim3(256),
                            0, stream, w.posc, w.pos[1], lf, n_crit, w.st, leaves, w.pos[0]);
