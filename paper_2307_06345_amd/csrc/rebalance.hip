@@ -61,11 +61,10 @@ __global__ __launch_bounds__(kCountBlock) void positions_kernel(const uint64_t* 
     if (i <= nl) pos[i] = static_cast<uint32_t>(lower_bound_u64(P, 0, n, K[i]));
 }
 
-__global__ __launch_bounds__(256) void loop_init_kernel(LoopState* st, uint64_t nl0, uint64_t* lb, size_t lb_words,
-                                                        uint32_t* pos, uint32_t n, int root, uint64_t* K,
-                                                        const uint32_t* input_flags) {
-    const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
-    const size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+// The loop's set-up, as thread t of `stride` threads.
+__device__ __forceinline__ void loop_init_part(size_t t, size_t stride, LoopState* st, uint64_t nl0, uint64_t* lb,
+                                               size_t lb_words, uint32_t* pos, uint32_t n, int root, uint64_t* K,
+                                               const uint32_t* input_flags) {
     for (size_t i = t; i < lb_words; i += stride) lb[i] = 0;
     if (t < kMaxRounds) {
         st->changed[t] = 0;
@@ -87,6 +86,13 @@ __global__ __launch_bounds__(256) void loop_init_kernel(LoopState* st, uint64_t 
             pos[1] = n;
         }
     }
+}
+
+__global__ __launch_bounds__(256) void loop_init_kernel(LoopState* st, uint64_t nl0, uint64_t* lb, size_t lb_words,
+                                                        uint32_t* pos, uint32_t n, int root, uint64_t* K,
+                                                        const uint32_t* input_flags) {
+    loop_init_part(static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x,
+                   static_cast<size_t>(gridDim.x) * blockDim.x, st, nl0, lb, lb_words, pos, n, root, K, input_flags);
 }
 
 // ---- an exact start from a uniform level ---------------------------------------
@@ -143,14 +149,13 @@ __global__ __launch_bounds__(kCoarseNodes) void start_check_kernel(const uint32_
 // Level-3 and level-lf positions from the sort's level-6 table: the first
 // position at or after node j's start is that of the first non-empty level-6
 // node at or after it; up to 64 entries are scanned, then P is searched.
-__global__ __launch_bounds__(256) void start_table_kernel(const uint64_t* __restrict__ P, uint32_t n,
-                                                          const uint32_t* __restrict__ level6, int lf,
-                                                          uint32_t* __restrict__ posc, uint32_t* __restrict__ posf) {
+__device__ __forceinline__ void start_table_part(uint32_t t, uint32_t stride, const uint64_t* __restrict__ P,
+                                                 uint32_t n, const uint32_t* __restrict__ level6, int lf,
+                                                 uint32_t* __restrict__ posc, uint32_t* __restrict__ posf) {
     const uint32_t nodes = 1u << (3 * lf);
     const int sh = 3 * (kStartFine - lf);   // level-6 nodes per level-lf node: 2^sh
     const int up = 3 * (lf - kStartCoarse);  // level-lf nodes per level-3 node: 2^up
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j <= nodes; j += stride) {
+    for (uint32_t j = t; j <= nodes; j += stride) {
         const uint32_t c0 = j << sh;
         uint32_t at = n;
         if (c0 < kLevel6Cells) {
@@ -165,6 +170,19 @@ __global__ __launch_bounds__(256) void start_table_kernel(const uint64_t* __rest
         posf[j] = at;
         if ((j & ((1u << up) - 1)) == 0) posc[j >> up] = at;
     }
+}
+
+// The loop's set-up and the table positions in one launch (independent work).
+__global__ __launch_bounds__(256) void loop_init_table_kernel(LoopState* st, uint64_t nl0, uint64_t* lb,
+                                                              size_t lb_words, uint32_t* pos, uint32_t n,
+                                                              const uint32_t* input_flags,
+                                                              const uint64_t* __restrict__ P,
+                                                              const uint32_t* __restrict__ level6, int lf,
+                                                              uint32_t* __restrict__ posc,
+                                                              uint32_t* __restrict__ posf) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+    loop_init_part(t, stride, st, nl0, lb, lb_words, pos, n, 0, nullptr, input_flags);
+    start_table_part(t, stride, P, n, level6, lf, posc, posf);
 }
 
 // Positions of the level-lf nodes: block c searches the nodes inside coarse
@@ -666,9 +684,16 @@ cstone_status RebalanceLoop::begin(const uint64_t* P, size_t n, uint32_t n_crit,
         lf = std::min(std::max(lf, kStartCoarse), kStartFine);
         if ((size_t{1} << (3 * lf)) <= cap) start_top_ = lf;
     }
-    hipLaunchKernelGGL(loop_init_kernel, dim3(clamp_grid(grid_1d(std::max<size_t>(w.lb_words, kMaxRounds + 1), 256))),
-                       dim3(256), 0, stream, w.st, static_cast<uint64_t>(nl0), w.lb, w.lb_words, w.pos[0],
-                       static_cast<uint32_t>(n), (root_ && !start_top_) ? 1 : 0, leaves, input_flags);
+    const size_t init_items = std::max<size_t>(w.lb_words, kMaxRounds + 1);
+    if (start_top_ && level6)  // the set-up and the start positions from the sort's table together
+        hipLaunchKernelGGL(loop_init_table_kernel,
+                           dim3(clamp_grid(grid_1d(std::max<size_t>(init_items, (size_t{1} << (3 * start_top_)) + 1), 256))),
+                           dim3(256), 0, stream, w.st, static_cast<uint64_t>(nl0), w.lb, w.lb_words, w.pos[0],
+                           static_cast<uint32_t>(n), input_flags, P, level6, start_top_, w.posc, w.pos[1]);
+    else
+        hipLaunchKernelGGL(loop_init_kernel, dim3(clamp_grid(grid_1d(init_items, 256))), dim3(256), 0, stream, w.st,
+                           static_cast<uint64_t>(nl0), w.lb, w.lb_words, w.pos[0], static_cast<uint32_t>(n),
+                           (root_ && !start_top_) ? 1 : 0, leaves, input_flags);
     if (!root_)
         hipLaunchKernelGGL(positions_kernel, dim3(grid_1d(nl0 + 1, kCountBlock)), dim3(kCountBlock), 0, stream, P, n,
                            leaves, nl0, w.pos[0]);
@@ -677,10 +702,7 @@ cstone_status RebalanceLoop::begin(const uint64_t* P, size_t n, uint32_t n_crit,
         const uint32_t un = static_cast<uint32_t>(n);
         // positions of the level-3 and level-lf nodes: from the sort's level-6
         // table when there is one, else by searching P
-        if (level6)
-            hipLaunchKernelGGL(start_table_kernel, dim3(clamp_grid(grid_1d((size_t{1} << (3 * lf)) + 1, 256))),
-                               dim3(256), 0, stream, P, un, level6, lf, w.posc, w.pos[1]);
-        else
+        if (!level6)
             hipLaunchKernelGGL(start_coarse_kernel, dim3(grid_1d(kCoarseNodes + 1, 256 / kWave)), dim3(256), 0, stream,
                                P, un, w.posc);
         if (level6) {  // positions at every level up to lf: all minima in one pass
