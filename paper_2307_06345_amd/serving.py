@@ -220,7 +220,7 @@ class ServingLoop:
 class GpuExecutor:
     """Runs each admitted group as one batched build on its own stream."""
 
-    def __init__(self, max_inflight: int = 3, device="cuda", keep=(), reserve=None):
+    def __init__(self, max_inflight: int = 3, device="cuda", keep=(), reserve=None, sink=None):
         import torch
 
         import workloads
@@ -233,6 +233,7 @@ class GpuExecutor:
         self.free = [torch.cuda.Stream(self.device) for _ in range(max_inflight)]
         self.keep = set(keep)
         self.kept = {}  # rid -> dict of host outputs
+        self.sink = sink  # sink(rid, outputs): takes the kept outputs instead of self.kept
         # leaf capacity of a request (default: leaf_reservation)
         self.reserve = reserve or (lambda r: leaf_reservation(r.n, r.n_crit, r.full))
 
@@ -270,7 +271,10 @@ class GpuExecutor:
                 rec = {k: to_numpy(v[k]).copy() for k in
                        ("sorted_keys", "perm", "leaves", "counts", "node_keys", "child", "level_offsets")}
                 rec.update({a: h["coords"][i][p0:p1].cpu().numpy() for i, a in enumerate("xyz")})
-                self.kept[r.rid] = rec
+                if self.sink is not None:
+                    self.sink(r.rid, rec)
+                else:
+                    self.kept[r.rid] = rec
         self.free.append(h["stream"])
         return out
 

@@ -13,9 +13,13 @@ def ordered(t):
     return torch.bitwise_xor(t, torch.tensor(SIGN, dtype=torch.int64, device=t.device))
 
 
-def check_sorted_perm(P, perm, n):
-    """P non-decreasing (keys < 2^63), perm a permutation, ties ascending."""
+def check_sorted_perm(P, perm, n, keys=None):
+    """P non-decreasing (keys < 2^63), perm a permutation, ties ascending, and
+    (if the unsorted keys are given) P[i] = keys[perm[i]]: together these fix
+    the stable sort's output exactly."""
     assert P.numel() == n and perm.numel() == n
+    if keys is not None and n:
+        assert torch.equal(P, keys[perm.long()]), "P must be the keys taken through perm"
     if n < 2:
         return
     assert bool((P[1:] >= P[:-1]).all()), "sorted keys must be non-decreasing"

@@ -3,6 +3,8 @@ known answers, determinism, a set drawn alone equals the same set drawn in a
 group), and continuous batching: every request's tree built in the mix of a
 serving run is bit-identical to the same request built alone (plain build and
 batch of one), and to the oracle on a sample."""
+import concurrent.futures as cf
+
 import numpy as np
 import pytest
 import torch
@@ -133,3 +135,93 @@ def test_serving_retries_sets_over_their_reservation():
         plain, _ = _alone(rec, r.kind, r.n, r.n_crit)
         eq(rec["leaves"], host(plain.leaves), f"request {rid} leaves vs alone")
         eq(rec["node_keys"], host(plain.node_keys), f"request {rid} NK vs alone")
+
+
+def _digest(rec, names):
+    import hashlib
+
+    return {k: hashlib.blake2b(np.ascontiguousarray(rec[k]).tobytes(), digest_size=20).hexdigest() for k in names}
+
+
+OUT_NAMES = ("sorted_keys", "perm", "leaves", "counts", "node_keys", "child", "level_offsets")
+
+
+def stratified_sample(specs, per_stratum=50):
+    """Request indices of the serving workload, `per_stratum` from every unit
+    interval of log2(size) in [12, 22) (in arrival order), plus the largest."""
+    sizes = np.array([s[1] for s in specs], dtype=np.float64)
+    lg = np.log2(sizes)
+    pick = set()
+    for k in range(12, 22):
+        pick.update(int(i) for i in np.flatnonzero((lg >= k) & (lg < k + 1))[:per_stratum])
+    pick.add(int(np.argmax(sizes)))
+    return sorted(pick)
+
+
+def test_serving_stratified_sample_equals_alone_and_oracle():
+    """Requests of the serving workload itself (same payload streams), 50 from
+    every octave of size up to 2^22 plus the largest, served together with
+    continuous batching: every one equals the oracle in every output (checked
+    on host threads as requests complete, then dropped) and the same request
+    built alone, as a plain build and (every 5th) as a batch of one."""
+    import threading
+
+    from tests import oracle_pool as pool
+
+    specs = wl.serving_specs()
+    pick = stratified_sample(specs)
+    sample = [specs[i] for i in pick]
+    assert len(sample) >= 500 and max(s[1] for s in sample) >= 1 << 21
+    assert {s[2] for s in sample} == {16, 64} and {s[0] for s in sample} == {"uniform", "plummer"}
+    reqs = sv.poisson_requests(sample, rate_per_s=5000.0)
+    say("serving", len(reqs), "sampled requests,", sum(r.n for r in reqs), "particles")
+    gate = threading.BoundedSemaphore(24)  # records waiting for the oracle (bounds host memory)
+    jobs = {}
+    ex_pool = cf.ThreadPoolExecutor(max_workers=pool.workers())
+    by_rid = {r.rid: r for r in reqs}
+
+    def check(rid, rec):
+        try:
+            r = by_rid[rid]
+            msgs = pool.compare_build(rec, rec["x"], rec["y"], rec["z"], sv.BOXES[r.kind], cs.HILBERT, r.n_crit,
+                                      f"request {rid} (n={r.n}, {r.kind}, n_crit={r.n_crit})")
+            return msgs, _digest(rec, OUT_NAMES + tuple("xyz"))
+        finally:
+            gate.release()
+
+    def sink(rid, rec):
+        gate.acquire()
+        jobs[rid] = ex_pool.submit(check, rid, rec)
+
+    try:
+        ex = sv.GpuExecutor(max_inflight=3, keep={r.rid for r in reqs}, sink=sink)
+        done, st = sv.ServingLoop(ex).run(reqs)
+        torch.cuda.synchronize()
+        say("batches", st.batches, "mean", st.mean_batch_requests, "max in flight", st.max_inflight)
+        assert len(done) == len(reqs) and all(r.status == "OK" for r in done), st.statuses
+        assert st.batches < len(reqs) and st.max_inflight > 1
+        results = {rid: f.result() for rid, f in jobs.items()}
+    finally:
+        ex_pool.shutdown(wait=True)
+    assert sorted(results) == sorted(by_rid)
+    msgs = [m for ms, _ in results.values() for m in ms]
+    assert not msgs, "\n".join(msgs[:20])
+    say("all", len(results), "requests equal the oracle; now alone")
+    cap = max(sv.leaf_bound(r.n, r.n_crit) for r in reqs)
+    builder = cs.Builder(max(r.n for r in reqs), 16, leaf_capacity=min(cap, 8 * (1 << 22) // 17 + 64))
+    for j, r in enumerate(done):
+        x, y, z, _ = wl.device_sets([(r.kind, r.n, r.seed, r.stream)])
+        x, y, z = x[:r.n], y[:r.n], z[:r.n]
+        mix = results[r.rid][1]
+        alone = builder.build(x, y, z, sv.BOXES[r.kind], cs.HILBERT, r.n_crit)
+        rec = {k: cs.to_numpy(getattr(alone, k)) for k in OUT_NAMES}
+        rec.update({a: host(t) for a, t in zip("xyz", (x, y, z))})
+        got = _digest(rec, OUT_NAMES + tuple("xyz"))
+        assert got == mix, f"request {r.rid} (n={r.n}): plain build alone differs from the mix"
+        if j % 5 == 0:
+            b = cs.Batch([(r.n, sv.BOXES[r.kind], cs.HILBERT, r.n_crit)])
+            b.build(x, y, z)
+            v = b.set_view(0)
+            got = _digest({k: host(v[k]) for k in OUT_NAMES}, OUT_NAMES)
+            assert got == {k: mix[k] for k in OUT_NAMES}, f"request {r.rid}: batch of one differs from the mix"
+            del b
