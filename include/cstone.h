@@ -218,21 +218,53 @@ CSTONE_API cstone_status cstone_build(const double* x, const double* y, const do
                            hipStream_t stream);
 
 /* ------------------------------------------------------------------------
- * Sort tile shapes. The radix sort has a few compiled shapes (digit width,
- * block size, keys per thread); the autotuner times them and the fastest is
- * used from then on by every sort of the process (the only process-wide
- * state of the library).
+ * Sort tile shapes and their autotune table. The radix sort has several
+ * compiled shapes (digit width, block size, keys per thread). Which one a
+ * sort runs is looked up once, when the sort (or build) starts, in a
+ * process-wide table keyed by (kernel, size class, device):
+ *   kernel      CSTONE_TUNE_SORT: the particle-key sort of cstone_sort and
+ *               cstone_build; CSTONE_TUNE_BATCH_SORT: the segmented sort of a
+ *               batch plan (looked up by cstone_batch_create, n = all its
+ *               particles);
+ *   size class  floor(log2 n);
+ *   device      the current HIP device's architecture and compute-unit count.
+ * Without an entry the built-in shape (index 0) is used. Every shape gives
+ * the same result (the sort is stable), so the table changes speed only.
+ * The table is the library's only process-wide state; its calls are
+ * thread-safe, and a sort already started keeps the shape it looked up.
  *   cstone_sort_autotune  sorts keys_in (device, n, < 2^63) with every shape,
- *                         reps times each, writes the mean times (host, one
- *                         per shape, or NULL) and the index chosen, and makes
- *                         it the default. ws: cstone_sort_workspace_bytes(n).
+ *                         reps times each after a warm-up, writes the mean
+ *                         times (host, one per shape, or NULL) and the index
+ *                         chosen, and records it for (CSTONE_TUNE_SORT, n,
+ *                         this device). ws: cstone_sort_workspace_bytes(n).
  *                         Synchronises `stream`.
+ *   cstone_tune_set       records `variant` for (kernel, size class of n, this
+ *                         device); -1 removes that entry. INVALID_ARG for an
+ *                         unknown kernel or shape.
+ *   cstone_tune_get       the recorded shape for (kernel, n, this device), or -1.
+ *   cstone_tune_clear     empties the table; cstone_tune_entries counts it.
+ *   cstone_tune_save      writes the table to a JSON file (one entry per line:
+ *                         kernel, size_log2, device, variant and the shape's
+ *                         digit bits, block and items). INVALID_ARG if the file
+ *                         cannot be written.
+ *   cstone_tune_load      merges such a file into the table, skipping entries
+ *                         whose index does not name the same shape in this
+ *                         library. INVALID_ARG if the file cannot be read or
+ *                         is not in that format (the table is then unchanged).
  */
+#define CSTONE_TUNE_SORT 0
+#define CSTONE_TUNE_BATCH_SORT 1
 CSTONE_API int cstone_sort_variant_count(void);
 CSTONE_API cstone_status cstone_sort_variant_info(int variant, int* digit_bits, int* block, int* items);
 CSTONE_API cstone_status cstone_sort_autotune(const uint64_t* keys_in, size_t n, uint64_t* keys_out, uint32_t* perm_out,
                                    void* ws, size_t ws_bytes, int reps, float* ms_per_variant, int* chosen,
                                    hipStream_t stream);
+CSTONE_API cstone_status cstone_tune_set(int kernel, size_t n, int variant);
+CSTONE_API int cstone_tune_get(int kernel, size_t n);
+CSTONE_API void cstone_tune_clear(void);
+CSTONE_API size_t cstone_tune_entries(void);
+CSTONE_API cstone_status cstone_tune_save(const char* path);
+CSTONE_API cstone_status cstone_tune_load(const char* path);
 
 /* ------------------------------------------------------------------------
  * Batched builds: many independent particle sets (Sec. 4-5 for each), of
@@ -288,7 +320,8 @@ CSTONE_API void cstone_batch_destroy(cstone_batch* plan);
 /* Any of the offset arrays (host, n_sets + 1 entries) may be NULL. */
 CSTONE_API cstone_status cstone_batch_get_layout(const cstone_batch* plan, cstone_batch_layout* layout,
                                       uint64_t* particle_offsets, uint64_t* leaf_offsets, uint64_t* node_offsets);
-/* Sort shape of this plan (cstone_sort_variant_count() shapes); call
+/* Sort shape of this plan (cstone_sort_variant_count() shapes; a new plan
+ * takes the autotune table's shape for its size, else the built-in one); call
  * cstone_batch_upload again afterwards. */
 CSTONE_API cstone_status cstone_batch_set_variant(cstone_batch* plan, int variant);
 /* Rebalance rounds enqueued per build, 1 .. L + 1 = 22 (the default); a set
@@ -312,8 +345,9 @@ CSTONE_API cstone_status cstone_batch_capture(cstone_batch* plan, const double* 
 /* Launch the captured graph on `stream` (asynchronous). */
 CSTONE_API cstone_status cstone_batch_launch(cstone_batch* plan, hipStream_t stream);
 /* Build with every sort shape (reps timed builds each, after one warm-up),
- * keep the fastest in the plan and upload it. Times per shape (host, or NULL).
- * Drops a captured graph. Synchronises `stream`. */
+ * keep the fastest in the plan, upload it and record it in the autotune table
+ * for (CSTONE_TUNE_BATCH_SORT, the plan's particle count, this device). Times
+ * per shape (host, or NULL). Drops a captured graph. Synchronises `stream`. */
 CSTONE_API cstone_status cstone_batch_autotune(cstone_batch* plan, const double* x, const double* y, const double* z,
                                     uint64_t* sorted_keys, uint32_t* perm, uint64_t* leaves, uint32_t* counts,
                                     uint64_t* node_keys, uint32_t* child, uint32_t* level_offsets,

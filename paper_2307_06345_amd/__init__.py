@@ -88,6 +88,12 @@ def _load() -> ctypes.CDLL:
         "cstone_sort_variant_info": (i32, [i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "cstone_sort_autotune": (i32, [P, sz, P, P, P, sz, i32, ctypes.POINTER(ctypes.c_float),
                                        ctypes.POINTER(i32), P]),
+        "cstone_tune_set": (i32, [i32, sz, i32]),
+        "cstone_tune_get": (i32, [i32, sz]),
+        "cstone_tune_clear": (None, []),
+        "cstone_tune_entries": (sz, []),
+        "cstone_tune_save": (i32, [ctypes.c_char_p]),
+        "cstone_tune_load": (i32, [ctypes.c_char_p]),
         "cstone_batch_create": (i32, [ctypes.POINTER(CSet), u32, ctypes.POINTER(P)]),
         "cstone_batch_destroy": (None, [P]),
         "cstone_batch_get_layout": (i32, [P, ctypes.POINTER(BatchLayout), P, P, P]),
@@ -379,8 +385,9 @@ def sort_variants() -> list:
 
 
 def sort_autotune(keys, reps: int = 3, stream=None):
-    """Time every sort shape on `keys` and make the fastest the default.
-    Returns (chosen index, ms per shape)."""
+    """Time every sort shape on `keys` and record the fastest in the autotune
+    table for sorts of this size class on this device. Returns (chosen index,
+    ms per shape)."""
     n = keys.numel()
     _dev(keys, torch.int64)
     out = torch.empty_like(keys)
@@ -392,6 +399,34 @@ def sort_autotune(keys, reps: int = 3, stream=None):
     _check(_lib.cstone_sort_autotune(_ptr(keys), n, _ptr(out), _ptr(perm), _ptr(ws), ws.numel(), int(reps), ms,
                                      ctypes.byref(chosen), _stream(stream)), "cstone_sort_autotune")
     return chosen.value, list(ms)
+
+
+TUNE_SORT, TUNE_BATCH_SORT = 0, 1
+
+
+def tune_set(kernel: int, n: int, variant: int):
+    """Record `variant` for (kernel, size class of n, current device); -1 removes the entry."""
+    _check(_lib.cstone_tune_set(int(kernel), int(n), int(variant)), "cstone_tune_set")
+
+
+def tune_get(kernel: int, n: int) -> int:
+    return int(_lib.cstone_tune_get(int(kernel), int(n)))
+
+
+def tune_clear():
+    _lib.cstone_tune_clear()
+
+
+def tune_entries() -> int:
+    return int(_lib.cstone_tune_entries())
+
+
+def tune_save(path: str):
+    _check(_lib.cstone_tune_save(os.fsencode(path)), "cstone_tune_save")
+
+
+def tune_load(path: str):
+    _check(_lib.cstone_tune_load(os.fsencode(path)), "cstone_tune_load")
 
 
 # ---- batched builds -------------------------------------------------------------------
@@ -493,7 +528,8 @@ class Batch:
         _check(_lib.cstone_batch_launch(self._plan, _stream(stream)), "cstone_batch_launch")
 
     def autotune(self, x, y, z, reps: int = 3, stream=None):
-        """Time every sort shape on this batch and keep the fastest; returns ms per shape."""
+        """Time every sort shape on this batch, keep the fastest (also recorded
+        in the autotune table for batches of this size); returns ms per shape."""
         nv = _lib.cstone_sort_variant_count()
         ms = (ctypes.c_float * nv)()
         _check(_lib.cstone_batch_autotune(self._plan, *self._args(x, y, z), int(reps), ms, _stream(stream)),

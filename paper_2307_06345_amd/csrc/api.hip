@@ -129,13 +129,16 @@ cstone_status cstone_build(const double* x, const double* y, const double* z, si
     uint64_t* keys = c.take<uint64_t>(n);
     uint32_t* flag = c.take<uint32_t>(1);
     uint32_t* level6_table = c.take<uint32_t>(kLevel6Cells);
-    uint32_t* level6 = n && sort_uses_split(n, 63, true) ? level6_table : nullptr;
+    // the sort shape is looked up once: the key kernel's digit counts, the
+    // sort's set-up and its passes must all use the same one
+    const int variant = sort_resolve_variant(n);
+    uint32_t* level6 = n && sort_uses_split(n, 63, true, variant) ? level6_table : nullptr;
     void* stage_ws = static_cast<char*>(ws) + c.off;
     const size_t stage_bytes = ws_bytes - c.off;
 
     hipEvent_t ev[5] = {};
     hipEvent_t pass_ev[9] = {};
-    const int passes = sort_passes(n, 63, true);
+    const int passes = sort_passes(n, 63, true, variant);
     const bool timed = timings != nullptr;
     auto cleanup = [&]() {
         for (auto& e : ev)
@@ -161,12 +164,12 @@ cstone_status cstone_build(const double* x, const double* y, const double* z, si
         // them, writes the flag word and clears what the passes need cleared.
         if (n) {
             uint32_t *hist_parts = nullptr, *bad_parts = nullptr, hist_mask = 0, hist_shift = 0, parts = 0;
-            sort_key_parts(stage_ws, n, true, 63, &hist_parts, &bad_parts, &hist_mask, &hist_shift);
+            sort_key_parts(stage_ws, n, true, 63, variant, &hist_parts, &bad_parts, &hist_mask, &hist_shift);
             s = launch_keys(x, y, z, n, *box, curve, keys, nullptr, stream, hist_parts, hist_mask, hist_shift,
                             bad_parts, &parts);
             if (s != CSTONE_OK) break;
             if (mark(1) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
-            if ((s = sort_setup_from_keys(stage_ws, n, true, parts, flag, level6, stream)) != CSTONE_OK) break;
+            if ((s = sort_setup_from_keys(stage_ws, n, true, variant, parts, flag, level6, stream)) != CSTONE_OK) break;
         } else {
             hipLaunchKernelGGL(clear_word_kernel, dim3(1), dim3(1), 0, stream, flag);
             if (mark(1) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
@@ -174,7 +177,7 @@ cstone_status cstone_build(const double* x, const double* y, const double* z, si
         // the sort reports a failed device-side wait into the same flag word,
         // and (split sort) hands the level-6 node positions to the loop's start
         s = launch_sort(keys, sorted_keys, perm, n, 63, stage_ws, stage_bytes, stream,
-                        timed && n ? pass_ev : nullptr, /*prepared=*/true, -1, flag, level6);
+                        timed && n ? pass_ev : nullptr, /*prepared=*/true, variant, flag, level6);
         if (s != CSTONE_OK) break;
         if (mark(2) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
         if (nl == 0) nl = 1;  // start from the root leaf {0, 8^L}

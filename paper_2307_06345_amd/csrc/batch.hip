@@ -223,7 +223,10 @@ CSTONE_API cstone_status cstone_batch_create(const cstone_set* sets, uint32_t n_
     p->split_capacity = splits + 1;
     for (int v = 0; v < cs::sort_variant_count(); ++v)
         p->max_tiles = std::max<uint64_t>(p->max_tiles, cs::tiles_for(*p, v));
-    p->variant = cs::sort_default_variant();
+    {  // the autotune table's shape for a batch of this many keys, else the built-in one
+        const int tuned = cs::tune_lookup(cs::kTuneBatchSort, p->n_total);
+        p->variant = tuned >= 0 ? tuned : cs::sort_builtin_variant();
+    }
     cs::make_tiles(*p);
     *plan = p;
     return CSTONE_OK;
@@ -371,6 +374,7 @@ CSTONE_API cstone_status cstone_batch_autotune(cstone_batch* p, const double* x,
     (void)hipEventDestroy(e1);
     if (st != CSTONE_OK) return st;
     if ((st = cstone_batch_set_variant(p, best)) != CSTONE_OK) return st;
+    cs::tune_record(cs::kTuneBatchSort, p->n_total, best);  // later plans of this size class start from it
     return cstone_batch_upload(p, ws, ws_bytes, stream);
 }
 
@@ -418,7 +422,7 @@ CSTONE_API cstone_status cstone_sort_autotune(const uint64_t* keys_in, size_t n,
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != CSTONE_OK) return st;
-    cs::sort_set_tuned_variant(best);
+    cs::tune_record(cs::kTuneSort, n, best);
     if (chosen) *chosen = best;
     return CSTONE_OK;
 }

@@ -36,25 +36,29 @@ size_t sort_workspace_bytes(size_t n, bool with_perm);
 // overflow), all above the public CSTONE_FLAG_* bits.
 // level6: NULL, or kLevel6Cells words set to kCellEmpty by the set-up; the
 // split sort stores there the first position of every non-empty level-6 node.
+// variant: the sort shape (sort_variant_count() of them); -1 takes the shape
+// of the autotune table for a particle-key sort of n keys (with perm, 63
+// bits), else the built-in one. A prepared sort must name the shape its
+// set-up used.
 cstone_status launch_sort(const uint64_t* keys_in, uint64_t* keys_out, uint32_t* perm_out, size_t n,
                           int sig_bits, void* ws, size_t ws_bytes, hipStream_t stream,
                           hipEvent_t* pass_events = nullptr, bool prepared = false, int variant = -1,
                           uint32_t* err_word = nullptr, uint32_t* level6 = nullptr);
-bool sort_uses_split(size_t n, int sig_bits, bool with_perm);
+bool sort_uses_split(size_t n, int sig_bits, bool with_perm, int variant);
 // clear_word: NULL, or one caller word zeroed by the same launch; variant: the
-// sort shape the passes will use (-1: the default)
-cstone_status sort_prepare(void* ws, size_t n, bool with_perm, hipStream_t stream, uint32_t* clear_word = nullptr,
-                           int variant = -1);
+// sort shape the passes will use
+cstone_status sort_prepare(void* ws, size_t n, bool with_perm, hipStream_t stream, uint32_t* clear_word,
+                           int variant);
 // Per-block first-digit counts and non-finite flags of the key kernel, in the
 // sort workspace: where to store them and which digit to count.
-void sort_key_parts(void* ws, size_t n, bool with_perm, int sig_bits, uint32_t** hist_parts, uint32_t** bad_parts,
-                    uint32_t* mask, uint32_t* shift);
+void sort_key_parts(void* ws, size_t n, bool with_perm, int sig_bits, int variant, uint32_t** hist_parts,
+                    uint32_t** bad_parts, uint32_t* mask, uint32_t* shift);
 // Set-up after the key kernel stored its parts (replaces sort_prepare in a
 // build): the first digit's counts are the sum of the `parts` rows, *flag the
 // OR of the blocks' flags, and everything sort_prepare clears is cleared.
-cstone_status sort_setup_from_keys(void* ws, size_t n, bool with_perm, uint32_t parts, uint32_t* flag,
+cstone_status sort_setup_from_keys(void* ws, size_t n, bool with_perm, int variant, uint32_t parts, uint32_t* flag,
                                    uint32_t* level6, hipStream_t stream);
-int sort_passes(size_t n, int sig_bits, bool with_perm);
+int sort_passes(size_t n, int sig_bits, bool with_perm, int variant);
 
 // ---- batched builds: many independent sets in one pass of every stage -------
 
@@ -96,8 +100,15 @@ struct SortVariantInfo {
 };
 int sort_variant_count();
 SortVariantInfo sort_variant_info(int variant);
-int sort_default_variant();
-void sort_set_tuned_variant(int variant);  // -1: back to the built-in default
+int sort_builtin_variant();  // the shape used where the autotune table has no entry
+
+// tune.hip — the autotune table: (kernel, floor(log2 n), device) -> shape
+constexpr int kTuneSort = 0;       // particle-key sort of cstone_sort / cstone_build
+constexpr int kTuneBatchSort = 1;  // segmented sort of a batch (n: all its keys)
+constexpr int kTuneKernels = 2;
+int tune_lookup(int kernel, size_t n);  // -1: no entry for the current device
+void tune_record(int kernel, size_t n, int variant);
+int sort_resolve_variant(size_t n);  // particle-key sort of n keys: the table's shape, else the built-in one
 size_t sort_seg_workspace_bytes(size_t n_total, size_t n_tiles, uint32_t n_sets, int variant);
 cstone_status sort_seg_prepare(void* ws, size_t n_total, size_t n_tiles, uint32_t n_sets, int variant,
                                hipStream_t stream);

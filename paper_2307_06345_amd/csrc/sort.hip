@@ -11,8 +11,6 @@
 // pass's digit, so only the first digit needs a histogram of its own (which the
 // key kernel of a build provides while writing the keys).
 #include <algorithm>
-#include <atomic>
-#include <cstdlib>
 
 #include "common.hpp"
 #include "internal.hpp"
@@ -1084,29 +1082,21 @@ struct Variant {
 
 #define CS_VARIANT(B, BL, IT, WI, XG) \
     {B, BL, IT, WI, XG, launch_pass_t<B, BL, IT, WI, XG>, launch_seg_t<B, BL, IT, WI, XG>, launch_list_t<B, BL, IT, WI, XG>}
+// Shapes: digit bits, block, keys per thread, look-back window, XCD grouping.
+// A block needs at least one thread per digit, so 256-thread blocks take
+// 8-bit digits; 1024-thread blocks hold one block per CU.
 const Variant kVariants[] = {
-    CS_VARIANT(9, 512, 16, 4, 8), CS_VARIANT(9, 512, 16, 4, 1), CS_VARIANT(8, 512, 16, 4, 8),
-    CS_VARIANT(9, 512, 12, 4, 8), CS_VARIANT(9, 512, 32, 4, 8), CS_VARIANT(8, 512, 16, 4, 1),
-    CS_VARIANT(9, 512, 12, 4, 1), CS_VARIANT(9, 512, 32, 4, 1),
+    CS_VARIANT(9, 512, 16, 4, 8),  CS_VARIANT(9, 512, 16, 4, 1), CS_VARIANT(8, 512, 16, 4, 8),
+    CS_VARIANT(9, 512, 12, 4, 8),  CS_VARIANT(9, 512, 32, 4, 8), CS_VARIANT(8, 512, 16, 4, 1),
+    CS_VARIANT(9, 512, 12, 4, 1),  CS_VARIANT(9, 512, 32, 4, 1), CS_VARIANT(9, 1024, 8, 4, 8),
+    CS_VARIANT(9, 1024, 16, 4, 8), CS_VARIANT(8, 256, 16, 4, 8),
 };
 #undef CS_VARIANT
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
-int builtin_variant() {
-    static const int v = [] {
-        const char* e = std::getenv("CSTONE_SORT_VARIANT");
-        int x = e ? std::atoi(e) : 0;  // 9-bit digits, 512 x 16 tiles, 8 tiles in a row per XCD
-        return (x >= 0 && x < kNumVariants) ? x : 0;
-    }();
-    return v;
-}
-
-std::atomic<int> g_tuned_variant{-1};  // set by the autotuner
-
-int default_variant() {
-    const int t = g_tuned_variant.load(std::memory_order_relaxed);
-    return t >= 0 ? t : builtin_variant();
-}
+// Shape used where the autotune table has no entry: 9-bit digits, 512 x 16
+// tiles, 8 tiles in a row per XCD.
+constexpr int kBuiltinVariant = 0;
 
 // Split sorts of particle keys: 9-bit digits, the top three first (the
 // level-9 octant), then four low passes for the listed buckets
@@ -1165,25 +1155,23 @@ SortWs carve_sort(void* ws, size_t n, bool with_perm) {
     return s;
 }
 
-bool split_enabled() {
-    static const bool on = [] {
-        const char* e = std::getenv("CSTONE_SORT_SPLIT");
-        return !(e && e[0] == '0');
-    }();
-    return on;
-}
-
 // Whether a sort of n particle keys takes the split path.
 bool use_split(size_t n, int sig_bits, bool with_perm, const Variant& var) {
-    return split_enabled() && with_perm && sig_bits == 63 && var.bits == kSplitBits && n > 0;
+    return with_perm && sig_bits == 63 && var.bits == kSplitBits && n > 0;
 }
 
 }  // namespace
 
 size_t sort_workspace_bytes(size_t n, bool with_perm) { return carve_sort(nullptr, n, with_perm).bytes; }
 
-int sort_passes(size_t n, int sig_bits, bool with_perm) {
-    const Variant& var = kVariants[default_variant()];
+int sort_builtin_variant() { return kBuiltinVariant; }
+
+namespace {
+const Variant& variant_or_builtin(int v) { return kVariants[v >= 0 && v < kNumVariants ? v : kBuiltinVariant]; }
+}  // namespace
+
+int sort_passes(size_t n, int sig_bits, bool with_perm, int variant) {
+    const Variant& var = variant_or_builtin(variant);
     if (use_split(n, sig_bits, with_perm, var)) return 4;  // top pass 1, the later top passes, buckets, low passes
     return (sig_bits + var.bits - 1) / var.bits;
 }
@@ -1193,7 +1181,7 @@ cstone_status sort_prepare(void* ws, size_t n, bool with_perm, hipStream_t strea
     SortWs s = carve_sort(ws, n, with_perm);
     // only the first pass's look-back rows need clearing: each pass clears the
     // rows of the next (32-bit words), or words carry the pass's epoch (64-bit)
-    const Variant& var = kVariants[variant >= 0 && variant < kNumVariants ? variant : default_variant()];
+    const Variant& var = variant_or_builtin(variant);
     const size_t tile = static_cast<size_t>(var.block) * var.items;
     const size_t words = ((n + tile - 1) / tile) << var.bits;
     const bool wide = n >= (1ull << 30);
@@ -1205,9 +1193,9 @@ cstone_status sort_prepare(void* ws, size_t n, bool with_perm, hipStream_t strea
     return CSTONE_OK;
 }
 
-void sort_key_parts(void* ws, size_t n, bool with_perm, int sig_bits, uint32_t** hist_parts, uint32_t** bad_parts,
-                    uint32_t* mask, uint32_t* shift) {
-    const Variant& var = kVariants[default_variant()];
+void sort_key_parts(void* ws, size_t n, bool with_perm, int sig_bits, int variant, uint32_t** hist_parts,
+                    uint32_t** bad_parts, uint32_t* mask, uint32_t* shift) {
+    const Variant& var = variant_or_builtin(variant);
     *mask = (1u << var.bits) - 1u;
     *shift = use_split(n, sig_bits, with_perm, var) ? kSplitShift : 0u;
     const SortWs s = carve_sort(ws, n, with_perm);
@@ -1215,11 +1203,12 @@ void sort_key_parts(void* ws, size_t n, bool with_perm, int sig_bits, uint32_t**
     *bad_parts = s.key_bad;
 }
 
-cstone_status sort_setup_from_keys(void* ws, size_t n, bool with_perm, uint32_t parts, uint32_t* flag,
+cstone_status sort_setup_from_keys(void* ws, size_t n, bool with_perm, int variant, uint32_t parts, uint32_t* flag,
                                    uint32_t* level6, hipStream_t stream) {
     if (!with_perm || parts == 0 || parts > kKeyBlocksMax) return CSTONE_ERR_INVALID_ARG;
+    if (variant < 0 || variant >= kNumVariants) return CSTONE_ERR_INVALID_ARG;
     SortWs s = carve_sort(ws, n, with_perm);
-    const Variant& var = kVariants[default_variant()];
+    const Variant& var = kVariants[variant];
     const size_t tile = static_cast<size_t>(var.block) * var.items;
     const size_t words = ((n + tile - 1) / tile) << var.bits;
     const bool wide = n >= (1ull << 30);
@@ -1232,8 +1221,8 @@ cstone_status sort_setup_from_keys(void* ws, size_t n, bool with_perm, uint32_t 
     return CSTONE_OK;
 }
 
-bool sort_uses_split(size_t n, int sig_bits, bool with_perm) {
-    return use_split(n, sig_bits, with_perm, kVariants[default_variant()]);
+bool sort_uses_split(size_t n, int sig_bits, bool with_perm, int variant) {
+    return use_split(n, sig_bits, with_perm, variant_or_builtin(variant));
 }
 
 namespace {
@@ -1332,8 +1321,9 @@ cstone_status launch_sort(const uint64_t* keys_in, uint64_t* keys_out, uint32_t*
     if (n == 0) return CSTONE_OK;
     if (n > 0xffffffffull) return CSTONE_ERR_INVALID_ARG;
     if (variant >= kNumVariants) return CSTONE_ERR_INVALID_ARG;
-    if (prepared && variant >= 0 && variant != default_variant()) return CSTONE_ERR_INVALID_ARG;
-    const Variant& var = kVariants[variant >= 0 ? variant : default_variant()];
+    if (prepared && variant < 0) return CSTONE_ERR_INVALID_ARG;  // the set-up fixed the shape
+    if (variant < 0) variant = with_perm && sig_bits == 63 ? sort_resolve_variant(n) : kBuiltinVariant;
+    const Variant& var = kVariants[variant];
     const int radix = 1 << var.bits;
     const int passes = (sig_bits + var.bits - 1) / var.bits;
     if (passes < 1 || passes > kMaxPasses) return CSTONE_ERR_INVALID_ARG;
@@ -1395,9 +1385,6 @@ SortVariantInfo sort_variant_info(int v) {
     return {x.bits, x.block, x.items, x.block * x.items};
 }
 
-int sort_default_variant() { return default_variant(); }
-
-void sort_set_tuned_variant(int v) { g_tuned_variant.store((v >= 0 && v < kNumVariants) ? v : -1); }
 
 namespace {
 
@@ -1421,7 +1408,7 @@ struct SegWs {
     size_t bytes;
 };
 
-bool seg_split(int variant) { return split_enabled() && kVariants[variant].bits == kSplitBits; }
+bool seg_split(int variant) { return kVariants[variant].bits == kSplitBits; }
 
 SegWs carve_seg(void* ws, size_t n_total, size_t n_tiles, uint32_t n_sets, int variant) {
     const Variant& var = kVariants[variant];

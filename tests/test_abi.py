@@ -117,3 +117,54 @@ def test_batch_plan_rejects_bad_sets():
         st, plan = _plan(cs, [bad])
         assert st == 1 and not plan.value, bad
     assert cs._lib.cstone_batch_launch(None, None) == 1
+
+
+def test_tune_table_round_trips_through_its_json_file(tmp_path):
+    """The autotune table: set, look up, save as JSON, clear, load back. Host
+    only (without a GPU the device key is "unknown", the same on both sides)."""
+    import json
+
+    import paper_2307_06345_amd as cs
+    nv = len(cs.sort_variants())
+    cs.tune_clear()
+    try:
+        cs.tune_set(cs.TUNE_SORT, 1 << 24, nv - 1)
+        cs.tune_set(cs.TUNE_BATCH_SORT, 77_000_000, 1)
+        cs.tune_set(cs.TUNE_SORT, (1 << 25) - 1, 2)  # same size class as 2^24: replaces the entry
+        assert cs.tune_entries() == 2
+        assert cs.tune_get(cs.TUNE_SORT, 1 << 24) == 2
+        assert cs.tune_get(cs.TUNE_SORT, 1 << 25) == -1
+        assert cs.tune_get(cs.TUNE_BATCH_SORT, 70_000_000) == 1
+        path = str(tmp_path / "tune.json")
+        cs.tune_save(path)
+        doc = json.load(open(path))
+        assert doc["format"] == "cstone-tune-1" and len(doc["entries"]) == 2
+        e = {x["kernel"]: x for x in doc["entries"]}
+        assert e["sort"]["size_log2"] == 24 and e["sort"]["variant"] == 2
+        assert (e["sort"]["digit_bits"], e["sort"]["block"], e["sort"]["items"]) == cs.sort_variants()[2]
+        assert e["batch_sort"]["size_log2"] == 26
+        cs.tune_clear()
+        assert cs.tune_entries() == 0 and cs.tune_get(cs.TUNE_SORT, 1 << 24) == -1
+        cs.tune_load(path)
+        assert cs.tune_entries() == 2
+        assert cs.tune_get(cs.TUNE_SORT, 1 << 24) == 2 and cs.tune_get(cs.TUNE_BATCH_SORT, 1 << 26) == 1
+        cs.tune_set(cs.TUNE_SORT, 1 << 24, -1)  # removes the entry
+        assert cs.tune_entries() == 1 and cs.tune_get(cs.TUNE_SORT, 1 << 24) == -1
+        # an entry naming a shape this library does not have under that index is skipped
+        doc["entries"][0]["block"] = 12345
+        with open(path, "w") as f:
+            f.write('{"format": "cstone-tune-1", "entries": [\n')
+            f.write(",\n".join(json.dumps(x) for x in doc["entries"]) + "\n]}\n")
+        cs.tune_clear()
+        cs.tune_load(path)
+        assert cs.tune_entries() == 1
+        # a file in another format is refused and leaves the table unchanged
+        bad = tmp_path / "bad.json"
+        bad.write_text('{"entries": []}\n')
+        with pytest.raises(cs.CstoneError):
+            cs.tune_load(str(bad))
+        assert cs.tune_entries() == 1
+        with pytest.raises(cs.CstoneError):
+            cs.tune_set(cs.TUNE_SORT, 10, nv)
+    finally:
+        cs.tune_clear()

@@ -351,19 +351,38 @@ def test_build_uniform_2_24_full_parity():
 
 
 def test_sort_autotune_keeps_the_sort_exact():
-    """The shape autotuner times every compiled sort shape and makes the fastest
-    the default; whichever it picks, the sort stays bit-exact."""
+    """The shape autotuner times every compiled sort shape and records the
+    fastest for this size class; every shape, set through the autotune table,
+    sorts bit-exactly, and so does a plain build that looks the shape up."""
     s = wl.make_set("plummer", 300001, 41, 0, wl.HILBERT, 16)
     keys, _ = oracle.compute_keys(s.x, s.y, s.z, s.box, s.curve)
     ref_P, ref_perm = oracle.sort(keys)
-    say("sort autotune", len(cs.sort_variants()), "shapes")
-    chosen, ms = cs.sort_autotune(dev(keys), reps=1)
-    assert 0 <= chosen < len(cs.sort_variants()) and len(ms) == len(cs.sort_variants())
-    assert all(t > 0 for t in ms) and ms[chosen] == min(ms)
-    P, perm = cs.sort(dev(keys))
-    torch.cuda.synchronize()
-    eq(host(P), ref_P, "tuned sort P")
-    eq(host(perm), ref_perm, "tuned sort perm")
+    nv = len(cs.sort_variants())
+    cs.tune_clear()
+    try:
+        for v in range(nv):
+            say("sort with shape", v, cs.sort_variants()[v])
+            cs.tune_set(cs.TUNE_SORT, s.n, v)
+            assert cs.tune_get(cs.TUNE_SORT, s.n) == v
+            P, perm = cs.sort(dev(keys))
+            torch.cuda.synchronize()
+            eq(host(P), ref_P, f"shape {v} P")
+            eq(host(perm), ref_perm, f"shape {v} perm")
+        cs.tune_clear()
+        say("sort autotune", nv, "shapes")
+        chosen, ms = cs.sort_autotune(dev(keys), reps=1)
+        assert 0 <= chosen < nv and len(ms) == nv
+        assert all(t > 0 for t in ms) and ms[chosen] == min(ms)
+        assert cs.tune_entries() == 1 and cs.tune_get(cs.TUNE_SORT, s.n) == chosen
+        assert cs.tune_get(cs.TUNE_SORT, 4 * s.n) == -1  # another size class keeps the built-in shape
+        P, perm = cs.sort(dev(keys))
+        torch.cuda.synchronize()
+        eq(host(P), ref_P, "tuned sort P")
+        eq(host(perm), ref_perm, "tuned sort perm")
+        r = cs.build(*coords(s), s.box, s.curve, s.n_crit)
+        _check_build(s, r, "build with the tuned shape")
+    finally:
+        cs.tune_clear()
 
 
 @pytest.mark.slow
