@@ -62,6 +62,13 @@ def _load():
         "oracle_node_count": (u64, [u64]),
         "oracle_link_octree": (u64, [P, u64, P, P, P]),
         "oracle_build": (u64, [P, P, P, u64, P, P, i32, u32, P, P, P, u64, P]),
+        "oracle_octree_node_counts": (None, [P, u64, P, u64, P]),
+        "oracle_sfc_partition": (None, [P, u64, u32, P]),
+        "oracle_mac_fails": (i32, [u64, i32, i32, u64, u64, ctypes.c_double]),
+        "oracle_node_box": (None, [u64, i32, i32, P, P]),
+        "oracle_focus_leaves": (u64, [P, u64, u32, i32, u64, u64, ctypes.c_double, P, u64]),
+        "oracle_focus_rebalance_step": (i32, [P, u64, P, u32, i32, u64, u64, ctypes.c_double, P, u64, P]),
+        "oracle_radix_nodes": (None, [P, u64, P, P, P]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -208,3 +215,121 @@ def build_tree(x, y, z, box, curve=HILBERT, n_crit=64):
     counts = node_counts(P, K)
     NK, CO, LO = link_octree(K)
     return dict(keys=keys, nonfinite=nonfinite, P=P, perm=perm, K=K, counts=counts, NK=NK, CO=CO, LO=LO)
+
+
+# ---- beyond the build: node properties, decomposition, focused tree ---------
+
+
+def octree_node_counts(P, NK):
+    """Particle count of every node of a linked octree (Sec. 5 node
+    properties): keys of P inside each node's range, by Eq. histogram."""
+    P, NK = _u64(P), _u64(NK)
+    out = np.empty(NK.size, np.uint32)
+    _load().oracle_octree_node_counts(_ptr(P), P.size, _ptr(NK), NK.size, _ptr(out))
+    return out
+
+
+def gather(a, perm):
+    """Particle property in SFC order: out[i] = a[perm[i]] (Sec. 4, the
+    permutation that sorts the keys applied to the particle arrays)."""
+    return np.ascontiguousarray(a)[np.asarray(perm).astype(np.int64)]
+
+
+def sfc_partition(counts, n_ranks: int):
+    """Sec. 6: bounds (uint32[n_ranks + 1]) of n_ranks bins of consecutive
+    leaves, bin r = leaves [bounds[r], bounds[r + 1])."""
+    counts = np.ascontiguousarray(counts, dtype=np.uint32)
+    out = np.empty(int(n_ranks) + 1, np.uint32)
+    _load().oracle_sfc_partition(_ptr(counts), counts.size, int(n_ranks), _ptr(out))
+    return out
+
+
+def global_rebalance(P_parts, n_crit: int, K=None, max_iters: int = L + 1):
+    """Sec. 6: the replicated tree of particles spread over several shards,
+    each holding its own sorted keys. Every round computes f on every shard,
+    sums the count arrays element-wise (f_r, the global reduction) and applies
+    g to the summed counts; from the root unless K is given. Returns (K,
+    summed counts, rounds, converged)."""
+    K = np.array([0, ROOT_END], np.uint64) if K is None else _u64(K)
+    for r in range(1, max_iters + 1):
+        N = np.zeros(K.size - 1, np.uint64)
+        for Pg in P_parts:
+            N += node_counts(Pg, K)
+        N = N.astype(np.uint32)
+        K2, changed = rebalance_step(K, N, n_crit)
+        if not changed:
+            Nf = np.zeros(K2.size - 1, np.uint64)
+            for Pg in P_parts:
+                Nf += node_counts(Pg, K2)
+            return K2, Nf.astype(np.uint32), r, True
+        K = K2
+    Nf = np.zeros(K.size - 1, np.uint64)
+    for Pg in P_parts:
+        Nf += node_counts(Pg, K)
+    return K, Nf.astype(np.uint32), max_iters, False
+
+
+def mac_fails(start: int, level: int, curve: int, fa: int, fb: int, theta: float) -> bool:
+    """Sec. 7.1 minimum-distance MAC of node (start, level) against F = [fa, fb)."""
+    return bool(_load().oracle_mac_fails(int(start), int(level), int(curve), int(fa), int(fb), float(theta)))
+
+
+def node_box(start: int, level: int, curve: int):
+    """(lower corner (3 ints), edge) of a node in grid cells."""
+    lo = np.zeros(3, np.uint32)
+    edge = np.zeros(1, np.uint32)
+    _load().oracle_node_box(int(start), int(level), int(curve), _ptr(lo), _ptr(edge))
+    return tuple(int(v) for v in lo), int(edge[0])
+
+
+def focus_leaves(P, n_crit: int, curve: int, fa: int, fb: int, theta: float):
+    """Sec. 7.1: the cornerstone array focused on F = [fa, fb), top-down."""
+    P = _u64(P)
+    lib = _load()
+    cap = 1024
+    while True:
+        K = np.empty(cap, np.uint64)
+        nl = lib.oracle_focus_leaves(_ptr(P), P.size, int(n_crit), int(curve), int(fa), int(fb), float(theta),
+                                     _ptr(K), cap)
+        if nl + 1 <= cap:
+            return K[: nl + 1].copy()
+        cap = int(nl) + 1
+
+
+def focus_rebalance_step(K, N, n_crit: int, curve: int, fa: int, fb: int, theta: float):
+    """One literal g^LE update (Sec. 7.2). Returns (K', changed)."""
+    K = _u64(K)
+    N = np.ascontiguousarray(N, dtype=np.uint32)
+    nl = K.size - 1
+    cap = 8 * nl + 1
+    out = np.empty(cap, np.uint64)
+    nl_out = ctypes.c_uint64(0)
+    changed = _load().oracle_focus_rebalance_step(_ptr(K), nl, _ptr(N), int(n_crit), int(curve), int(fa), int(fb),
+                                                  float(theta), _ptr(out), cap, ctypes.byref(nl_out))
+    return out[: nl_out.value + 1].copy(), bool(changed)
+
+
+def focus_iterate(P, n_crit: int, curve: int, fa: int, fb: int, theta: float, K=None, max_iters: int = L + 1):
+    """Alternate f and g^LE from K (default the root) until no leaf changes.
+    Returns (K, counts, rounds, converged, history)."""
+    K = np.array([0, ROOT_END], np.uint64) if K is None else _u64(K)
+    history = []
+    for r in range(1, max_iters + 1):
+        K2, changed = focus_rebalance_step(K, node_counts(P, K), n_crit, curve, fa, fb, theta)
+        history.append(K2)
+        if not changed:
+            return K2, node_counts(P, K2), r, True, history
+        K = K2
+    return K, node_counts(P, K), max_iters, False, history
+
+
+def radix_nodes(keys):
+    """Binary radix tree over sorted unique keys: per adjacent pair i, the
+    prefix length and key range [first, last] of the node that splits there."""
+    keys = _u64(keys)
+    m = keys.size
+    k = max(m - 1, 0)
+    pl, fi, la = (np.empty(k, np.uint32) for _ in range(3))
+    if k:
+        _load().oracle_radix_nodes(_ptr(keys), m, _ptr(pl), _ptr(fi), _ptr(la))
+    return pl, fi, la

@@ -28,6 +28,18 @@
 //                       iteration to the top-down fixed point)
 //   link                pinned (paper Fig. 2 level offsets, structural
 //                       characterisation of NK / CO / LO)
+//   octree node counts  pinned (root = N, children sum to their parent,
+//                       leaves equal Eq. histogram, brute-force count)
+//   SFC partition       pinned (brute-force search of the defining minimum,
+//                       balance within one leaf's count, equal-count cases)
+//   focus MAC           pinned (brute force over F's cells at a coarse
+//                       level, translation and reflection cases, overlap)
+//   focused leaves      pinned (theta = 0 and F = whole domain reduce to the
+//                       balanced tree; Sec. 7.1 definition checked leaf by
+//                       leaf; the literal g^LE iteration reaches it)
+//   radix nodes         pinned (brute force over all key pairs; ranges nest
+//                       and every key has one parent; the nodes with prefix
+//                       length 3 l are exactly the internal octree nodes)
 //
 // Build: g++ -O2 -std=c++17 -ffp-contract=off -shared -fPIC (no fast-math).
 
@@ -162,6 +174,99 @@ void split_node(const uint64_t* P, uint64_t n, uint32_t n_crit, uint64_t start, 
     uint64_t count = lower_bound_pos(P, n, end) - lower_bound_pos(P, n, start);
     if (count > n_crit && level < kL) {
         for (uint64_t j = 0; j < 8; ++j) split_node(P, n, n_crit, start + j * pow8(kL - level - 1), level + 1, K);
+    } else {
+        K.push_back(start);
+    }
+}
+
+
+// ---- Node geometry (used by the focus-tree MAC, Sec. 7) --------------------
+
+// Inverse of morton(): bit 3b+2 of the key is bit b of x, 3b+1 of y, 3b of z.
+void morton_decode(uint64_t key, uint32_t out[3]) {
+    out[0] = out[1] = out[2] = 0;
+    for (int b = 0; b < kL; ++b) {
+        out[0] |= static_cast<uint32_t>((key >> (3 * b + 2)) & 1u) << b;
+        out[1] |= static_cast<uint32_t>((key >> (3 * b + 1)) & 1u) << b;
+        out[2] |= static_cast<uint32_t>((key >> (3 * b)) & 1u) << b;
+    }
+}
+
+// Grid box of the node whose key range starts at `start` on `level`: an
+// aligned block of 8^(L - level) keys is an aligned cube of edge
+// 2^(L - level) grid cells (Sec. 3), so its lower corner is any of its cells'
+// coordinates with the low L - level bits cleared.
+void node_box(uint64_t start, int level, int curve, uint32_t lo[3], uint32_t* edge) {
+    uint32_t c[3];
+    if (curve == 0)
+        morton_decode(start, c);
+    else
+        hilbert_decode(start, kL, c);
+    const uint32_t side = 1u << (kL - level);
+    for (int d = 0; d < 3; ++d) lo[d] = c[d] & ~(side - 1u);
+    *edge = side;
+}
+
+// Squared distance between two closed axis-aligned boxes of the grid (0 if
+// they touch or overlap), exact in integers.
+uint64_t box_dist2(const uint32_t a[3], uint32_t ea, const uint32_t b[3], uint32_t eb) {
+    uint64_t r2 = 0;
+    for (int d = 0; d < 3; ++d) {
+        int64_t gap = 0;
+        const int64_t a0 = a[d], a1 = static_cast<int64_t>(a[d]) + ea;
+        const int64_t b0 = b[d], b1 = static_cast<int64_t>(b[d]) + eb;
+        if (b0 > a1) gap = b0 - a1;
+        if (a0 > b1) gap = a0 - b1;
+        r2 += static_cast<uint64_t>(gap * gap);
+    }
+    return r2;
+}
+
+// The SFC range [fa, fb) as maximal aligned key blocks (start, level), left to
+// right: at each position the largest block 8^e that starts there and ends
+// by fb.
+std::vector<std::pair<uint64_t, int>> range_blocks(uint64_t fa, uint64_t fb) {
+    std::vector<std::pair<uint64_t, int>> out;
+    uint64_t k = fa;
+    while (k < fb) {
+        int e = kL;
+        while (e > 0 && (k % pow8(e) != 0 || fb - k < pow8(e))) --e;
+        out.push_back({k, kL - e});
+        k += pow8(e);
+    }
+    return out;
+}
+
+// Minimum-distance MAC (Sec. 7.1) of the node (start, level) against the focus
+// range F = [fa, fb): it fails if some point of F is at distance r_min <= l /
+// theta from the node, l the node's edge. In squares: fails iff
+// r_min^2 * theta^2 <= l^2, with r_min^2 exact and theta^2 = theta * theta, one
+// IEEE double rounding each. With no point in F (fa == fb) it never fails.
+bool mac_fails(uint64_t start, int level, int curve, const std::vector<std::pair<uint64_t, int>>& F,
+               double theta) {
+    uint32_t lo[3], edge;
+    node_box(start, level, curve, lo, &edge);
+    const double theta2 = theta * theta;
+    const double l2 = static_cast<double>(edge) * static_cast<double>(edge);
+    for (const auto& blk : F) {
+        uint32_t flo[3], fe;
+        node_box(blk.first, blk.second, curve, flo, &fe);
+        const uint64_t r2 = box_dist2(lo, edge, flo, fe);
+        if (!(static_cast<double>(r2) * theta2 > l2)) return true;
+    }
+    return false;
+}
+
+// Top-down reference of the focused tree (Sec. 7.1 definition): a node is
+// split iff it holds more than n_crit particles, is above level L and fails
+// the MAC against F (every node that overlaps F fails it, r_min being 0).
+void split_focus(const uint64_t* P, uint64_t n, uint32_t n_crit, uint64_t start, int level, int curve,
+                 const std::vector<std::pair<uint64_t, int>>& F, double theta, std::vector<uint64_t>& K) {
+    uint64_t end = start + pow8(kL - level);
+    uint64_t count = lower_bound_pos(P, n, end) - lower_bound_pos(P, n, start);
+    if (count > n_crit && level < kL && mac_fails(start, level, curve, F, theta)) {
+        for (uint64_t j = 0; j < 8; ++j)
+            split_focus(P, n, n_crit, start + j * pow8(kL - level - 1), level + 1, curve, F, theta, K);
     } else {
         K.push_back(start);
     }
@@ -314,6 +419,135 @@ uint64_t oracle_link_octree(const uint64_t* K, uint64_t n_leaves, uint64_t* NK, 
         }
     }
     return n;
+}
+
+// ---- Node properties (Sec. 5: properties of all n nodes in separate arrays) --
+
+// Particle count of every node of a linked octree (NK in placeholder-bit
+// format): the number of keys of P inside the node's key range, i.e. Eq.
+// histogram applied to every node, leaves and internal nodes alike.
+void oracle_octree_node_counts(const uint64_t* P, uint64_t n, const uint64_t* NK, uint64_t n_nodes,
+                               uint32_t* counts) {
+    for (uint64_t p = 0; p < n_nodes; ++p) {
+        int level = 0;
+        while (level < kL && (NK[p] >> (3 * (level + 1))) != 0) ++level;  // the placeholder bit sits at 3 * level
+        const uint64_t start = (NK[p] ^ (1ull << (3 * level))) << (3 * (kL - level));
+        const uint64_t end = start + pow8(kL - level);
+        counts[p] = static_cast<uint32_t>(lower_bound_pos(P, n, end) - lower_bound_pos(P, n, start));
+    }
+}
+
+// ---- SFC domain decomposition (Sec. 6) ---------------------------------------
+
+// Group the n_l leaves into n_ranks bins of consecutive leaves holding about
+// N / n_ranks particles each. With C_i the number of particles in leaves
+// before leaf i (C_0 = 0, C_{n_l} = N), bin r starts at the first leaf
+// boundary at or past r N / n_ranks: bounds[r] = min { i : C_i * n_ranks >=
+// r * N }, so bounds[0] = 0 and bounds[n_ranks] = n_l (exact integers).
+void oracle_sfc_partition(const uint32_t* counts, uint64_t n_leaves, uint32_t n_ranks, uint32_t* bounds) {
+    std::vector<uint64_t> C(n_leaves + 1, 0);
+    for (uint64_t i = 0; i < n_leaves; ++i) C[i + 1] = C[i] + counts[i];
+    const uint64_t N = C[n_leaves];
+    for (uint32_t r = 0; r <= n_ranks; ++r) {
+        uint64_t i = 0;
+        while (i < n_leaves && C[i] * n_ranks < static_cast<uint64_t>(r) * N) ++i;
+        bounds[r] = static_cast<uint32_t>(r == n_ranks ? n_leaves : i);
+    }
+}
+
+// ---- Focused (locally essential) tree on one GPU's data (Sec. 7) --------------
+
+// Minimum-distance MAC of one node against the focus range [fa, fb); returns
+// 1 if it fails (the node must be resolved further for F), else 0.
+int oracle_mac_fails(uint64_t start, int level, int curve, uint64_t fa, uint64_t fb, double theta) {
+    return mac_fails(start, level, curve, range_blocks(fa, fb), theta) ? 1 : 0;
+}
+
+// Grid box (lower corner and edge) of the node (start, level).
+void oracle_node_box(uint64_t start, int level, int curve, uint32_t* lo3, uint32_t* edge) {
+    node_box(start, level, curve, lo3, edge);
+}
+
+// The focused cornerstone array by top-down recursion (split iff count >
+// n_crit, level < L and the MAC fails). Writes K if it fits in `capacity`
+// keys; returns n_l.
+uint64_t oracle_focus_leaves(const uint64_t* P, uint64_t n, uint32_t n_crit, int curve, uint64_t fa, uint64_t fb,
+                             double theta, uint64_t* K, uint64_t capacity) {
+    std::vector<uint64_t> leaves;
+    split_focus(P, n, n_crit, 0, 0, curve, range_blocks(fa, fb), theta, leaves);
+    leaves.push_back(kRootEnd);
+    if (leaves.size() <= capacity) std::memcpy(K, leaves.data(), leaves.size() * sizeof(uint64_t));
+    return leaves.size() - 1;
+}
+
+// One literal update g^LE = g3 . g2 . g^LE_1 (Sec. 7.2) of the focused array K
+// with leaf counts N. g^LE_1: split a leaf if it holds more than n_crit
+// particles, can be split and fails the MAC; merge a complete group of 8
+// sibling leaves if their parent holds at most n_crit particles or passes the
+// MAC; otherwise keep. Inside F (and wherever a node overlaps F) the MAC always
+// fails, so the rule there is g1's. Returns 1 if some O_i != 1.
+int oracle_focus_rebalance_step(const uint64_t* K, uint64_t n_leaves, const uint32_t* N, uint32_t n_crit, int curve,
+                                uint64_t fa, uint64_t fb, double theta, uint64_t* K_out, uint64_t capacity,
+                                uint64_t* n_leaves_out) {
+    const uint64_t nl = n_leaves;
+    const auto F = range_blocks(fa, fb);
+    std::vector<uint64_t> O(nl + 1, 0);
+    int changed = 0;
+    for (uint64_t i = 0; i < nl; ++i) {
+        const uint64_t delta = K[i + 1] - K[i];
+        const int level = level_of_span(delta);
+        uint64_t op = 1;
+        if (N[i] > n_crit && delta > 1 && mac_fails(K[i], level, curve, F, theta)) {
+            op = 8;
+        } else if (delta < kRootEnd) {  // reading R7: the root never merges
+            const uint64_t j = (K[i] % (8 * delta)) / delta;
+            if (j >= 1 && i >= j && i - j + 8 <= nl && K[i - j] + 8 * delta == K[i - j + 8]) {
+                uint64_t group = 0;
+                for (uint64_t m = 0; m < 8; ++m) group += N[i - j + m];
+                // reading R5 for "smaller than N_crit": the parent's count <= n_crit
+                if (group <= n_crit || !mac_fails(K[i - j], level - 1, curve, F, theta)) op = 0;
+            }
+        }
+        O[i] = op;
+        if (op != 1) changed = 1;
+    }
+    std::vector<uint64_t> Op(nl + 1, 0);
+    for (uint64_t i = 0; i < nl; ++i) Op[i + 1] = Op[i] + O[i];
+    const uint64_t nl_new = Op[nl];
+    *n_leaves_out = nl_new;
+    if (nl_new + 1 > capacity) return changed;
+    for (uint64_t i = 0; i < nl; ++i) {
+        const uint64_t delta = K[i + 1] - K[i];
+        if (O[i] == 1) {
+            K_out[Op[i]] = K[i];
+        } else if (O[i] == 8) {
+            for (uint64_t j = 0; j < 8; ++j) K_out[Op[i] + j] = K[i] + j * (delta / 8);
+        }
+    }
+    K_out[nl_new] = kRootEnd;
+    return changed;
+}
+
+// ---- Binary radix tree over sorted unique keys (Sec. 5, after Karras) --------
+
+// For m sorted unique keys k_0 < ... < k_{m-1} (63-bit), the binary radix tree
+// has one internal node per adjacent pair (i, i + 1): the node whose key
+// ranges split between them. Its prefix is the common prefix of k_i and
+// k_{i+1}, of prefix_len[i] = (leading zeros of k_i XOR k_{i+1}) - 1 bits
+// within the 63-bit key (reading R11). Its key range [first[i], last[i]] is
+// the maximal run of keys sharing that prefix. Found here by scanning outwards
+// from the pair, one key at a time.
+void oracle_radix_nodes(const uint64_t* k, uint64_t m, uint32_t* prefix_len, uint32_t* first, uint32_t* last) {
+    for (uint64_t i = 0; i + 1 < m; ++i) {
+        const int d = __builtin_clzll(k[i] ^ k[i + 1]) - 1;
+        prefix_len[i] = static_cast<uint32_t>(d);
+        const uint64_t pre = k[i] >> (63 - d);
+        uint64_t a = i, b = i + 1;
+        while (a > 0 && (k[a - 1] >> (63 - d)) == pre) --a;
+        while (b + 1 < m && (k[b + 1] >> (63 - d)) == pre) ++b;
+        first[i] = static_cast<uint32_t>(a);
+        last[i] = static_cast<uint32_t>(b);
+    }
 }
 
 // Convenience: the whole pipeline of Secs. 3-5 for one particle set.
