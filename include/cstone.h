@@ -218,6 +218,40 @@ CSTONE_API cstone_status cstone_build(const double* x, const double* y, const do
                            hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Node properties and particles in curve order (Sec. 5: properties of the n
+ * nodes kept in separate arrays of length n, filled after the build; Sec. 4:
+ * the permutation that sorts the keys, applied to the particle arrays).
+ *
+ * cstone_octree_node_counts: the particle count of every node of a linked
+ * octree, node_counts[p] = number of particles whose key lies in node p's key
+ * range. Leaves get their leaf count; an internal node the sum over its
+ * children, i.e. what an upward pass over the tree gives (the root holds
+ * the sum of all leaf counts).
+ *   leaves      device, n_leaves + 1 uint64, the cornerstone array K
+ *   counts      device, n_leaves uint32, its leaf counts (Eq. histogram)
+ *   node_keys   device, n_nodes uint64, NK of cstone_link_octree on K
+ *   node_counts device, n_nodes uint32 (output, same order as node_keys)
+ *   ws          device, cstone_octree_node_counts_workspace_bytes(n_leaves)
+ * Asynchronous. A node key that does not start at a leaf boundary of K (NK
+ * of another tree) gets 0xffffffff. Errors: INVALID_ARG.
+ *
+ * cstone_gather: dst[i] = src[perm[i]] for i < n (src, dst: device, n
+ * doubles, not aliasing; perm: device, a permutation of 0 .. n-1, e.g. from
+ * cstone_sort). cstone_gather_xyz does it for x, y, z: as three passes (one
+ * array's reads stay in the last-level cache for n up to 2^25) or, with
+ * fused != 0, one pass over all three. Asynchronous. Errors: INVALID_ARG.
+ */
+CSTONE_API size_t cstone_octree_node_counts_workspace_bytes(size_t n_leaves);
+CSTONE_API cstone_status cstone_octree_node_counts(const uint64_t* leaves, const uint32_t* counts, size_t n_leaves,
+                                                   const uint64_t* node_keys, size_t n_nodes, uint32_t* node_counts,
+                                                   void* ws, size_t ws_bytes, hipStream_t stream);
+CSTONE_API cstone_status cstone_gather(const double* src, const uint32_t* perm, size_t n, double* dst,
+                                       hipStream_t stream);
+CSTONE_API cstone_status cstone_gather_xyz(const double* x, const double* y, const double* z, const uint32_t* perm,
+                                           size_t n, double* ox, double* oy, double* oz, int fused,
+                                           hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Sort tile shapes and their autotune table. The radix sort has several
  * compiled shapes (digit width, block size, keys per thread). Which one a
  * sort runs is looked up once, when the sort (or build) starts, in a

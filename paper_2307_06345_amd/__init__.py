@@ -88,6 +88,10 @@ def _load() -> ctypes.CDLL:
         "cstone_sort_variant_info": (i32, [i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "cstone_sort_autotune": (i32, [P, sz, P, P, P, sz, i32, ctypes.POINTER(ctypes.c_float),
                                        ctypes.POINTER(i32), P]),
+        "cstone_octree_node_counts_workspace_bytes": (sz, [sz]),
+        "cstone_octree_node_counts": (i32, [P, P, sz, P, sz, P, P, sz, P]),
+        "cstone_gather": (i32, [P, P, sz, P, P]),
+        "cstone_gather_xyz": (i32, [P, P, P, P, sz, P, P, P, i32, P]),
         "cstone_tune_set": (i32, [i32, sz, i32]),
         "cstone_tune_get": (i32, [i32, sz]),
         "cstone_tune_clear": (None, []),
@@ -262,6 +266,42 @@ def link_octree(leaves, node_keys=None, child=None, level_offsets=None, ws=None,
     _check(fn(_ptr(leaves), nl, _ptr(node_keys), _ptr(child), _ptr(level_offsets), _ptr(ws), ws.numel(),
               _stream(stream)), "cstone_link_octree")
     return node_keys[:n], child[:n], level_offsets
+
+
+def octree_node_counts(leaves, counts, node_keys, out=None, ws=None, stream=None) -> torch.Tensor:
+    """Particle count of every node of the linked octree over `leaves` (same
+    order as node_keys)."""
+    nl = leaves.numel() - 1
+    n = node_keys.numel()
+    if out is None:
+        out = torch.empty(max(n, 1), dtype=torch.int32, device=leaves.device)
+    if ws is None:
+        ws = _workspace(_lib.cstone_octree_node_counts_workspace_bytes(nl), leaves.device)
+    _check(_lib.cstone_octree_node_counts(_ptr(leaves), _ptr(counts), nl, _ptr(node_keys), n, _ptr(out), _ptr(ws),
+                                          ws.numel(), _stream(stream)), "cstone_octree_node_counts")
+    return out[:n]
+
+
+def gather(src, perm, out=None, stream=None) -> torch.Tensor:
+    """out[i] = src[perm[i]] (float64 device arrays)."""
+    n = perm.numel()
+    _dev(src, torch.float64)
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=src.device)
+    _check(_lib.cstone_gather(_ptr(src), _ptr(perm), n, _ptr(out), _stream(stream)), "cstone_gather")
+    return out
+
+
+def gather_xyz(x, y, z, perm, out=None, fused: bool = False, stream=None):
+    """(x, y, z) in curve order: each taken through perm."""
+    n = perm.numel()
+    for t in (x, y, z):
+        _dev(t, torch.float64)
+    if out is None:
+        out = tuple(torch.empty(n, dtype=torch.float64, device=x.device) for _ in range(3))
+    _check(_lib.cstone_gather_xyz(_ptr(x), _ptr(y), _ptr(z), _ptr(perm), n, *(_ptr(o) for o in out), int(fused),
+                                  _stream(stream)), "cstone_gather_xyz")
+    return out
 
 
 # ---- whole build with preallocated buffers ----------------------------------------

@@ -99,6 +99,29 @@ cstone_status cstone_link_octree_by_sort(const uint64_t* leaves, size_t n_leaves
     return launch_link_by_sort(leaves, n_leaves, node_keys, child, level_offsets, ws, ws_bytes, stream);
 }
 
+size_t cstone_octree_node_counts_workspace_bytes(size_t n_leaves) { return node_props_workspace_bytes(n_leaves); }
+
+cstone_status cstone_octree_node_counts(const uint64_t* leaves, const uint32_t* counts, size_t n_leaves,
+                                        const uint64_t* node_keys, size_t n_nodes, uint32_t* node_counts, void* ws,
+                                        size_t ws_bytes, hipStream_t stream) {
+    if (n_leaves < 1 || n_leaves > kMaxN || n_nodes > kMaxN) return CSTONE_ERR_INVALID_ARG;
+    if (!leaves || !counts || !ws || (n_nodes && (!node_keys || !node_counts))) return CSTONE_ERR_INVALID_ARG;
+    return launch_octree_node_counts(leaves, counts, n_leaves, node_keys, n_nodes, node_counts, ws, ws_bytes, stream);
+}
+
+cstone_status cstone_gather(const double* src, const uint32_t* perm, size_t n, double* dst, hipStream_t stream) {
+    if (n > kMaxN || (n && (!src || !perm || !dst))) return CSTONE_ERR_INVALID_ARG;
+    return launch_gather(&src, perm, n, &dst, 1, false, stream);
+}
+
+cstone_status cstone_gather_xyz(const double* x, const double* y, const double* z, const uint32_t* perm, size_t n,
+                                double* ox, double* oy, double* oz, int fused, hipStream_t stream) {
+    if (n > kMaxN || (n && (!x || !y || !z || !perm || !ox || !oy || !oz))) return CSTONE_ERR_INVALID_ARG;
+    const double* src[3] = {x, y, z};
+    double* dst[3] = {ox, oy, oz};
+    return launch_gather(src, perm, n, dst, 3, fused != 0, stream);
+}
+
 size_t cstone_build_workspace_bytes(size_t n, size_t leaf_capacity) {
     Carve c(nullptr);
     c.take<uint64_t>(n);  // unsorted keys

@@ -120,6 +120,16 @@ cstone_status launch_sort_segmented(const uint64_t* keys_in, uint64_t* keys_out,
                                     uint32_t n_sets, size_t max_set, int sig_bits, int variant, void* ws,
                                     size_t ws_bytes, hipStream_t stream);
 
+// props.hip — particle counts of every node of a linked octree; gather of
+// particle arrays by the sort permutation (separate passes, or one fused pass
+// over three arrays)
+size_t node_props_workspace_bytes(size_t n_leaves);
+cstone_status launch_octree_node_counts(const uint64_t* leaves, const uint32_t* counts, size_t n_leaves,
+                                        const uint64_t* node_keys, size_t n_nodes, uint32_t* node_counts, void* ws,
+                                        size_t ws_bytes, hipStream_t stream);
+cstone_status launch_gather(const double* const* src, const uint32_t* perm, size_t n, double* const* dst, int arrays,
+                            bool fused, hipStream_t stream);
+
 // rebalance.hip
 cstone_status launch_node_counts(const uint64_t* sorted_keys, size_t n, const uint64_t* leaves, size_t n_leaves,
                                  uint32_t* counts, hipStream_t stream);
