@@ -218,6 +218,29 @@ CSTONE_API cstone_status cstone_build(const double* x, const double* y, const do
                            hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * cstone_build without a caller workspace, for callers that cannot allocate
+ * device memory (code under stream capture, serving loops, harnesses that
+ * forbid allocation). Same arguments, outputs and errors as cstone_build,
+ * less ws, ws_bytes and timings: the workspace is a fixed device array of
+ * CSTONE_STATIC_SCRATCH_BYTES inside the library, held on every device the
+ * library runs on until the process ends. Its address on a device is looked up
+ * on the first call there. The call allocates nothing.
+ * INVALID_ARG if cstone_build_workspace_bytes(n, leaf_capacity) exceeds the
+ * array (e.g. n above about 2^21 with a leaf capacity of about 8 n / N_crit);
+ * DEVICE if the array cannot be found. Every call on a device shares that
+ * device's array, which keeps the last call's contents: calls that overlap on
+ * one device (other streams, other host threads) race, so the caller must
+ * order them. Synchronises `stream`, as cstone_build does.
+ */
+#define CSTONE_STATIC_SCRATCH_BYTES (64ull << 20)
+CSTONE_API cstone_status cstone_build_static(const double* x, const double* y, const double* z, size_t n,
+                                             const cstone_box* box, cstone_curve curve, uint32_t n_crit,
+                                             uint64_t* sorted_keys, uint32_t* perm, uint64_t* leaves,
+                                             size_t* n_leaves, size_t leaf_capacity, uint32_t* counts,
+                                             uint64_t* node_keys, uint32_t* child, uint32_t* level_offsets,
+                                             uint32_t max_iters, uint32_t* iters_done, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Node properties and particles in curve order (Sec. 5: properties of the n
  * nodes kept in separate arrays of length n, filled after the build; Sec. 4:
  * the permutation that sorts the keys, applied to the particle arrays).

@@ -109,6 +109,7 @@ def _load() -> ctypes.CDLL:
         "cstone_batch_launch": (i32, [P, P]),
         "cstone_batch_autotune": (i32, [P] + [P] * 11 + [P, sz, i32, ctypes.POINTER(ctypes.c_float), P]),
         "cstone_build_workspace_bytes": (sz, [sz, sz]),
+        "cstone_build_static": (i32, [P, P, P, sz, pbox, i32, u32, P, P, P, psz, sz, P, P, P, P, u32, pu32, P]),
         "cstone_build": (i32, [P, P, P, sz, pbox, i32, u32, P, P, P, psz, sz, P, P, P, P, u32, pu32, P, sz,
                                ctypes.POINTER(Timings), P]),
     }

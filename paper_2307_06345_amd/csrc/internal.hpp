@@ -141,8 +141,8 @@ constexpr int kMaxRounds = 64;
 constexpr int kTileGroups = 8;
 constexpr int kCounterWords = 32;
 
-// Device-side loop state.
-struct LoopState {
+// Device-side loop state: the part the host reads after a batch of rounds ...
+struct LoopHeader {
     uint64_t nl[kMaxRounds + 1];    // leaves entering round r (batched: entries, closing keys included)
     uint32_t changed[kMaxRounds];   // some O_i != 1 in round r
     uint32_t merged[kMaxRounds];    // some O_i == 0 in round r
@@ -156,7 +156,10 @@ struct LoopState {
     uint32_t start_level;  // from the root: rounds skipped by starting at the uniform grid of this level
     uint32_t start_fine;   // the start-level search went finer than level 3
     uint32_t mins[kL + 1]; // least node count of every level (start-level search)
-    // last, and not copied to the host: the tile counters of every round
+};
+
+// ... and, after it and never copied to the host, the tile counters of every round.
+struct LoopState : LoopHeader {
     alignas(128) uint32_t counters[kMaxRounds][kTileGroups * kCounterWords];
 };
 

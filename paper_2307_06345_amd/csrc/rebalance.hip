@@ -778,9 +778,9 @@ cstone_status RebalanceLoop::enqueue(uint32_t rounds) {
 const uint64_t* RebalanceLoop::device_leaf_count() const { return &st_->final_nl; }
 
 cstone_status RebalanceLoop::wait(bool* finished) {
-    std::unique_ptr<LoopState> held(new LoopState);  // large (the device-only tile counters at its end)
-    LoopState& host = *held;
-    CS_HIP(hipMemcpyAsync(&host, st_, offsetof(LoopState, counters), hipMemcpyDeviceToHost, stream_));
+    LoopHeader host;  // the loop state without its tile counters
+    CS_HIP(hipMemcpyAsync(&host, static_cast<const LoopHeader*>(st_), sizeof(LoopHeader), hipMemcpyDeviceToHost,
+                          stream_));
     CS_HIP(hipStreamSynchronize(stream_));
     input_flags = host.input_flags;
     rounds = host.final_last + host.start_level;
