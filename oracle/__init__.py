@@ -69,6 +69,7 @@ def _load():
         "oracle_focus_leaves": (u64, [P, u64, u32, i32, u64, u64, ctypes.c_double, P, u64]),
         "oracle_focus_rebalance_step": (i32, [P, u64, P, u32, i32, u64, u64, ctypes.c_double, P, u64, P]),
         "oracle_radix_nodes": (None, [P, u64, P, P, P]),
+        "oracle_compact_octree": (u64, [P, u64, P, P, P, u64]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -333,3 +334,16 @@ def radix_nodes(keys):
     if k:
         _load().oracle_radix_nodes(_ptr(keys), m, _ptr(pl), _ptr(fi), _ptr(la))
     return pl, fi, la
+
+
+def compact_octree(K, counts):
+    """Compact octree over the non-empty leaves (Sec. 5): (NK sorted, parent)."""
+    K = _u64(K)
+    counts = np.ascontiguousarray(counts, dtype=np.uint32)
+    lib = _load()
+    cap = max(2 * K.size, 16)
+    NK = np.empty(cap, np.uint64)
+    par = np.empty(cap, np.uint32)
+    n = lib.oracle_compact_octree(_ptr(K), K.size - 1, _ptr(counts), _ptr(NK), _ptr(par), cap)
+    assert n <= cap
+    return NK[:n].copy(), par[:n].copy()

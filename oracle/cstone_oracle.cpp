@@ -37,6 +37,10 @@
 //   focused leaves      pinned (theta = 0 and F = whole domain reduce to the
 //                       balanced tree; Sec. 7.1 definition checked leaf by
 //                       leaf; the literal g^LE iteration reaches it)
+//   compact octree      pinned (without empty leaves it is the linked
+//                       octree; every internal node has 2 or more children;
+//                       parents contain their children; brute force on
+//                       tiny trees)
 //   radix nodes         pinned (brute force over all key pairs; ranges nest
 //                       and every key has one parent; the nodes with prefix
 //                       length 3 l are exactly the internal octree nodes)
@@ -548,6 +552,53 @@ void oracle_radix_nodes(const uint64_t* k, uint64_t m, uint32_t* prefix_len, uin
         first[i] = static_cast<uint32_t>(a);
         last[i] = static_cast<uint32_t>(b);
     }
+}
+
+// Compact octree (Sec. 5, the binary radix tree with the empty buckets of K
+// removed): the leaves of K that hold particles, plus one internal node for
+// every node of the binary radix tree over those leaves' keys whose prefix
+// length is a multiple of 3 (each adjacent pair of leaf keys splits exactly
+// one binary node, of prefix length = their common prefix), plus the root
+// (reading: the whole domain is always a node, so that the nodes form one
+// tree even where the radix tree's top prefix is not a whole digit). Node
+// keys in placeholder-bit format, sorted (breadth-first order); parent[p] is
+// the index of the nearest proper ancestor present (its longest proper prefix
+// among the nodes), 0xffffffff for the root. Writes up to `capacity` nodes
+// and returns their number.
+uint64_t oracle_compact_octree(const uint64_t* K, uint64_t n_leaves, const uint32_t* counts, uint64_t* NK,
+                               uint32_t* parent, uint64_t capacity) {
+    std::vector<uint64_t> keys, leaf_nodes;
+    for (uint64_t i = 0; i < n_leaves; ++i) {
+        if (counts[i] == 0) continue;
+        const int level = level_of_span(K[i + 1] - K[i]);
+        keys.push_back(K[i]);
+        leaf_nodes.push_back((1ull << (3 * level)) | (K[i] >> (3 * (kL - level))));
+    }
+    std::vector<uint64_t> nodes = leaf_nodes;
+    for (size_t i = 0; i + 1 < keys.size(); ++i) {
+        const int d = __builtin_clzll(keys[i] ^ keys[i + 1]) - 1;
+        if (d % 3 == 0) nodes.push_back((1ull << d) | (d ? keys[i] >> (63 - d) : 0ull));
+    }
+    if (std::find(nodes.begin(), nodes.end(), 1ull) == nodes.end()) nodes.push_back(1ull);  // the root
+    std::sort(nodes.begin(), nodes.end());
+    const uint64_t n = nodes.size();
+    if (n <= capacity) {
+        for (uint64_t p = 0; p < n; ++p) {
+            NK[p] = nodes[p];
+            parent[p] = 0xffffffffu;
+            int level = 0;
+            while ((nodes[p] >> (3 * (level + 1))) != 0) ++level;
+            for (int up = level - 1; up >= 0; --up) {  // nearest ancestor present
+                const uint64_t a = nodes[p] >> (3 * (level - up));
+                const uint64_t at = lower_bound_pos(nodes.data(), n, a);
+                if (at < n && nodes[at] == a) {
+                    parent[p] = static_cast<uint32_t>(at);
+                    break;
+                }
+            }
+        }
+    }
+    return n;
 }
 
 // Convenience: the whole pipeline of Secs. 3-5 for one particle set.

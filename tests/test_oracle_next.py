@@ -365,3 +365,69 @@ def test_radix_nodes_with_prefix_length_3l_are_the_octree_nodes():
         NK, CO, LO = oracle.link_octree(K)
         internal = sorted(int(k) for k in NK[CO != 0])
         assert got == internal
+
+
+# ---- compact octree (Sec. 5, empty buckets removed) ---------------------------------------
+
+
+def test_compact_octree_without_empty_leaves_is_the_linked_octree():
+    rng = np.random.default_rng(21)
+    for n_crit in (1, 4, 16):
+        P = clustered_P(rng, 8000)
+        K = oracle.build_leaves(P, n_crit)
+        ones = np.ones(K.size - 1, np.uint32)  # every leaf counted as non-empty
+        NKc, par = oracle.compact_octree(K, ones)
+        NK, CO, LO = oracle.link_octree(K)
+        assert np.array_equal(NKc, NK)
+        for p in np.flatnonzero(CO):
+            assert all(par[c] == p for c in range(CO[p], CO[p] + 8))
+        assert par[0] == 0xFFFFFFFF
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_compact_octree_structure(seed):
+    rng = np.random.default_rng(seed)
+    P = clustered_P(rng, 3000)
+    K = oracle.build_leaves(P, int(rng.integers(1, 9)))
+    N = oracle.node_counts(P, K)
+    NKc, par = oracle.compact_octree(K, N)
+    ranges = [placeholder_range(int(k)) for k in NKc]
+    # every non-empty leaf is a node, no empty one is
+    leaf_keys = {(int(K[i]), int(K[i + 1])) for i in range(K.size - 1) if N[i]}
+    present = {(a, b) for a, b, _ in ranges}
+    assert leaf_keys <= present
+    assert not {(int(K[i]), int(K[i + 1])) for i in range(K.size - 1) if not N[i]} & present
+    # parents contain their children; at most one node has no parent
+    children = {}
+    for p, q in enumerate(par):
+        if q == 0xFFFFFFFF:
+            continue
+        a, b, lv = ranges[p]
+        pa, pb, plv = ranges[q]
+        assert pa <= a and b <= pb and plv < lv
+        children.setdefault(int(q), []).append(p)
+    assert int(np.sum(par == 0xFFFFFFFF)) == 1 and par[0] == 0xFFFFFFFF and NKc[0] == 1  # the root
+    # internal nodes but the root have 2 or more children
+    internal = set(range(NKc.size)) - {i for i, r in enumerate(ranges) if (r[0], r[1]) in leaf_keys}
+    for q in internal:
+        assert q == 0 or len(children.get(q, [])) >= 2, q
+    assert len(children.get(0, [])) >= 1
+    # brute force: a node is internal iff two adjacent non-empty leaves split exactly at its digit boundary
+    lk = sorted(a for a, b in leaf_keys)
+    want = set()
+    for x, y in zip(lk[:-1], lk[1:]):
+        d = 63 - (x ^ y).bit_length()
+        if d % 3 == 0:
+            want.add((1 << d) | (x >> (63 - d) if d else 0))
+    assert {int(NKc[q]) for q in internal} == want | {1}
+
+
+def test_compact_octree_degenerate():
+    K = np.array([0, END], np.uint64)
+    NKc, par = oracle.compact_octree(K, np.array([5], np.uint32))  # the root is the only leaf
+    assert list(NKc) == [1] and list(par) == [0xFFFFFFFF]
+    NKc, par = oracle.compact_octree(K, np.array([0], np.uint32))  # no particles: the root alone
+    assert list(NKc) == [1] and list(par) == [0xFFFFFFFF]
+    K = np.array([0] + [j << 60 for j in range(1, 8)] + [END], np.uint64)
+    NKc, par = oracle.compact_octree(K, np.array([0, 0, 3, 0, 0, 0, 0, 0], np.uint32))  # one non-empty octant
+    assert list(NKc) == [1, 0o12] and list(par) == [0xFFFFFFFF, 0]
