@@ -241,6 +241,47 @@ CSTONE_API cstone_status cstone_build_static(const double* x, const double* y, c
                                              uint32_t max_iters, uint32_t* iters_done, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Octrees by way of a binary radix tree (Sec. 5, after Karras).
+ *
+ * cstone_radix_tree: the binary radix tree over m sorted unique keys (device,
+ * uint64 < 2^63): m - 1 internal nodes, node i covering keys [first[i],
+ * last[i]] (one end is i), split after key split[i] (left child: key split[i]
+ * if first[i] == split[i], else internal node split[i]; right child: key
+ * split[i] + 1 if that is last[i], else internal node split[i] + 1), and
+ * prefix_len[i] = the bits its keys share within the 63-bit key; node 0 is
+ * the root. Outputs: device, m - 1 uint32 each; first, last and split may be
+ * NULL. Asynchronous. Errors: INVALID_ARG.
+ *
+ * cstone_link_octree_radix: the linked octree of a cornerstone array through
+ * the radix tree over its leaf keys: its nodes with a prefix length that is a
+ * multiple of 3 are the internal octree nodes, extracted by a flag per node
+ * and an exclusive scan, then sorted and linked as in steps 3-5. Outputs
+ * equal those of cstone_link_octree. ws:
+ * cstone_link_octree_radix_workspace_bytes(n_leaves). Asynchronous.
+ *
+ * cstone_compact_octree: the octree with the empty buckets of K removed: the
+ * leaves whose count is not 0, the internal nodes of the radix tree over their
+ * keys whose prefix length is a multiple of 3, and the root (always present,
+ * so that the nodes form one tree). Every internal node but the root has at
+ * least 2 children. node_keys (device, capacity 2 n_leaves + 1 uint64):
+ * placeholder-bit keys in breadth-first order; parent (device, same
+ * capacity, uint32): index of the nearest proper ancestor present,
+ * 0xffffffff for the root; level_offsets (device, 23 uint32) as LO; *n_nodes
+ * (host): the node count. counts: device, n_leaves uint32 (Eq. histogram).
+ * Synchronises `stream`. ws: cstone_compact_octree_workspace_bytes(n_leaves).
+ */
+CSTONE_API cstone_status cstone_radix_tree(const uint64_t* keys, size_t m, uint32_t* first, uint32_t* last,
+                                           uint32_t* split, uint32_t* prefix_len, hipStream_t stream);
+CSTONE_API size_t cstone_link_octree_radix_workspace_bytes(size_t n_leaves);
+CSTONE_API cstone_status cstone_link_octree_radix(const uint64_t* leaves, size_t n_leaves, uint64_t* node_keys,
+                                                  uint32_t* child, uint32_t* level_offsets, void* ws, size_t ws_bytes,
+                                                  hipStream_t stream);
+CSTONE_API size_t cstone_compact_octree_workspace_bytes(size_t n_leaves);
+CSTONE_API cstone_status cstone_compact_octree(const uint64_t* leaves, const uint32_t* counts, size_t n_leaves,
+                                               uint64_t* node_keys, uint32_t* parent, uint32_t* level_offsets,
+                                               size_t* n_nodes, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Node properties and particles in curve order (Sec. 5: properties of the n
  * nodes kept in separate arrays of length n, filled after the build; Sec. 4:
  * the permutation that sorts the keys, applied to the particle arrays).
@@ -273,6 +314,97 @@ CSTONE_API cstone_status cstone_gather(const double* src, const uint32_t* perm, 
 CSTONE_API cstone_status cstone_gather_xyz(const double* x, const double* y, const double* z, const uint32_t* perm,
                                            size_t n, double* ox, double* oy, double* oz, int fused,
                                            hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * The replicated tree of particles held by several ranks, and the domain
+ * decomposition built on it (Sec. 6), for n_shards shards on one device.
+ *
+ * Shard g holds the particles [shard_offsets[g], shard_offsets[g+1]) (host
+ * array, n_shards + 1 entries, non-decreasing from 0 to n). Every round
+ * applies f (Eq. histogram) to each shard's own sorted keys, sums the
+ * n_shards count arrays element by element (f_r: the global reduction of the
+ * counts; a collective across ranks, here a reduction kernel), and applies g
+ * (Eqs. g1-g3) to the summed counts, until no leaf changes (f_glob = f_r . f
+ * alternating with g). The result is the balanced tree of all particles.
+ *
+ * cstone_global_rebalance: sorted_keys (device, n uint64) holds each shard's
+ * keys sorted on their own, back to back. leaves / n_leaves / leaf_capacity /
+ * counts (the summed counts of the final array) / max_iters / iters_done as
+ * in cstone_rebalance, and so are its errors. Synchronises `stream` once per
+ * round. ws: cstone_global_rebalance_workspace_bytes(leaf_capacity, n_shards).
+ *
+ * cstone_build_sharded: keys of every particle (Sec. 3), every shard sorted
+ * on its own (sorted_keys and perm per shard, perm relative to the shard's
+ * first particle), then cstone_global_rebalance from `leaves` (e.g. the root
+ * {0, 8^L}). ws: cstone_build_sharded_workspace_bytes (0 for bad offsets).
+ * Errors as cstone_build (no linking: cstone_link_octree on the result).
+ *
+ * cstone_sfc_partition: groups the leaves into n_ranks bins of consecutive
+ * leaves holding about N / n_ranks particles each (N the sum of counts):
+ * bounds (device, n_ranks + 1 uint32) with bin r = leaves [bounds[r],
+ * bounds[r+1]); with C_i the particles in leaves before leaf i, bounds[r] is
+ * the least i with C_i * n_ranks >= r * N, and bounds[n_ranks] = n_leaves.
+ * Bin r covers the keys [leaves[bounds[r]], leaves[bounds[r+1]]). counts:
+ * device, n_leaves uint32. Asynchronous. ws:
+ * cstone_sfc_partition_workspace_bytes(n_leaves). Errors: INVALID_ARG.
+ */
+CSTONE_API size_t cstone_global_rebalance_workspace_bytes(size_t leaf_capacity, uint32_t n_shards);
+CSTONE_API cstone_status cstone_global_rebalance(const uint64_t* sorted_keys, const uint64_t* shard_offsets,
+                                                 uint32_t n_shards, uint32_t n_crit, uint64_t* leaves,
+                                                 size_t* n_leaves, size_t leaf_capacity, uint32_t* counts,
+                                                 uint32_t max_iters, uint32_t* iters_done, void* ws, size_t ws_bytes,
+                                                 hipStream_t stream);
+CSTONE_API size_t cstone_build_sharded_workspace_bytes(const uint64_t* shard_offsets, uint32_t n_shards,
+                                                       size_t leaf_capacity);
+CSTONE_API cstone_status cstone_build_sharded(const double* x, const double* y, const double* z,
+                                              const uint64_t* shard_offsets, uint32_t n_shards,
+                                              const cstone_box* box, cstone_curve curve, uint32_t n_crit,
+                                              uint64_t* sorted_keys, uint32_t* perm, uint64_t* leaves,
+                                              size_t* n_leaves, size_t leaf_capacity, uint32_t* counts,
+                                              uint32_t max_iters, uint32_t* iters_done, void* ws, size_t ws_bytes,
+                                              hipStream_t stream);
+CSTONE_API size_t cstone_sfc_partition_workspace_bytes(size_t n_leaves);
+CSTONE_API cstone_status cstone_sfc_partition(const uint32_t* counts, size_t n_leaves, uint32_t n_ranks,
+                                              uint32_t* bounds, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * The tree focused on a range of the curve (Sec. 7: a locally essential tree
+ * for the subdomain F = [focus_start, focus_end) of one rank), from the
+ * particles at hand (the counts need no communication here).
+ *
+ * Minimum-distance MAC (Sec. 7.1): a node of edge l fails it against F if
+ * some point of F lies within distance l / theta of the node; distances are
+ * measured in grid cells between the closed grid boxes of the node and of F
+ * (F cut into maximal aligned key blocks), as r^2 theta^2 <= l^2 with r^2
+ * exact and theta^2 = theta * theta. A node overlapping F always fails;
+ * theta = 0 makes every node fail; an empty F makes none fail.
+ *
+ * cstone_focus_rebalance: rounds of f (Eq. histogram) and g^LE = g3 . g2 .
+ * g^LE_1 (Sec. 7.2) until no leaf changes, from `leaves` (e.g. the root).
+ * g^LE_1 splits a leaf holding more than n_crit particles only if it fails
+ * the MAC, and merges a complete group of 8 sibling leaves if their parent
+ * holds at most n_crit particles or passes the MAC; inside F this is g1. The
+ * result is the unique tree in which a node is split iff it holds more than
+ * n_crit particles, lies above level L and fails the MAC. Arguments, outputs
+ * and errors as cstone_rebalance; theta >= 0 and finite, focus_start <=
+ * focus_end <= 8^L. Synchronises `stream` once per round.
+ * ws: cstone_focus_rebalance_workspace_bytes(leaf_capacity).
+ *
+ * cstone_focus_mac (f^LE_2): fails[p] = 1 if node p of a linked octree (NK,
+ * placeholder-bit keys, device, n_nodes uint64) fails the MAC against F, else
+ * 0 (device, n_nodes bytes). Asynchronous.
+ * ws: cstone_focus_mac_workspace_bytes().
+ */
+CSTONE_API size_t cstone_focus_rebalance_workspace_bytes(size_t leaf_capacity);
+CSTONE_API cstone_status cstone_focus_rebalance(const uint64_t* sorted_keys, size_t n, uint32_t n_crit,
+                                                cstone_curve curve, uint64_t focus_start, uint64_t focus_end,
+                                                double theta, uint64_t* leaves, size_t* n_leaves,
+                                                size_t leaf_capacity, uint32_t* counts, uint32_t max_iters,
+                                                uint32_t* iters_done, void* ws, size_t ws_bytes, hipStream_t stream);
+CSTONE_API size_t cstone_focus_mac_workspace_bytes(void);
+CSTONE_API cstone_status cstone_focus_mac(const uint64_t* node_keys, size_t n_nodes, cstone_curve curve,
+                                          uint64_t focus_start, uint64_t focus_end, double theta, uint8_t* fails,
+                                          void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Sort tile shapes and their autotune table. The radix sort has several

@@ -88,10 +88,26 @@ def _load() -> ctypes.CDLL:
         "cstone_sort_variant_info": (i32, [i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "cstone_sort_autotune": (i32, [P, sz, P, P, P, sz, i32, ctypes.POINTER(ctypes.c_float),
                                        ctypes.POINTER(i32), P]),
+        "cstone_radix_tree": (i32, [P, sz, P, P, P, P, P]),
+        "cstone_link_octree_radix_workspace_bytes": (sz, [sz]),
+        "cstone_link_octree_radix": (i32, [P, sz, P, P, P, P, sz, P]),
+        "cstone_compact_octree_workspace_bytes": (sz, [sz]),
+        "cstone_compact_octree": (i32, [P, P, sz, P, P, P, psz, P, sz, P]),
         "cstone_octree_node_counts_workspace_bytes": (sz, [sz]),
         "cstone_octree_node_counts": (i32, [P, P, sz, P, sz, P, P, sz, P]),
         "cstone_gather": (i32, [P, P, sz, P, P]),
         "cstone_gather_xyz": (i32, [P, P, P, P, sz, P, P, P, i32, P]),
+        "cstone_global_rebalance_workspace_bytes": (sz, [sz, u32]),
+        "cstone_global_rebalance": (i32, [P, P, u32, u32, P, psz, sz, P, u32, pu32, P, sz, P]),
+        "cstone_build_sharded_workspace_bytes": (sz, [P, u32, sz]),
+        "cstone_build_sharded": (i32, [P, P, P, P, u32, pbox, i32, u32, P, P, P, psz, sz, P, u32, pu32, P, sz, P]),
+        "cstone_focus_rebalance_workspace_bytes": (sz, [sz]),
+        "cstone_focus_rebalance": (i32, [P, sz, u32, i32, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double, P, psz, sz,
+                                         P, u32, pu32, P, sz, P]),
+        "cstone_focus_mac_workspace_bytes": (sz, []),
+        "cstone_focus_mac": (i32, [P, sz, i32, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double, P, P, sz, P]),
+        "cstone_sfc_partition_workspace_bytes": (sz, [sz]),
+        "cstone_sfc_partition": (i32, [P, sz, u32, P, P, sz, P]),
         "cstone_tune_set": (i32, [i32, sz, i32]),
         "cstone_tune_get": (i32, [i32, sz]),
         "cstone_tune_clear": (None, []),
@@ -269,6 +285,45 @@ def link_octree(leaves, node_keys=None, child=None, level_offsets=None, ws=None,
     return node_keys[:n], child[:n], level_offsets
 
 
+def radix_tree(keys, stream=None):
+    """Binary radix tree over sorted unique keys: (first, last, split, prefix_len) per internal node."""
+    m = keys.numel()
+    k = max(m - 1, 1)
+    out = [torch.empty(k, dtype=torch.int32, device=keys.device) for _ in range(4)]
+    _check(_lib.cstone_radix_tree(_ptr(keys), m, *(_ptr(o) for o in out), _stream(stream)), "cstone_radix_tree")
+    return tuple(o[: max(m - 1, 0)] for o in out)
+
+
+def link_octree_radix(leaves, node_keys=None, child=None, level_offsets=None, ws=None, stream=None):
+    """Linked octree through the binary radix tree (same outputs as link_octree)."""
+    nl = leaves.numel() - 1
+    n = node_count(nl)
+    dev = leaves.device
+    node_keys = torch.empty(n, dtype=torch.int64, device=dev) if node_keys is None else node_keys
+    child = torch.empty(n, dtype=torch.int32, device=dev) if child is None else child
+    level_offsets = torch.empty(LEVEL_OFFSETS, dtype=torch.int32, device=dev) if level_offsets is None else level_offsets
+    if ws is None:
+        ws = _workspace(_lib.cstone_link_octree_radix_workspace_bytes(nl), dev)
+    _check(_lib.cstone_link_octree_radix(_ptr(leaves), nl, _ptr(node_keys), _ptr(child), _ptr(level_offsets),
+                                         _ptr(ws), ws.numel(), _stream(stream)), "cstone_link_octree_radix")
+    return node_keys[:n], child[:n], level_offsets
+
+
+def compact_octree(leaves, counts, stream=None):
+    """Octree over the non-empty leaves (empty buckets removed): (NK, parent, LO)."""
+    nl = leaves.numel() - 1
+    dev = leaves.device
+    cap = 2 * nl + 1
+    nk = torch.empty(cap, dtype=torch.int64, device=dev)
+    par = torch.empty(cap, dtype=torch.int32, device=dev)
+    lo = torch.empty(LEVEL_OFFSETS, dtype=torch.int32, device=dev)
+    ws = _workspace(_lib.cstone_compact_octree_workspace_bytes(nl), dev)
+    n = ctypes.c_size_t(0)
+    _check(_lib.cstone_compact_octree(_ptr(leaves), _ptr(counts), nl, _ptr(nk), _ptr(par), _ptr(lo),
+                                      ctypes.byref(n), _ptr(ws), ws.numel(), _stream(stream)), "cstone_compact_octree")
+    return nk[: n.value], par[: n.value], lo
+
+
 def octree_node_counts(leaves, counts, node_keys, out=None, ws=None, stream=None) -> torch.Tensor:
     """Particle count of every node of the linked octree over `leaves` (same
     order as node_keys)."""
@@ -303,6 +358,115 @@ def gather_xyz(x, y, z, perm, out=None, fused: bool = False, stream=None):
     _check(_lib.cstone_gather_xyz(_ptr(x), _ptr(y), _ptr(z), _ptr(perm), n, *(_ptr(o) for o in out), int(fused),
                                   _stream(stream)), "cstone_gather_xyz")
     return out
+
+
+def _offsets(shard_offsets):
+    off = np.ascontiguousarray(shard_offsets, dtype=np.uint64)
+    return off, off.ctypes.data_as(ctypes.c_void_p), off.size - 1
+
+
+def build_sharded(x, y, z, shard_offsets, box, curve, n_crit: int, capacity=None, max_iters: int = 0, stream=None):
+    """Sec. 6 on one device: particles split into shards at `shard_offsets`
+    (n_shards + 1 ints), each shard's keys sorted on their own, the tree of all
+    particles from per-shard counts summed every round. Returns (sorted keys
+    per shard, perm per shard, K, summed counts, rounds)."""
+    n = x.numel()
+    for t in (x, y, z):
+        _dev(t, torch.float64)
+    off, off_p, G = _offsets(shard_offsets)
+    dev = x.device
+    if capacity is None:
+        capacity = leaf_capacity_bound(n, n_crit)
+    P = torch.empty(max(n, 1), dtype=torch.int64, device=dev)
+    perm = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    K = torch.empty(capacity + 1, dtype=torch.int64, device=dev)
+    K[:2].copy_(torch.tensor([0, -(1 << 63)], dtype=torch.int64))  # the root {0, 8^L}
+    counts = torch.empty(capacity, dtype=torch.int32, device=dev)
+    ws = _workspace(_lib.cstone_build_sharded_workspace_bytes(off_p, G, capacity), dev)
+    nl = ctypes.c_size_t(1)
+    rounds = ctypes.c_uint32(0)
+    b = Box.of(box)
+    _check(_lib.cstone_build_sharded(_ptr(x), _ptr(y), _ptr(z), off_p, G, ctypes.byref(b), int(curve), int(n_crit),
+                                     _ptr(P), _ptr(perm), _ptr(K), ctypes.byref(nl), capacity, _ptr(counts),
+                                     int(max_iters), ctypes.byref(rounds), _ptr(ws), ws.numel(), _stream(stream)),
+           "cstone_build_sharded")
+    return P[:n], perm[:n], K[: nl.value + 1], counts[: nl.value], int(rounds.value)
+
+
+def global_rebalance(sorted_keys, shard_offsets, n_crit: int, leaves=None, capacity=None, max_iters: int = 0,
+                     stream=None):
+    """Tree of all shards' particles from their separately sorted keys (back to
+    back at `shard_offsets`), from `leaves` (default the root). Returns (K,
+    summed counts, rounds)."""
+    n = sorted_keys.numel()
+    off, off_p, G = _offsets(shard_offsets)
+    dev = sorted_keys.device
+    nl0 = 1 if leaves is None else leaves.numel() - 1
+    if capacity is None:
+        capacity = leaf_capacity_bound(n, n_crit, nl0)
+    K = torch.empty(capacity + 1, dtype=torch.int64, device=dev)
+    if leaves is None:
+        K[:2].copy_(torch.tensor([0, -(1 << 63)], dtype=torch.int64))
+    else:
+        K[: nl0 + 1].copy_(leaves)
+    counts = torch.empty(capacity, dtype=torch.int32, device=dev)
+    ws = _workspace(_lib.cstone_global_rebalance_workspace_bytes(capacity, G), dev)
+    nl = ctypes.c_size_t(nl0)
+    rounds = ctypes.c_uint32(0)
+    _check(_lib.cstone_global_rebalance(_ptr(sorted_keys), off_p, G, int(n_crit), _ptr(K), ctypes.byref(nl),
+                                        capacity, _ptr(counts), int(max_iters), ctypes.byref(rounds), _ptr(ws),
+                                        ws.numel(), _stream(stream)), "cstone_global_rebalance")
+    return K[: nl.value + 1], counts[: nl.value], int(rounds.value)
+
+
+def focus_rebalance(sorted_keys, n_crit: int, curve: int, focus_start: int, focus_end: int, theta: float,
+                    leaves=None, capacity=None, max_iters: int = 0, stream=None):
+    """Tree focused on the curve range [focus_start, focus_end) (Sec. 7), from
+    `leaves` (default the root). Returns (K, counts, rounds)."""
+    n = sorted_keys.numel()
+    dev = sorted_keys.device
+    nl0 = 1 if leaves is None else leaves.numel() - 1
+    if capacity is None:
+        capacity = leaf_capacity_bound(n, n_crit, nl0)
+    K = torch.empty(capacity + 1, dtype=torch.int64, device=dev)
+    if leaves is None:
+        K[:2].copy_(torch.tensor([0, -(1 << 63)], dtype=torch.int64))
+    else:
+        K[: nl0 + 1].copy_(leaves)
+    counts = torch.empty(capacity, dtype=torch.int32, device=dev)
+    ws = _workspace(_lib.cstone_focus_rebalance_workspace_bytes(capacity), dev)
+    nl = ctypes.c_size_t(nl0)
+    rounds = ctypes.c_uint32(0)
+    st = _lib.cstone_focus_rebalance(_ptr(sorted_keys), n, int(n_crit), int(curve), int(focus_start), int(focus_end),
+                                     float(theta), _ptr(K), ctypes.byref(nl), capacity, _ptr(counts), int(max_iters),
+                                     ctypes.byref(rounds), _ptr(ws), ws.numel(), _stream(stream))
+    if st != 0:
+        err = CstoneError(st, "cstone_focus_rebalance")
+        err.n_leaves = nl.value
+        raise err
+    return K[: nl.value + 1], counts[: nl.value], int(rounds.value)
+
+
+def focus_mac(node_keys, curve: int, focus_start: int, focus_end: int, theta: float, stream=None) -> torch.Tensor:
+    """f^LE_2: 1 where a node of the linked octree fails the MAC against F (uint8)."""
+    n = node_keys.numel()
+    out = torch.empty(max(n, 1), dtype=torch.uint8, device=node_keys.device)
+    ws = _workspace(_lib.cstone_focus_mac_workspace_bytes(), node_keys.device)
+    _check(_lib.cstone_focus_mac(_ptr(node_keys), n, int(curve), int(focus_start), int(focus_end), float(theta),
+                                 _ptr(out), _ptr(ws), ws.numel(), _stream(stream)), "cstone_focus_mac")
+    return out[:n]
+
+
+def sfc_partition(counts, n_ranks: int, bounds=None, stream=None) -> torch.Tensor:
+    """Bounds (n_ranks + 1) of n_ranks bins of consecutive leaves with about
+    N / n_ranks particles each (Sec. 6)."""
+    nl = counts.numel()
+    if bounds is None:
+        bounds = torch.empty(int(n_ranks) + 1, dtype=torch.int32, device=counts.device)
+    ws = _workspace(_lib.cstone_sfc_partition_workspace_bytes(nl), counts.device)
+    _check(_lib.cstone_sfc_partition(_ptr(counts), nl, int(n_ranks), _ptr(bounds), _ptr(ws), ws.numel(),
+                                     _stream(stream)), "cstone_sfc_partition")
+    return bounds
 
 
 # ---- whole build with preallocated buffers ----------------------------------------

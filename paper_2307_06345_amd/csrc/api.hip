@@ -99,6 +99,32 @@ cstone_status cstone_link_octree_by_sort(const uint64_t* leaves, size_t n_leaves
     return launch_link_by_sort(leaves, n_leaves, node_keys, child, level_offsets, ws, ws_bytes, stream);
 }
 
+cstone_status cstone_radix_tree(const uint64_t* keys, size_t m, uint32_t* first, uint32_t* last, uint32_t* split,
+                                uint32_t* prefix_len, hipStream_t stream) {
+    if (m > kMaxN || (m >= 2 && (!keys || !prefix_len))) return CSTONE_ERR_INVALID_ARG;
+    return launch_radix_tree(keys, m, first, last, split, prefix_len, stream);
+}
+
+size_t cstone_link_octree_radix_workspace_bytes(size_t n_leaves) { return radix_link_workspace_bytes(n_leaves); }
+
+cstone_status cstone_link_octree_radix(const uint64_t* leaves, size_t n_leaves, uint64_t* node_keys, uint32_t* child,
+                                       uint32_t* level_offsets, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (n_leaves < 1 || n_leaves > kMaxN || (n_leaves - 1) % 7 != 0) return CSTONE_ERR_INVALID_ARG;
+    if (!leaves || !node_keys || !child || !level_offsets || !ws) return CSTONE_ERR_INVALID_ARG;
+    return launch_link_radix(leaves, n_leaves, node_keys, child, level_offsets, ws, ws_bytes, stream);
+}
+
+size_t cstone_compact_octree_workspace_bytes(size_t n_leaves) { return compact_octree_workspace_bytes(n_leaves); }
+
+cstone_status cstone_compact_octree(const uint64_t* leaves, const uint32_t* counts, size_t n_leaves,
+                                    uint64_t* node_keys, uint32_t* parent, uint32_t* level_offsets, size_t* n_nodes,
+                                    void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (n_leaves < 1 || n_leaves >= kMaxN / 2) return CSTONE_ERR_INVALID_ARG;
+    if (!leaves || !counts || !node_keys || !parent || !level_offsets || !n_nodes || !ws) return CSTONE_ERR_INVALID_ARG;
+    return launch_compact_octree(leaves, counts, n_leaves, node_keys, parent, level_offsets, n_nodes, ws, ws_bytes,
+                                 stream);
+}
+
 size_t cstone_octree_node_counts_workspace_bytes(size_t n_leaves) { return node_props_workspace_bytes(n_leaves); }
 
 cstone_status cstone_octree_node_counts(const uint64_t* leaves, const uint32_t* counts, size_t n_leaves,

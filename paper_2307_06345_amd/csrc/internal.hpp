@@ -123,12 +123,38 @@ cstone_status launch_sort_segmented(const uint64_t* keys_in, uint64_t* keys_out,
 // props.hip — particle counts of every node of a linked octree; gather of
 // particle arrays by the sort permutation (separate passes, or one fused pass
 // over three arrays)
+// exclusive prefix sum: out[i] = in[0] + ... + in[i - 1] for i <= n (out[n]
+// the total, modulo 2^32), one pass; n < 2^32 - 1
+size_t scan_u32_workspace_bytes(size_t n);
+cstone_status launch_scan_u32(const uint32_t* in, size_t n, uint32_t* out, void* ws, size_t ws_bytes,
+                              hipStream_t stream);
 size_t node_props_workspace_bytes(size_t n_leaves);
 cstone_status launch_octree_node_counts(const uint64_t* leaves, const uint32_t* counts, size_t n_leaves,
                                         const uint64_t* node_keys, size_t n_nodes, uint32_t* node_counts, void* ws,
                                         size_t ws_bytes, hipStream_t stream);
 cstone_status launch_gather(const double* const* src, const uint32_t* perm, size_t n, double* const* dst, int arrays,
                             bool fused, hipStream_t stream);
+
+// global.hip — the replicated tree of sharded particles, its partition
+size_t global_rebalance_workspace_bytes(size_t leaf_capacity, uint32_t n_shards);
+cstone_status run_global_rebalance(const uint64_t* sorted_keys, const uint64_t* shard_off_dev, uint32_t n_shards,
+                                   uint32_t n_crit, uint64_t* leaves, size_t* n_leaves, size_t leaf_capacity,
+                                   uint32_t* counts, uint32_t max_iters, uint32_t* iters_done, void* ws,
+                                   size_t ws_bytes, hipStream_t stream);
+size_t sfc_partition_workspace_bytes(size_t n_leaves);
+cstone_status launch_sfc_partition(const uint32_t* counts, size_t n_leaves, uint32_t n_ranks, uint32_t* bounds,
+                                   void* ws, size_t ws_bytes, hipStream_t stream);
+
+// radix.hip — binary radix tree (after Karras) and the octrees built on it
+cstone_status launch_radix_tree(const uint64_t* keys, size_t m, uint32_t* first, uint32_t* last, uint32_t* split,
+                                uint32_t* prefix_len, hipStream_t stream);
+size_t radix_link_workspace_bytes(size_t n_leaves);
+cstone_status launch_link_radix(const uint64_t* leaves, size_t n_leaves, uint64_t* node_keys, uint32_t* child,
+                                uint32_t* level_offsets, void* ws, size_t ws_bytes, hipStream_t stream);
+size_t compact_octree_workspace_bytes(size_t n_leaves);
+cstone_status launch_compact_octree(const uint64_t* leaves, const uint32_t* counts, size_t n_leaves,
+                                    uint64_t* node_keys, uint32_t* parent, uint32_t* level_offsets, size_t* n_nodes,
+                                    void* ws, size_t ws_bytes, hipStream_t stream);
 
 // rebalance.hip
 cstone_status launch_node_counts(const uint64_t* sorted_keys, size_t n, const uint64_t* leaves, size_t n_leaves,
@@ -234,6 +260,10 @@ size_t link_batch_workspace_bytes(uint32_t n_sets, size_t entry_capacity);
 cstone_status launch_link_batch(const BatchTreeView& tree, const BatchSet* sets, uint32_t n_sets,
                                 size_t entry_capacity, uint64_t* node_keys, uint32_t* child,
                                 uint32_t* level_offsets, void* ws, size_t ws_bytes, hipStream_t stream);
+// steps 3-5 of Sec. 5 from unsorted node keys: sort (keys only, 64 bits), LO
+// by search, and CO (skipped if child is NULL)
+cstone_status launch_link_finish(const uint64_t* unsorted, size_t n, uint64_t* node_keys, uint32_t* child,
+                                 uint32_t* level_offsets, void* sort_ws, size_t sort_ws_bytes, hipStream_t stream);
 cstone_status launch_link_by_sort(const uint64_t* leaves, size_t n_leaves, uint64_t* node_keys, uint32_t* child,
                                   uint32_t* level_offsets, void* ws, size_t ws_bytes, hipStream_t stream);
 

@@ -460,6 +460,19 @@ cstone_status launch_link(const uint64_t* leaves, size_t nl, const uint64_t* nl_
     return CSTONE_OK;
 }
 
+cstone_status launch_link_finish(const uint64_t* unsorted, size_t n, uint64_t* node_keys, uint32_t* child,
+                                 uint32_t* level_offsets, void* sort_ws, size_t sort_ws_bytes, hipStream_t stream) {
+    // placeholder keys use up to 64 bits (level 21 sets bit 63)
+    cstone_status s = launch_sort(unsorted, node_keys, nullptr, n, 64, sort_ws, sort_ws_bytes, stream);
+    if (s != CSTONE_OK) return s;
+    hipLaunchKernelGGL(level_offsets_kernel, dim3(1), dim3(64), 0, stream, node_keys, n, level_offsets);
+    if (child)
+        hipLaunchKernelGGL(child_offsets_kernel, dim3((n + kLinkBlock - 1) / kLinkBlock), dim3(kLinkBlock), 0, stream,
+                           node_keys, n, level_offsets, child);
+    CS_HIP(hipGetLastError());
+    return CSTONE_OK;
+}
+
 cstone_status launch_link_by_sort(const uint64_t* leaves, size_t nl, uint64_t* node_keys, uint32_t* child,
                                   uint32_t* level_offsets, void* ws, size_t ws_bytes, hipStream_t stream) {
     if (ws_bytes < link_workspace_bytes(nl)) return CSTONE_ERR_INVALID_ARG;
@@ -470,14 +483,7 @@ cstone_status launch_link_by_sort(const uint64_t* leaves, size_t nl, uint64_t* n
     hipLaunchKernelGGL(link_nodes_kernel, dim3((nl + kLinkBlock - 1) / kLinkBlock), dim3(kLinkBlock), 0, stream,
                        leaves, nl, unsorted);
     CS_HIP(hipGetLastError());
-    // placeholder keys use up to 64 bits (level 21 sets bit 63)
-    cstone_status s = launch_sort(unsorted, node_keys, nullptr, n, 64, sort_ws, ws_bytes - c.off, stream);
-    if (s != CSTONE_OK) return s;
-    hipLaunchKernelGGL(level_offsets_kernel, dim3(1), dim3(64), 0, stream, node_keys, n, level_offsets);
-    hipLaunchKernelGGL(child_offsets_kernel, dim3((n + kLinkBlock - 1) / kLinkBlock), dim3(kLinkBlock), 0, stream,
-                       node_keys, n, level_offsets, child);
-    CS_HIP(hipGetLastError());
-    return CSTONE_OK;
+    return launch_link_finish(unsorted, n, node_keys, child, level_offsets, sort_ws, ws_bytes - c.off, stream);
 }
 
 }  // namespace cs

@@ -40,11 +40,11 @@ __global__ __launch_bounds__(256) void props_setup_kernel(uint64_t* words, size_
     }
 }
 
-// S[i] = counts[0] + ... + counts[i - 1] for i <= n_l (S[n_l] = N): one pass,
-// tiles taken in order from a counter, decoupled look-back across tiles.
-__global__ __launch_bounds__(kScanBlock) void leaf_scan_kernel(const uint32_t* __restrict__ counts, uint32_t nl,
-                                                               uint32_t* __restrict__ S, uint64_t* words,
-                                                               uint32_t* counter, uint32_t* err) {
+// S[i] = counts[0] + ... + counts[i - 1] for i <= nl (S[nl] the total): one
+// pass, tiles taken in order from a counter, decoupled look-back across tiles.
+__global__ __launch_bounds__(kScanBlock) void exclusive_scan_kernel(const uint32_t* __restrict__ counts, uint32_t nl,
+                                                                    uint32_t* __restrict__ S, uint64_t* words,
+                                                                    uint32_t* counter, uint32_t* err) {
     __shared__ uint32_t slot;
     __shared__ uint64_t scan_tmp[kScanBlock / kWave];
     __shared__ uint64_t tile_prefix;
@@ -150,19 +150,17 @@ __global__ __launch_bounds__(kGatherBlock) void gather_kernel(const double* __re
     }
 }
 
-struct PropsWs {
-    uint32_t* S;
+struct ScanWs {
     uint64_t* words;
     uint32_t* counter;
     uint32_t* err;
     size_t tiles, bytes;
 };
 
-PropsWs carve_props(void* ws, size_t nl) {
+ScanWs carve_scan(void* ws, size_t n) {
     Carve c(ws);
-    PropsWs w{};
-    w.tiles = (nl + 1 + kScanTile - 1) / kScanTile;
-    w.S = c.take<uint32_t>(nl + 1);
+    ScanWs w{};
+    w.tiles = (n + 1 + kScanTile - 1) / kScanTile;
     w.words = c.take<uint64_t>(w.tiles);
     w.counter = c.take<uint32_t>(1);
     w.err = c.take<uint32_t>(1);
@@ -172,20 +170,37 @@ PropsWs carve_props(void* ws, size_t nl) {
 
 }  // namespace
 
-size_t node_props_workspace_bytes(size_t n_leaves) { return carve_props(nullptr, n_leaves).bytes; }
+size_t scan_u32_workspace_bytes(size_t n) { return carve_scan(nullptr, n).bytes; }
+
+cstone_status launch_scan_u32(const uint32_t* in, size_t n, uint32_t* out, void* ws, size_t ws_bytes,
+                              hipStream_t stream) {
+    ScanWs w = carve_scan(ws, n);
+    if (ws_bytes < w.bytes || n >= 0xffffffffull) return CSTONE_ERR_INVALID_ARG;
+    hipLaunchKernelGGL(props_setup_kernel, dim3(static_cast<uint32_t>(std::min<size_t>((w.tiles + 255) / 256, 256))),
+                       dim3(256), 0, stream, w.words, w.tiles, w.counter, w.err);
+    hipLaunchKernelGGL(exclusive_scan_kernel, dim3(static_cast<uint32_t>(w.tiles)), dim3(kScanBlock), 0, stream, in,
+                       static_cast<uint32_t>(n), out, w.words, w.counter, w.err);
+    CS_HIP(hipGetLastError());
+    return CSTONE_OK;
+}
+
+size_t node_props_workspace_bytes(size_t n_leaves) {
+    Carve c(nullptr);
+    c.take<uint32_t>(n_leaves + 1);
+    return c.off + scan_u32_workspace_bytes(n_leaves);
+}
 
 cstone_status launch_octree_node_counts(const uint64_t* leaves, const uint32_t* counts, size_t nl,
                                         const uint64_t* node_keys, size_t n_nodes, uint32_t* node_counts, void* ws,
                                         size_t ws_bytes, hipStream_t stream) {
-    PropsWs w = carve_props(ws, nl);
-    if (ws_bytes < w.bytes) return CSTONE_ERR_INVALID_ARG;
-    hipLaunchKernelGGL(props_setup_kernel, dim3(static_cast<uint32_t>(std::min<size_t>((w.tiles + 255) / 256, 256))),
-                       dim3(256), 0, stream, w.words, w.tiles, w.counter, w.err);
-    hipLaunchKernelGGL(leaf_scan_kernel, dim3(static_cast<uint32_t>(w.tiles)), dim3(kScanBlock), 0, stream, counts,
-                       static_cast<uint32_t>(nl), w.S, w.words, w.counter, w.err);
+    if (ws_bytes < node_props_workspace_bytes(nl)) return CSTONE_ERR_INVALID_ARG;
+    Carve c(ws);
+    uint32_t* S = c.take<uint32_t>(nl + 1);
+    cstone_status st = launch_scan_u32(counts, nl, S, static_cast<char*>(ws) + c.off, ws_bytes - c.off, stream);
+    if (st != CSTONE_OK) return st;
     if (n_nodes)
         hipLaunchKernelGGL(node_counts_tree_kernel, dim3(static_cast<uint32_t>((n_nodes + kNodeBlock - 1) / kNodeBlock)),
-                           dim3(kNodeBlock), 0, stream, leaves, static_cast<uint32_t>(nl), w.S, node_keys,
+                           dim3(kNodeBlock), 0, stream, leaves, static_cast<uint32_t>(nl), S, node_keys,
                            static_cast<uint32_t>(n_nodes), node_counts);
     CS_HIP(hipGetLastError());
     return CSTONE_OK;
