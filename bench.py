@@ -27,6 +27,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+# Compulsory bytes per particle of a build: coordinates read once (24), keys
+# written and read once (16), P and perm written once (12), and the leaf /
+# node arrays (about 10 per particle at N_crit 64).
+FLOOR_BYTES_PER_PARTICLE = 62
 
 
 def byte_model(n: int, leaves_per_round: list, n_leaves: int) -> dict:
@@ -95,6 +99,174 @@ def cpu_baseline(sample_n: int) -> dict:
     return {"value": sample_n / dt, "unit": "particles/s", "cores": 1, "kind": "oracle",
             "sample": f"single-threaded oracle, whole build (keys, sort, leaves, counts, links) of {sample_n} "
                       f"uniform particles, Hilbert, N_crit 64 ({ref['K'].size - 1} leaves) in {dt:.2f} s"}
+
+
+def cpu_baseline_small() -> dict:
+    """The oracle on the whole 65,536-particle Morton configuration."""
+    import oracle
+    import workloads as wl
+
+    s = wl.config_small()
+    t0 = time.perf_counter()
+    oracle.build_tree(s.x, s.y, s.z, s.box, s.curve, s.n_crit)
+    dt = time.perf_counter() - t0
+    return {"value": s.n / dt, "unit": "particles/s", "cores": 1, "kind": "oracle", "ms": dt * 1e3,
+            "sample": f"the whole configuration: {s.n} uniform particles, Morton, N_crit 64"}
+
+
+def cpu_baseline_plummer(sample_n: int) -> dict:
+    """The oracle on a bounded sample of the 2^27 Plummer configuration: the
+    first sample_n particles of the same seeded stream (the oracle builds
+    every tree from scratch, so a rebuild costs it a whole build)."""
+    import oracle
+    import workloads as wl
+
+    s = wl.make_set("plummer", sample_n, 3, 0, wl.HILBERT, 16)
+    t0 = time.perf_counter()
+    ref = oracle.build_tree(s.x, s.y, s.z, s.box, s.curve, s.n_crit)
+    dt = time.perf_counter() - t0
+    return {"value": sample_n / dt, "unit": "particles/s", "cores": 1, "kind": "oracle",
+            "sample": f"single-threaded oracle, whole build of {sample_n} Plummer particles (a = 1, r_t = 20), "
+                      f"Hilbert, N_crit 16 ({ref['K'].size - 1} leaves) in {dt:.2f} s"}
+
+
+def copy_bandwidth(nbytes: int, reps: int = 10) -> dict:
+    """Device-to-device copy of nbytes (read + write), for context beside the
+    8 TB/s peak: GB/s of (2 nbytes) per copy, median over reps."""
+    import torch
+
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for _ in range(reps):
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = float(np.median(ts))
+    del src, dst
+    return {"bytes_moved": 2 * nbytes, "ms": ms, "gbs": 2 * nbytes / (ms * 1e-3) / 1e9}
+
+
+def event_ms(fn, reps: int):
+    """Median and minimum ms of fn() between two events on the current stream."""
+    import torch
+
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts)), float(np.min(ts))
+
+
+def bench_small(steps: int) -> dict:
+    """Latency of the 65,536-particle Morton build (N_crit 64, from the root):
+    wall time of each synchronous build, median and minimum."""
+    import torch
+
+    import paper_2307_06345_amd as cs
+    import workloads as wl
+
+    s = wl.config_small()
+    x, y, z = (cs.from_numpy(a, "cuda") for a in (s.x, s.y, s.z))
+    b = cs.Builder(s.n, s.n_crit)
+    for _ in range(5):
+        b.build(x, y, z, s.box, s.curve, s.n_crit)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        r = b.build(x, y, z, s.box, s.curve, s.n_crit)
+        ts.append((time.perf_counter() - t0) * 1e3)
+    return {"workload": "plain build, 65,536 uniform particles, Morton, N_crit 64, from the root",
+            "latency_ms_median": float(np.median(ts)), "latency_ms_min": float(np.min(ts)),
+            "leaves": r.n_leaves, "rounds": r.rounds}
+
+
+def bench_beyond(b, x, y, z, s, r, reps: int) -> dict:
+    """The steps around the build and its alternatives, on the 2^24 tree just
+    built (each timed with events, median of reps):
+      node counts of the linked octree: 8 n (NK) + 4 n (out) + 4 n_l (leaf
+        counts) + 8 n_l (S written and read) algorithmic bytes;
+      gather of x, y, z by perm: 4 N + 24 N + 24 N = 52 N (one array per pass,
+        or one fused pass);
+      the link through the binary radix tree against the default link;
+      the compact octree (empty buckets removed);
+      the sharded build with 8 shards (keys, 8 shard sorts, rounds with summed
+        counts and a host synchronisation each) against the plain build;
+      the tree focused on 1/64 of the curve, theta 0.5, from the root."""
+    import torch
+
+    import paper_2307_06345_amd as cs
+
+    n, nl = s.n, r.n_leaves
+    nn = cs.node_count(nl)
+    out = {}
+    leaves, counts, nk = r.leaves.clone(), r.counts.clone(), r.node_keys.clone()
+    P, perm = r.sorted_keys.clone(), r.perm.clone()
+    cnt = torch.empty(nn, dtype=torch.int32, device="cuda")
+    ws = cs._workspace(cs._lib.cstone_octree_node_counts_workspace_bytes(nl), "cuda")
+    med, mn = event_ms(lambda: cs.octree_node_counts(leaves, counts, nk, out=cnt, ws=ws), reps)
+    byt = 8 * nn + 4 * nn + 4 * nl + 8 * nl
+    out["node_counts"] = {"ms": med, "ms_min": mn, "nodes": nn, "bytes": byt, "gbs": byt / (med * 1e-3) / 1e9}
+    gx = tuple(torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(3))
+    byt = 52 * n
+    med, mn = event_ms(lambda: cs.gather_xyz(x, y, z, perm, out=gx), reps)
+    medf, mnf = event_ms(lambda: cs.gather_xyz(x, y, z, perm, out=gx, fused=True), reps)
+    out["gather_xyz"] = {"ms_per_array_passes": med, "ms_fused": medf, "bytes": byt,
+                         "gbs_per_array_passes": byt / (med * 1e-3) / 1e9, "gbs_fused": byt / (medf * 1e-3) / 1e9}
+    NK = torch.empty(nn, dtype=torch.int64, device="cuda")
+    CO = torch.empty(nn, dtype=torch.int32, device="cuda")
+    LO = torch.empty(cs.LEVEL_OFFSETS, dtype=torch.int32, device="cuda")
+    wl_ = cs._workspace(cs._lib.cstone_link_workspace_bytes(nl), "cuda")
+    wr = cs._workspace(cs._lib.cstone_link_octree_radix_workspace_bytes(nl), "cuda")
+    d_med, _ = event_ms(lambda: cs.link_octree(leaves, NK, CO, LO, ws=wl_), reps)
+    s_med, _ = event_ms(lambda: cs.link_octree(leaves, NK, CO, LO, ws=wl_, by_sort=True), reps)
+    r_med, _ = event_ms(lambda: cs.link_octree_radix(leaves, NK, CO, LO, ws=wr), reps)
+    same = bool(torch.equal(NK, nk))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ck, cp, _ = cs.compact_octree(leaves, counts)
+    c_ms = (time.perf_counter() - t0) * 1e3 / reps
+    out["link"] = {"breadth_first_ms": d_med, "five_steps_by_sort_ms": s_med, "radix_tree_ms": r_med,
+                   "radix_equals_default": same, "compact_octree_ms_wall": c_ms,
+                   "compact_nodes": int(ck.numel()), "linked_nodes": nn}
+    G = 8
+    off = np.linspace(0, n, G + 1).astype(np.uint64)
+    cs.build_sharded(x, y, z, off, s.box, s.curve, s.n_crit)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(max(1, reps // 2)):
+        t0 = time.perf_counter()
+        _, _, Kg, Ng, rg = cs.build_sharded(x, y, z, off, s.box, s.curve, s.n_crit)
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    out["sharded_8"] = {"ms_wall": float(np.median(ts)), "rounds": rg, "equals_plain": bool(torch.equal(Kg, leaves)),
+                        "particles_per_s": n / (float(np.median(ts)) * 1e-3)}
+    Ph = P[int(n * 0.5)].item() & ((1 << 64) - 1)
+    fa = (Ph >> 45) << 45
+    fb = min(fa + (1 << 57), 1 << 63)
+    cs.focus_rebalance(P, s.n_crit, s.curve, fa, fb, 0.5)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(max(1, reps // 2)):
+        t0 = time.perf_counter()
+        Kf, _, rf = cs.focus_rebalance(P, s.n_crit, s.curve, fa, fb, 0.5)
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    out["focus"] = {"ms_wall": float(np.median(ts)), "rounds": rf, "leaves": int(Kf.numel() - 1),
+                    "range": [fa, fb], "theta": 0.5}
+    return out
 
 
 def bench_batched(steps: int) -> dict:
@@ -258,6 +430,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-plummer", action="store_true")
+    ap.add_argument("--no-beyond", action="store_true")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="also copy 24 N bytes device to device once (the same bytes as a digit pass), "
                          "to scale hardware traffic counters")
@@ -284,8 +457,11 @@ def main():
 
     # throughput: K whole builds (each synchronises once, as cstone_build does)
     t0 = time.perf_counter()
+    build_ms = []
     for _ in range(args.steps):
-        r = b.build(x, y, z, s.box, s.curve, s.n_crit)
+        t1 = time.perf_counter()
+        r = b.build(x, y, z, s.box, s.curve, s.n_crit)  # synchronises once (the leaf count)
+        build_ms.append((time.perf_counter() - t1) * 1e3)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
 
@@ -299,6 +475,8 @@ def main():
         stage = [a + v for a, v in zip(stage, r.stage_ms)]
         passes = list(r.sort_pass_ms) if passes is None else [a + v for a, v in zip(passes, r.sort_pass_ms)]
     torch.cuda.synchronize()
+
+    copy = copy_bandwidth(24 * s.n)
 
     if args.calibration_copy:
         src = torch.empty(24 * s.n, dtype=torch.uint8, device="cuda").fill_(1)
@@ -369,8 +547,16 @@ def main():
                   "model_bytes": model,
                   "model_fraction": model["total"] / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9),
                   "path_bytes": path,
-                  "path_fraction": path["total"] / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9)},
+                  "path_fraction": path["total"] / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9),
+                  "floor_bytes": FLOOR_BYTES_PER_PARTICLE * n,
+                  "floor_fraction": FLOOR_BYTES_PER_PARTICLE * n / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9),
+                  "build_ms_median": float(np.median(build_ms)), "build_ms_min": float(np.min(build_ms)),
+                  "build_ms_all": build_ms},
+        "copy_bandwidth": copy,
     }
+    out["small_65536"] = bench_small(args.steps)
+    if not args.no_beyond:
+        out["beyond_the_build"] = bench_beyond(b, x, y, z, s, r, 10)
     if not args.no_batched:
         out["batched"] = bench_batched(args.batch_steps)
     if not args.no_plummer:
@@ -380,6 +566,8 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(min(args.cpu_sample, n))
         out["cpu_baseline"]["host_cpus"] = os.cpu_count()
+        out["cpu_baseline"]["small_65536"] = cpu_baseline_small()
+        out["cpu_baseline"]["plummer_sample"] = cpu_baseline_plummer(1 << 23)
     print(json.dumps(out), flush=True)
 
 
