@@ -66,6 +66,34 @@ def path_bytes(model: dict, n: int) -> dict:
     return out
 
 
+def leaves_per_round(leaves, level_offsets) -> list:
+    """Leaves entering every round of a build from the root, from the final
+    tree: from the root the loop only splits (a split parent's children sum to
+    more than N_crit, so nothing merges), so after t rounds the leaves are the
+    final tree cut at level t: its leaves on levels <= t plus its internal
+    nodes on level t. Ends with the final count twice (the check round)."""
+    import paper_2307_06345_amd as cs
+
+    K = cs.to_numpy(leaves).astype(np.uint64)
+    LO = cs.to_numpy(level_offsets).astype(np.int64)
+    delta = K[1:] - K[:-1]
+    lev = 21 - (np.floor(np.log2(delta.astype(np.float64)) + 0.5).astype(np.int64) // 3)
+    hist = np.bincount(lev, minlength=22)
+    nodes = LO[1:23] - LO[0:22]  # nodes per level
+    depth = int(lev.max())
+    out = [1]
+    for t in range(1, depth + 1):
+        out.append(int(hist[:t + 1].sum() + (nodes[t] - hist[t]) if t < depth else hist.sum()))
+    out.append(int(hist.sum()))
+    return out
+
+
+def lsd_sort_bytes(n: int, passes: int) -> int:
+    """A plain LSD sort with the permutation: 20 N for the first pass (values
+    implicit), 24 N for every other."""
+    return 20 * n + 24 * n * (passes - 1)
+
+
 def kernel_source_digest() -> str:
     h = hashlib.sha256()
     for name in ("sort.hip", "common.hpp"):
@@ -390,6 +418,10 @@ def bench_plummer(reps: int = 3, rebuilds: int = 10) -> dict:
 
     n, n_crit = 1 << 27, 16
     x, y, z, _ = wl.device_sets([("plummer", n, 3, 0)])
+    # the sort shape for this size class, tuned on these keys (excluded from the timing)
+    keys = cs.compute_keys(x, y, z, wl.PLUMMER_BOX, wl.HILBERT)
+    chosen, tune_ms = cs.sort_autotune(keys, reps=2)
+    del keys
     b = cs.Builder(n, n_crit, leaf_capacity=8 * n // (n_crit + 1) + 64)
     b.build(x, y, z, wl.PLUMMER_BOX, wl.HILBERT, n_crit)  # warm-up
     torch.cuda.synchronize()
@@ -410,12 +442,27 @@ def bench_plummer(reps: int = 3, rebuilds: int = 10) -> dict:
         reb_ms.append((time.perf_counter() - t0) * 1e3)
         reb_rounds.append(r.rounds)
     t_root = float(np.median(root_ms))
+    r0 = b.build(x, y, z, wl.PLUMMER_BOX, wl.HILBERT, n_crit)  # from the root again, for its tree
+    hist = leaves_per_round(r0.leaves, r0.level_offsets)
+    model = byte_model(n, hist, r0.n_leaves)
+    bits, _, _ = cs.sort_variants()[chosen]
+    split = bool(cs.sort_variant_layouts()[chosen][1])
+    path = dict(model)
+    # the split sort's low passes over listed buckets are data-dependent: its path bytes count the top passes
+    # and the bucket pass only (a lower bound); an LSD shape's are exact
+    path["sort"] = (20 * n + 2 * 24 * n + 8 * n) if split else lsd_sort_bytes(n, (63 + bits - 1) // bits)
+    path["total"] = model["keys"] + path["sort"] + model["rebalance"] + model["link"]
+    peak = HBM_PEAK_GBS * 1e9
     return {"workload": "2^27 Plummer particles (a = 1, r_t = 20, box [-20, 20]^3), Hilbert, N_crit 16; "
                         "then 10 incremental rebuilds after cumulative N(0, 1e-3^2) displacements",
+            "leaves_per_round": hist, "model_bytes": model, "model_fraction": model["total"] / (t_root * 1e-3) / peak,
+            "path_bytes": path, "path_fraction": path["total"] / (t_root * 1e-3) / peak,
             "n": n, "leaves": leaves, "rounds_from_root": rounds,
             "from_root_ms": t_root, "from_root_particles_per_s": n / (t_root * 1e-3),
             "rebuild_ms": reb_ms, "rebuild_rounds": reb_rounds,
-            "rebuild_particles_per_s": n / (float(np.mean(reb_ms)) * 1e-3)}
+            "rebuild_particles_per_s": n / (float(np.mean(reb_ms)) * 1e-3),
+            "sort_shape": {"chosen": chosen, "shape": cs.sort_variants()[chosen],
+                           "xcd_group_split": cs.sort_variant_layouts()[chosen], "sort_ms_per_shape": tune_ms}}
 
 
 def main():
@@ -431,6 +478,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-plummer", action="store_true")
     ap.add_argument("--no-beyond", action="store_true")
+    ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="also copy 24 N bytes device to device once (the same bytes as a digit pass), "
                          "to scale hardware traffic counters")
@@ -493,14 +541,8 @@ def main():
     passes = [v / args.steps for v in passes]
 
     # leaves per round from the root, for the byte model
-    leaves_hist = [1]
     nl_final = r.leaves.numel() - 1
-    for rr in range(1, r.rounds + 1):
-        try:
-            K, _, _ = cs.rebalance(r.sorted_keys, s.n_crit, max_iters=rr)
-            leaves_hist.append(K.numel() - 1)
-        except cs.CstoneError as e:
-            leaves_hist.append(e.n_leaves)
+    leaves_hist = leaves_per_round(r.leaves, r.level_offsets)
     model = byte_model(n, leaves_hist, nl_final)
 
     # dominant kernel: a later top digit pass (keys + permutation in and out).
@@ -554,7 +596,8 @@ def main():
                   "build_ms_all": build_ms},
         "copy_bandwidth": copy,
     }
-    out["small_65536"] = bench_small(args.steps)
+    if not args.no_small:
+        out["small_65536"] = bench_small(args.steps)
     if not args.no_beyond:
         out["beyond_the_build"] = bench_beyond(b, x, y, z, s, r, 10)
     if not args.no_batched:

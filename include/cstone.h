@@ -434,8 +434,8 @@ CSTONE_API cstone_status cstone_focus_mac(const uint64_t* node_keys, size_t n_no
  *   cstone_tune_clear     empties the table; cstone_tune_entries counts it.
  *   cstone_tune_save      writes the table to a JSON file (one entry per line:
  *                         kernel, size_log2, device, variant and the shape's
- *                         digit bits, block and items). INVALID_ARG if the file
- *                         cannot be written.
+ *                         digit bits, block, items, XCD grouping and split).
+ *                         INVALID_ARG if the file cannot be written.
  *   cstone_tune_load      merges such a file into the table, skipping entries
  *                         whose index does not name the same shape in this
  *                         library. INVALID_ARG if the file cannot be read or
@@ -445,6 +445,9 @@ CSTONE_API cstone_status cstone_focus_mac(const uint64_t* node_keys, size_t n_no
 #define CSTONE_TUNE_BATCH_SORT 1
 CSTONE_API int cstone_sort_variant_count(void);
 CSTONE_API cstone_status cstone_sort_variant_info(int variant, int* digit_bits, int* block, int* items);
+/* The rest of a shape: consecutive tiles dealt to one XCD (1: none), and
+ * whether particle keys take the split sort (1) or plain LSD passes (0). */
+CSTONE_API cstone_status cstone_sort_variant_layout(int variant, int* xcd_group, int* split);
 CSTONE_API cstone_status cstone_sort_autotune(const uint64_t* keys_in, size_t n, uint64_t* keys_out, uint32_t* perm_out,
                                    void* ws, size_t ws_bytes, int reps, float* ms_per_variant, int* chosen,
                                    hipStream_t stream);

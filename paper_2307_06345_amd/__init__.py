@@ -86,6 +86,7 @@ def _load() -> ctypes.CDLL:
         "cstone_link_octree_by_sort": (i32, [P, sz, P, P, P, P, sz, P]),
         "cstone_sort_variant_count": (i32, []),
         "cstone_sort_variant_info": (i32, [i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "cstone_sort_variant_layout": (i32, [i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "cstone_sort_autotune": (i32, [P, sz, P, P, P, sz, i32, ctypes.POINTER(ctypes.c_float),
                                        ctypes.POINTER(i32), P]),
         "cstone_radix_tree": (i32, [P, sz, P, P, P, P, P]),
@@ -586,6 +587,16 @@ def sort_variants() -> list:
         _check(_lib.cstone_sort_variant_info(v, ctypes.byref(b), ctypes.byref(bl), ctypes.byref(it)),
                "cstone_sort_variant_info")
         out.append((b.value, bl.value, it.value))
+    return out
+
+
+def sort_variant_layouts() -> list:
+    """(XCD grouping, split sort 0/1) of every compiled sort shape."""
+    out = []
+    for v in range(_lib.cstone_sort_variant_count()):
+        xg, sp = ctypes.c_int(), ctypes.c_int()
+        _check(_lib.cstone_sort_variant_layout(v, ctypes.byref(xg), ctypes.byref(sp)), "cstone_sort_variant_layout")
+        out.append((xg.value, sp.value))
     return out
 
 

@@ -389,6 +389,14 @@ CSTONE_API cstone_status cstone_sort_variant_info(int variant, int* digit_bits, 
     return CSTONE_OK;
 }
 
+CSTONE_API cstone_status cstone_sort_variant_layout(int variant, int* xcd_group, int* split) {
+    if (variant < 0 || variant >= cs::sort_variant_count()) return CSTONE_ERR_INVALID_ARG;
+    const cs::SortVariantInfo v = cs::sort_variant_info(variant);
+    if (xcd_group) *xcd_group = v.xcd_group;
+    if (split) *split = v.split;
+    return CSTONE_OK;
+}
+
 CSTONE_API cstone_status cstone_sort_autotune(const uint64_t* keys_in, size_t n, uint64_t* keys_out,
                                               uint32_t* perm_out, void* ws, size_t ws_bytes, int reps,
                                               float* ms_per_variant, int* chosen, hipStream_t stream) {

@@ -96,7 +96,7 @@ cstone_status launch_keys_batch(const double* x, const double* y, const double* 
 // set, set}, never straddling two sets; seg_base[s] = first key of set s.
 // Permutation values are relative to the set's first key.
 struct SortVariantInfo {
-    int bits, block, items, tile;
+    int bits, block, items, tile, xcd_group, split;
 };
 int sort_variant_count();
 SortVariantInfo sort_variant_info(int variant);

@@ -1075,21 +1075,27 @@ void launch_list_t(const PassArgs& a, const SegArgs& g, uint32_t* counter, hipSt
 
 struct Variant {
     int bits, block, items, window, xcd_group;
+    bool split;  // particle keys take the split sort (9-bit digits only), else plain LSD passes
     void (*launch)(const PassArgs&, bool, bool, hipStream_t);
     void (*launch_seg)(const PassArgs&, const SegArgs&, bool, bool, hipStream_t);
     void (*launch_list)(const PassArgs&, const SegArgs&, uint32_t*, hipStream_t);
 };
 
-#define CS_VARIANT(B, BL, IT, WI, XG) \
-    {B, BL, IT, WI, XG, launch_pass_t<B, BL, IT, WI, XG>, launch_seg_t<B, BL, IT, WI, XG>, launch_list_t<B, BL, IT, WI, XG>}
-// Shapes: digit bits, block, keys per thread, look-back window, XCD grouping.
-// A block needs at least one thread per digit, so 256-thread blocks take
-// 8-bit digits; 1024-thread blocks hold one block per CU.
+#define CS_VARIANT(B, BL, IT, WI, XG, SP)                                                                   \
+    {B, BL, IT, WI, XG, SP, launch_pass_t<B, BL, IT, WI, XG>, launch_seg_t<B, BL, IT, WI, XG>, \
+     launch_list_t<B, BL, IT, WI, XG>}
+// Shapes: digit bits, block, keys per thread, look-back window, XCD grouping,
+// split sort for particle keys. A block needs at least one thread per digit,
+// so 256-thread blocks take 8-bit digits; 1024-thread blocks hold one block
+// per CU. The 9-bit shapes without the split run 7 plain LSD passes, which a
+// strongly clustered set (many level-9 buckets over the bucket kernel's
+// sizes) can favour.
 const Variant kVariants[] = {
-    CS_VARIANT(9, 512, 16, 4, 8),  CS_VARIANT(9, 512, 16, 4, 1), CS_VARIANT(8, 512, 16, 4, 8),
-    CS_VARIANT(9, 512, 12, 4, 8),  CS_VARIANT(9, 512, 32, 4, 8), CS_VARIANT(8, 512, 16, 4, 1),
-    CS_VARIANT(9, 512, 12, 4, 1),  CS_VARIANT(9, 512, 32, 4, 1), CS_VARIANT(9, 1024, 8, 4, 8),
-    CS_VARIANT(9, 1024, 16, 4, 8), CS_VARIANT(8, 256, 16, 4, 8),
+    CS_VARIANT(9, 512, 16, 4, 8, true),   CS_VARIANT(9, 512, 16, 4, 1, true),  CS_VARIANT(8, 512, 16, 4, 8, false),
+    CS_VARIANT(9, 512, 12, 4, 8, true),   CS_VARIANT(9, 512, 32, 4, 8, true),  CS_VARIANT(8, 512, 16, 4, 1, false),
+    CS_VARIANT(9, 512, 12, 4, 1, true),   CS_VARIANT(9, 512, 32, 4, 1, true),  CS_VARIANT(9, 1024, 8, 4, 8, true),
+    CS_VARIANT(9, 1024, 16, 4, 8, true),  CS_VARIANT(8, 256, 16, 4, 8, false), CS_VARIANT(9, 512, 16, 4, 8, false),
+    CS_VARIANT(9, 512, 12, 4, 8, false),
 };
 #undef CS_VARIANT
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
@@ -1157,7 +1163,7 @@ SortWs carve_sort(void* ws, size_t n, bool with_perm) {
 
 // Whether a sort of n particle keys takes the split path.
 bool use_split(size_t n, int sig_bits, bool with_perm, const Variant& var) {
-    return with_perm && sig_bits == 63 && var.bits == kSplitBits && n > 0;
+    return with_perm && sig_bits == 63 && var.split && n > 0;
 }
 
 }  // namespace
@@ -1366,10 +1372,7 @@ cstone_status launch_sort(const uint64_t* keys_in, uint64_t* keys_out, uint32_t*
         var.launch(a, p == 0, with_perm, stream);
         src_k = a.keys_out;
         src_v = a.vals_out;
-        // events after the first and the last top pass only: the later top
-        // passes are timed together, with no event between their launches
-        if (pass_events && (p == 0 || p == kSplitTop - 1))
-            CS_HIP(hipEventRecord(pass_events[p == 0 ? 1 : 2], stream));
+        if (pass_events) CS_HIP(hipEventRecord(pass_events[p + 1], stream));  // one interval per pass
     }
     CS_HIP(hipGetLastError());
     return CSTONE_OK;
@@ -1382,7 +1385,7 @@ int sort_variant_count() { return kNumVariants; }
 
 SortVariantInfo sort_variant_info(int v) {
     const Variant& x = kVariants[(v >= 0 && v < kNumVariants) ? v : 0];
-    return {x.bits, x.block, x.items, x.block * x.items};
+    return {x.bits, x.block, x.items, x.block * x.items, x.xcd_group, x.split ? 1 : 0};
 }
 
 
@@ -1408,7 +1411,7 @@ struct SegWs {
     size_t bytes;
 };
 
-bool seg_split(int variant) { return kVariants[variant].bits == kSplitBits; }
+bool seg_split(int variant) { return kVariants[variant].split; }
 
 SegWs carve_seg(void* ws, size_t n_total, size_t n_tiles, uint32_t n_sets, int variant) {
     const Variant& var = kVariants[variant];

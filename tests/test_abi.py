@@ -142,6 +142,7 @@ def test_tune_table_round_trips_through_its_json_file(tmp_path):
         e = {x["kernel"]: x for x in doc["entries"]}
         assert e["sort"]["size_log2"] == 24 and e["sort"]["variant"] == 2
         assert (e["sort"]["digit_bits"], e["sort"]["block"], e["sort"]["items"]) == cs.sort_variants()[2]
+        assert (e["sort"]["xcd_group"], e["sort"]["split"]) == cs.sort_variant_layouts()[2]
         assert e["batch_sort"]["size_log2"] == 26
         cs.tune_clear()
         assert cs.tune_entries() == 0 and cs.tune_get(cs.TUNE_SORT, 1 << 24) == -1
