@@ -210,7 +210,7 @@ __device__ __forceinline__ void onesweep_tile(const TileDesc td, const uint64_t*
     uint32_t* stage32 = reinterpret_cast<uint32_t*>(stage);
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = lane_id();
-    const uint32_t wave = tid / kWave;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid / kWave);  // wave-uniform, in a scalar register
     const uint32_t tile = td.tile;
     const uint32_t tile_base = td.base;
     const uint32_t tile_count = FULL ? static_cast<uint32_t>(TILE) : td.count;
@@ -591,7 +591,7 @@ __device__ __forceinline__ void lds_sort_segment(const uint64_t* kin, const uint
     constexpr int RADIX = 1 << BITS;
     constexpr int W = BLOCK / kWave;
     static_assert(BLOCK >= RADIX, "one digit per thread in the digit loops");
-    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = __builtin_amdgcn_readfirstlane(tid / kWave);
     const uint32_t wbase = wave * ITEMS * kWave;
     const uint32_t off = a - wlo;
     const uint64_t k0 = in_lds ? sm.keys[off] : kin[a];
@@ -694,7 +694,7 @@ __device__ __forceinline__ void lds_sort_window(const uint64_t* kin, const uint3
                                                 LocalSmem<BITS, BLOCK, ITEMS>& sm) {
     constexpr int W = BLOCK / kWave;
     static_assert(ITEMS * W <= kWave, "one wave scans the per-(item, wave) start counts");
-    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = __builtin_amdgcn_readfirstlane(tid / kWave);
     if (tid == 0) sm.maxb = 0;
     uint64_t k[ITEMS];
     uint64_t smask[ITEMS];
