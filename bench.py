@@ -27,6 +27,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+
+_T0 = time.perf_counter()
+
+
+def progress(*a):
+    """A progress line on stderr (the JSON result goes to stdout)."""
+    print(f"[bench {time.perf_counter() - _T0:7.1f} s]", *a, file=sys.stderr, flush=True)
 # Compulsory bytes per particle of a build: coordinates read once (24), keys
 # written and read once (16), P and perm written once (12), and the leaf /
 # node arrays (about 10 per particle at N_crit 64).
@@ -365,9 +373,10 @@ def bench_serving(count: int, rhos=(0.5, 0.7, 0.9)) -> dict:
     """Continuous batching of `count` build requests (sizes floor(2^U), U ~
     U[12, 22], uniform/Plummer, Hilbert, N_crit in {16, 64}) arriving as a
     Poisson stream, HBM budget 64 GB, coordinates drawn on the device as each
-    group is launched. Capacity is measured first with every request of a
-    2000-request prefix available at once; the arrival rate is then
-    rho * capacity / E[N] for each rho."""
+    group is launched. Each launch slot keeps its device buffers between
+    groups (they grow only when a group needs more). Capacity is measured
+    first with every request of a 2000-request prefix available at once; the
+    arrival rate is then rho * capacity / E[N] for each rho."""
     import torch
 
     from paper_2307_06345_amd import serving as sv
@@ -376,26 +385,33 @@ def bench_serving(count: int, rhos=(0.5, 0.7, 0.9)) -> dict:
     specs = wl.serving_specs(count)
     mean_n = float(np.mean([s[1] for s in specs]))
 
+    ex = sv.GpuExecutor(max_inflight=3, budget_bytes=64 * 10**9)  # slots keep their buffers across runs
+
     def run(reqs):
-        ex = sv.GpuExecutor(max_inflight=3)
         loop = sv.ServingLoop(ex, budget_bytes=64 * 10**9, max_inflight=3)
         done, st = loop.run(reqs)
         torch.cuda.synchronize()
         return done, st
 
-    run(sv.poisson_requests(specs[:200], rate_per_s=1e12))  # warm-up (allocator, code objects)
+    # warm-up: the capacity workload itself, so that every slot has grown its
+    # buffers to the largest group before anything is timed
+    run(sv.poisson_requests(specs[:min(count, 2000)], rate_per_s=1e12))
+    progress("serving warm-up done")
     _, cal = run(sv.poisson_requests(specs[:min(count, 2000)], rate_per_s=1e12))
+    progress("serving capacity run done")
     capacity = cal.particles_per_s
     runs = {}
     for rho in rhos:
         rate = rho * capacity / mean_n
         done, st = run(sv.poisson_requests(specs, rate_per_s=rate))
+        progress(f"serving run at rho {rho} done")
         runs[str(rho)] = {"arrival_rate_per_s": rate, "particles_per_s": st.particles_per_s,
                           "latency_p50_ms": st.latency_p50_ms, "latency_p99_ms": st.latency_p99_ms,
                           "latency_mean_ms": st.latency_mean_ms, "makespan_s": st.makespan_s,
                           "batches": st.batches, "mean_batch_requests": st.mean_batch_requests,
                           "max_inflight": st.max_inflight, "peak_reserved_gb": st.peak_reserved_bytes / 1e9,
                           "retries": st.retries, "statuses": st.statuses}
+    out_buffers = {"slot_buffer_peak_gb": ex.peak_buffer_bytes / 1e9, "slot_buffer_growths": ex.grows}
     main_run = runs[str(0.7)] if str(0.7) in runs else next(iter(runs.values()))
     return {"workload": f"{count} requests, sizes floor(2^U), U ~ U[12, 22], uniform/Plummer, Hilbert, "
                         "N_crit in {16, 64}, Poisson arrivals, HBM budget 64 GB, seed 5",
@@ -403,7 +419,7 @@ def bench_serving(count: int, rhos=(0.5, 0.7, 0.9)) -> dict:
             "capacity_particles_per_s": capacity, "capacity_batches": cal.batches,
             "rho": 0.7, "latency_p50_ms": main_run["latency_p50_ms"],
             "latency_p99_ms": main_run["latency_p99_ms"], "particles_per_s": main_run["particles_per_s"],
-            "runs": runs}
+            "runs": runs, "resident_buffers": out_buffers}
 
 
 def bench_plummer(reps: int = 3, rebuilds: int = 10) -> dict:
@@ -446,7 +462,7 @@ def bench_plummer(reps: int = 3, rebuilds: int = 10) -> dict:
     hist = leaves_per_round(r0.leaves, r0.level_offsets)
     model = byte_model(n, hist, r0.n_leaves)
     bits, _, _ = cs.sort_variants()[chosen]
-    split = bool(cs.sort_variant_layouts()[chosen][1])
+    split = bool(cs.sort_variant_splits()[chosen])
     path = dict(model)
     # the split sort's low passes over listed buckets are data-dependent: its path bytes count the top passes
     # and the bucket pass only (a lower bound); an LSD shape's are exact
@@ -462,7 +478,7 @@ def bench_plummer(reps: int = 3, rebuilds: int = 10) -> dict:
             "rebuild_ms": reb_ms, "rebuild_rounds": reb_rounds,
             "rebuild_particles_per_s": n / (float(np.mean(reb_ms)) * 1e-3),
             "sort_shape": {"chosen": chosen, "shape": cs.sort_variants()[chosen],
-                           "xcd_group_split": cs.sort_variant_layouts()[chosen], "sort_ms_per_shape": tune_ms}}
+                           "split": cs.sort_variant_splits()[chosen], "sort_ms_per_shape": tune_ms}}
 
 
 def main():
@@ -596,16 +612,22 @@ def main():
                   "build_ms_all": build_ms},
         "copy_bandwidth": copy,
     }
+    progress("2^24 builds done:", f"{ms_per_step:.4f} ms per build")
     if not args.no_small:
         out["small_65536"] = bench_small(args.steps)
+        progress("65,536-particle latency done")
     if not args.no_beyond:
         out["beyond_the_build"] = bench_beyond(b, x, y, z, s, r, 10)
+        progress("steps beyond the build done")
     if not args.no_batched:
         out["batched"] = bench_batched(args.batch_steps)
+        progress("batched builds done")
     if not args.no_plummer:
         out["plummer_2_27"] = bench_plummer()
+        progress("2^27 Plummer builds done")
     if not args.no_serving:
         out["serving"] = bench_serving(args.serving_requests)
+        progress("serving done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(min(args.cpu_sample, n))
         out["cpu_baseline"]["host_cpus"] = os.cpu_count()

@@ -434,7 +434,7 @@ CSTONE_API cstone_status cstone_focus_mac(const uint64_t* node_keys, size_t n_no
  *   cstone_tune_clear     empties the table; cstone_tune_entries counts it.
  *   cstone_tune_save      writes the table to a JSON file (one entry per line:
  *                         kernel, size_log2, device, variant and the shape's
- *                         digit bits, block, items, XCD grouping and split).
+ *                         digit bits, block, items and split).
  *                         INVALID_ARG if the file cannot be written.
  *   cstone_tune_load      merges such a file into the table, skipping entries
  *                         whose index does not name the same shape in this
@@ -445,9 +445,14 @@ CSTONE_API cstone_status cstone_focus_mac(const uint64_t* node_keys, size_t n_no
 #define CSTONE_TUNE_BATCH_SORT 1
 CSTONE_API int cstone_sort_variant_count(void);
 CSTONE_API cstone_status cstone_sort_variant_info(int variant, int* digit_bits, int* block, int* items);
-/* The rest of a shape: consecutive tiles dealt to one XCD (1: none), and
- * whether particle keys take the split sort (1) or plain LSD passes (0). */
-CSTONE_API cstone_status cstone_sort_variant_layout(int variant, int* xcd_group, int* split);
+/* The rest of a shape: whether particle keys take the split sort (1) or
+ * plain LSD passes (0). */
+CSTONE_API cstone_status cstone_sort_variant_split(int variant, int* split);
+/* Look-back waits before a sort block counts a missing predecessor tile's
+ * digits itself (the look-back's fallback), for later launches on the current
+ * device; default 256. Any value gives the same sort; 0 sends every wait to
+ * the fallback (for tests). Errors: DEVICE. */
+CSTONE_API cstone_status cstone_set_lookback_patience(uint32_t waits);
 CSTONE_API cstone_status cstone_sort_autotune(const uint64_t* keys_in, size_t n, uint64_t* keys_out, uint32_t* perm_out,
                                    void* ws, size_t ws_bytes, int reps, float* ms_per_variant, int* chosen,
                                    hipStream_t stream);
@@ -477,7 +482,11 @@ CSTONE_API cstone_status cstone_tune_load(const char* path);
  * its nodes to node_keys / child[node_offsets[s] ...] (child indices relative
  * to the set), and its 23 level offsets to level_offsets[23 s ...].
  * results[s] receives leaf and node counts, rounds and a cstone_status (OK,
- * NONFINITE, CAPACITY, NOT_CONVERGED) for the set.
+ * NONFINITE, CAPACITY, NOT_CONVERGED) for the set, or DEVICE in every set if
+ * a device-side wait gave up (its arrays are then unreliable). Look-back
+ * passes take their tiles in the order their blocks start, so batches (and
+ * single builds) on different streams of one device may run at the same
+ * time.
  */
 typedef struct cstone_set {
     uint64_t n;             /* particles, 0 allowed */
@@ -522,6 +531,15 @@ CSTONE_API cstone_status cstone_batch_set_rounds(cstone_batch* plan, uint32_t ro
 /* Copy the plan's tables into the workspace (device, layout.workspace_bytes).
  * Synchronises `stream`; needed once before building with that workspace. */
 CSTONE_API cstone_status cstone_batch_upload(const cstone_batch* plan, void* ws, size_t ws_bytes, hipStream_t stream);
+/* The same copy without a host synchronisation: the tables are packed into
+ * `host_stage` (host memory of at least cstone_batch_table_bytes(plan) bytes,
+ * page-locked so that the copy is asynchronous: hipHostMalloc) in their
+ * workspace layout and copied with one asynchronous transfer on `stream`.
+ * The caller keeps host_stage unchanged until the stream has passed the copy.
+ * Errors: INVALID_ARG (a null pointer, a workspace or stage too small). */
+CSTONE_API size_t cstone_batch_table_bytes(const cstone_batch* plan);
+CSTONE_API cstone_status cstone_batch_upload_staged(const cstone_batch* plan, void* ws, size_t ws_bytes, void* host_stage,
+                                                    size_t stage_bytes, hipStream_t stream);
 /* Enqueue the whole batched build on `stream`; no host synchronisation, no
  * allocation, so it may be captured. Device arrays as in the layout above. */
 CSTONE_API cstone_status cstone_batch_build(const cstone_batch* plan, const double* x, const double* y, const double* z,

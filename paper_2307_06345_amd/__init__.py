@@ -86,7 +86,8 @@ def _load() -> ctypes.CDLL:
         "cstone_link_octree_by_sort": (i32, [P, sz, P, P, P, P, sz, P]),
         "cstone_sort_variant_count": (i32, []),
         "cstone_sort_variant_info": (i32, [i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
-        "cstone_sort_variant_layout": (i32, [i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "cstone_sort_variant_split": (i32, [i32, ctypes.POINTER(i32)]),
+        "cstone_set_lookback_patience": (i32, [u32]),
         "cstone_sort_autotune": (i32, [P, sz, P, P, P, sz, i32, ctypes.POINTER(ctypes.c_float),
                                        ctypes.POINTER(i32), P]),
         "cstone_radix_tree": (i32, [P, sz, P, P, P, P, P]),
@@ -121,6 +122,8 @@ def _load() -> ctypes.CDLL:
         "cstone_batch_set_variant": (i32, [P, i32]),
         "cstone_batch_set_rounds": (i32, [P, u32]),
         "cstone_batch_upload": (i32, [P, P, sz, P]),
+        "cstone_batch_table_bytes": (sz, [P]),
+        "cstone_batch_upload_staged": (i32, [P, P, sz, P, sz, P]),
         "cstone_batch_build": (i32, [P] + [P] * 11 + [P, sz, P]),
         "cstone_batch_capture": (i32, [P] + [P] * 11 + [P, sz, P]),
         "cstone_batch_launch": (i32, [P, P]),
@@ -590,13 +593,21 @@ def sort_variants() -> list:
     return out
 
 
-def sort_variant_layouts() -> list:
-    """(XCD grouping, split sort 0/1) of every compiled sort shape."""
+def set_lookback_patience(waits: int):
+    """Look-back waits before a sort block counts a missing predecessor
+    tile's digits itself (default 256; 0 sends every wait to that fallback).
+    Applies to later launches on the current device."""
+    _check(_lib.cstone_set_lookback_patience(int(waits)), "cstone_set_lookback_patience")
+
+
+def sort_variant_splits() -> list:
+    """Whether each compiled sort shape takes the split sort (1) or plain LSD
+    passes (0) for particle keys."""
     out = []
     for v in range(_lib.cstone_sort_variant_count()):
-        xg, sp = ctypes.c_int(), ctypes.c_int()
-        _check(_lib.cstone_sort_variant_layout(v, ctypes.byref(xg), ctypes.byref(sp)), "cstone_sort_variant_layout")
-        out.append((xg.value, sp.value))
+        sp = ctypes.c_int()
+        _check(_lib.cstone_sort_variant_split(v, ctypes.byref(sp)), "cstone_sort_variant_split")
+        out.append(sp.value)
     return out
 
 
@@ -650,6 +661,91 @@ def tune_load(path: str):
 SET_RESULT_FIELDS = ("n_leaves", "n_nodes", "rounds", "status")
 
 
+class BatchArena:
+    """Device buffers for batched builds, reusable across plans: a batch takes
+    views of the first elements it needs. `need` gives the element counts of
+    a plan: particles, leaf slots, node slots, sets, workspace bytes."""
+
+    _GROUPS = (("sorted_keys", "perm"), ("leaves", "counts"), ("node_keys", "child"), ("level_offsets", "results"),
+               ("ws",))
+
+    def __init__(self, device, need):
+        self.device = torch.device(device)
+        self.cap = (0, 0, 0, 0, 0)
+        self.grow(need)
+
+    def _alloc(self, group: int, c: int):
+        dev = self.device
+        if group == 0:
+            self.sorted_keys = torch.empty(c, dtype=torch.int64, device=dev)
+            self.perm = torch.empty(c, dtype=torch.int32, device=dev)
+        elif group == 1:
+            self.leaves = torch.empty(c, dtype=torch.int64, device=dev)
+            self.counts = torch.empty(c, dtype=torch.int32, device=dev)
+        elif group == 2:
+            self.node_keys = torch.empty(c, dtype=torch.int64, device=dev)
+            self.child = torch.empty(c, dtype=torch.int32, device=dev)
+        elif group == 3:
+            self.level_offsets = torch.empty(c * LEVEL_OFFSETS, dtype=torch.int32, device=dev)
+            self.results = torch.empty(c * 4, dtype=torch.int32, device=dev)
+        else:
+            self.ws = _workspace(c, dev)
+
+    def grow(self, want):
+        """Make every buffer hold at least `want` (same order as a need):
+        only the buffers that are too small are reallocated (their contents
+        are not kept)."""
+        caps = list(self.cap)
+        for g, v in enumerate(want):
+            v = max(int(v), 256 if g == 4 else 1)
+            if v > caps[g]:
+                for name in self._GROUPS[g]:  # free first, so the old and new buffers are not held together
+                    setattr(self, name, None)
+                self._alloc(g, v)
+                caps[g] = v
+        self.cap = tuple(caps)
+
+    @staticmethod
+    def need(layout) -> tuple:
+        return (int(layout.n_particles), int(layout.leaf_slots), int(layout.node_slots), int(layout.n_sets),
+                int(layout.workspace_bytes))
+
+    @staticmethod
+    def bytes_of(need) -> int:
+        n, leaf, node, sets, ws = (max(int(v), 1) for v in need)
+        return 12 * n + 12 * leaf + 12 * node + sets * (4 * LEVEL_OFFSETS + 16) + max(ws, 256)
+
+    @property
+    def nbytes(self) -> int:
+        return self.bytes_of(self.cap)
+
+    def fits(self, need) -> bool:
+        return all(max(int(v), 1) <= c for v, c in zip(need, self.cap))
+
+    def views(self, need):
+        n, leaf, node, sets, ws = (max(int(v), 1) for v in need)
+        return (self.sorted_keys[:n], self.perm[:n], self.leaves[:leaf], self.counts[:leaf], self.node_keys[:node],
+                self.child[:node], self.level_offsets[:sets * LEVEL_OFFSETS], self.results[:sets * 4],
+                self.ws[:max(ws, 256)])
+
+
+def batch_layout(sets) -> BatchLayout:
+    """The layout a Batch of these sets would have (host-side plan only)."""
+    arr = (CSet * max(len(sets), 1))()
+    for i, spec in enumerate(sets):
+        n, box, curve, n_crit = spec[:4]
+        cap = spec[4] if len(spec) > 4 else 0
+        arr[i] = CSet(int(n), Box.of(box), int(curve), int(n_crit), int(cap))
+    plan = ctypes.c_void_p()
+    _check(_lib.cstone_batch_create(arr, len(sets), ctypes.byref(plan)), "cstone_batch_create")
+    try:
+        lay = BatchLayout()
+        _check(_lib.cstone_batch_get_layout(plan, ctypes.byref(lay), None, None, None), "cstone_batch_get_layout")
+    finally:
+        _lib.cstone_batch_destroy(plan)
+    return lay
+
+
 class Batch:
     """A planned batch of independent particle sets and every device buffer
     its build needs (allocated once here; building allocates nothing).
@@ -659,7 +755,13 @@ class Batch:
     self.particle_offsets); build() enqueues the whole batch, capture() records
     it into a hipGraph that launch() replays."""
 
-    def __init__(self, sets, device="cuda"):
+    def __init__(self, sets, device="cuda", arena=None, stage=None):
+        """arena: optional BatchArena whose buffers this batch uses (views)
+        instead of allocating its own, or a callable that takes the plan's
+        needs (BatchArena.need) and returns such an arena large enough.
+        stage: optional callable that takes the tables' size in bytes and
+        returns a pinned uint8 host tensor at least that large; the tables
+        then go up asynchronously through it (see upload)."""
         self.device = torch.device(device)
         arr = (CSet * max(len(sets), 1))()
         for i, spec in enumerate(sets):
@@ -673,17 +775,18 @@ class Batch:
         self._refresh_layout()
         lay = self.layout
         dev = self.device
-        n = max(int(lay.n_particles), 1)
-        self.sorted_keys = torch.empty(n, dtype=torch.int64, device=dev)
-        self.perm = torch.empty(n, dtype=torch.int32, device=dev)
-        self.leaves = torch.empty(max(int(lay.leaf_slots), 1), dtype=torch.int64, device=dev)
-        self.counts = torch.empty(max(int(lay.leaf_slots), 1), dtype=torch.int32, device=dev)
-        self.node_keys = torch.empty(max(int(lay.node_slots), 1), dtype=torch.int64, device=dev)
-        self.child = torch.empty(max(int(lay.node_slots), 1), dtype=torch.int32, device=dev)
-        self.level_offsets = torch.empty(max(self.n_sets, 1) * LEVEL_OFFSETS, dtype=torch.int32, device=dev)
-        self.results = torch.zeros(max(self.n_sets, 1) * 4, dtype=torch.int32, device=dev)
-        self.ws = _workspace(lay.workspace_bytes, dev)
-        self.upload()
+        need = BatchArena.need(lay)
+        if callable(arena):
+            arena = arena(need)
+        if arena is not None:
+            assert arena.fits(need), "the arena is smaller than this batch"
+            views = arena.views(need)
+        else:
+            views = BatchArena(dev, need).views(need)
+        (self.sorted_keys, self.perm, self.leaves, self.counts, self.node_keys, self.child, self.level_offsets,
+         self.results, self.ws) = views
+        self.results.zero_()  # (a reused arena holds an earlier batch's results)
+        self.upload(stage=stage(self.table_bytes) if stage is not None else None)
 
     def _refresh_layout(self):
         lay = BatchLayout()
@@ -697,7 +800,7 @@ class Batch:
 
     def __del__(self):
         plan = getattr(self, "_plan", None)
-        if plan is not None and plan.value:
+        if plan is not None and plan.value and _lib is not None:  # (None once the interpreter is shutting down)
             _lib.cstone_batch_destroy(plan)
             self._plan = None
 
@@ -720,9 +823,22 @@ class Batch:
         _check(_lib.cstone_batch_set_rounds(self._plan, int(rounds)), "cstone_batch_set_rounds")
         self._refresh_layout()
 
-    def upload(self, stream=None):
-        _check(_lib.cstone_batch_upload(self._plan, _ptr(self.ws), self.ws.numel(), _stream(stream)),
-               "cstone_batch_upload")
+    def upload(self, stream=None, stage=None):
+        """Copy the plan's tables into the workspace. With `stage` (a pinned
+        uint8 host tensor of at least table_bytes) the copy is asynchronous on
+        the stream, and the stage must stay unchanged until the stream has
+        passed it; without, the call synchronises the stream."""
+        if stage is None:
+            _check(_lib.cstone_batch_upload(self._plan, _ptr(self.ws), self.ws.numel(), _stream(stream)),
+                   "cstone_batch_upload")
+            return
+        assert stage.is_pinned() and stage.dtype == torch.uint8
+        _check(_lib.cstone_batch_upload_staged(self._plan, _ptr(self.ws), self.ws.numel(), _ptr(stage), stage.numel(),
+                                               _stream(stream)), "cstone_batch_upload_staged")
+
+    @property
+    def table_bytes(self) -> int:
+        return int(_lib.cstone_batch_table_bytes(self._plan))
 
     def _args(self, x, y, z):
         for t in (x, y, z):

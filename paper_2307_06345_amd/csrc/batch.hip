@@ -58,6 +58,7 @@ struct BatchWs {
     void* stage;  // the sort's workspace, then the rebalance's and the link's
     size_t stage_bytes;
     size_t bytes;
+    size_t off_tiles, off_seg_base, tables_end;  // byte offsets of the plan tables (sets start at 0)
 };
 
 size_t stage_bytes_for(const cstone_batch& p) {
@@ -75,9 +76,12 @@ BatchWs carve_batch(const cstone_batch& p, void* ws) {
     Carve c(ws);
     BatchWs w{};
     w.sets = c.take<BatchSet>(p.sets.size());
+    w.off_tiles = c.off;
     w.tiles = c.take<uint4>(p.max_tiles);
+    w.off_seg_base = c.off;
     w.seg_base = c.take<uint32_t>(p.sets.size());
-    w.flags = c.take<uint32_t>(p.sets.size());
+    w.tables_end = w.off_seg_base + p.sets.size() * sizeof(uint32_t);
+    w.flags = c.take<uint32_t>(p.sets.size() + 1);  // per set, then the sort's device-wait error word
     w.keys = c.take<uint64_t>(p.n_total);
     w.stage_bytes = stage_bytes_for(p);
     w.stage = c.take<uint8_t>(w.stage_bytes);
@@ -134,8 +138,9 @@ cstone_status enqueue_build(const cstone_batch& p, const double* x, const double
     if (ns == 0) return CSTONE_OK;
     const uint32_t nt = static_cast<uint32_t>(p.tiles.size());
     cstone_status st;
-    hipLaunchKernelGGL(fill_u32_kernel, dim3((ns + 255) / 256), dim3(256), 0, stream, w.flags,
-                       static_cast<size_t>(ns), 0u);
+    uint32_t* sort_err = w.flags + ns;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((ns + 256) / 256), dim3(256), 0, stream, w.flags,
+                       static_cast<size_t>(ns) + 1, 0u);
     if (p.n_total) {
         if ((st = sort_seg_prepare(w.stage, p.n_total, nt, ns, p.variant, stream)) != CSTONE_OK) return st;
         uint32_t stride = 0, mask = 0, shift = 0;
@@ -144,14 +149,14 @@ cstone_status enqueue_build(const cstone_batch& p, const double* x, const double
                                     stream)) != CSTONE_OK)
             return st;
         if ((st = launch_sort_segmented(w.keys, sorted_keys, perm, p.n_total, w.tiles, nt, w.seg_base, ns,
-                                        p.max_set, 63, p.variant, w.stage, w.stage_bytes, stream)) != CSTONE_OK)
+                                        p.max_set, 63, p.variant, w.stage, w.stage_bytes, stream, sort_err)) !=
+            CSTONE_OK)
             return st;
     }
     const size_t rb = batch_rebalance_workspace_bytes(ns, p.entries, p.split_capacity);
     if ((st = launch_batch_rebalance(sorted_keys, p.n_total, w.sets, ns, p.entries, p.split_capacity, p.rounds, w.flags,
-                                     leaves,
-                                     counts, reinterpret_cast<BatchResult*>(results), rebalance_ws(w), rb,
-                                     stream)) != CSTONE_OK)
+                                     leaves, counts, reinterpret_cast<BatchResult*>(results), rebalance_ws(w), rb,
+                                     sort_err, stream)) != CSTONE_OK)
         return st;
     const BatchTreeView view = batch_rebalance_view(rebalance_ws(w), ns, p.entries, p.split_capacity);
     return launch_link_batch(view, w.sets, ns, p.entries, node_keys, child, level_offsets, link_ws(p, w),
@@ -292,6 +297,27 @@ CSTONE_API cstone_status cstone_batch_upload(const cstone_batch* p, void* ws, si
     return CSTONE_OK;
 }
 
+CSTONE_API size_t cstone_batch_table_bytes(const cstone_batch* p) {
+    return p ? cs::carve_batch(*p, nullptr).tables_end : 0;
+}
+
+CSTONE_API cstone_status cstone_batch_upload_staged(const cstone_batch* p, void* ws, size_t ws_bytes, void* host_stage,
+                                                    size_t stage_bytes, hipStream_t stream) {
+    if (!p) return CSTONE_ERR_INVALID_ARG;
+    const cs::BatchWs w = cs::carve_batch(*p, ws);
+    if (!ws || ws_bytes < w.bytes || !host_stage || stage_bytes < w.tables_end) return CSTONE_ERR_INVALID_ARG;
+    // the tables in their device layout, so one copy moves them all (the
+    // gaps between them are copied too and never read)
+    char* h = static_cast<char*>(host_stage);
+    if (!p->sets.empty()) {
+        std::memcpy(h, p->sets.data(), p->sets.size() * sizeof(BatchSet));
+        std::memcpy(h + w.off_seg_base, p->seg_base.data(), p->seg_base.size() * sizeof(uint32_t));
+    }
+    if (!p->tiles.empty()) std::memcpy(h + w.off_tiles, p->tiles.data(), p->tiles.size() * sizeof(uint4));
+    if (w.tables_end) CS_HIP(hipMemcpyAsync(ws, host_stage, w.tables_end, hipMemcpyHostToDevice, stream));
+    return CSTONE_OK;
+}
+
 CSTONE_API cstone_status cstone_batch_build(const cstone_batch* p, const double* x, const double* y, const double* z,
                                             uint64_t* sorted_keys, uint32_t* perm, uint64_t* leaves, uint32_t* counts,
                                             uint64_t* node_keys, uint32_t* child, uint32_t* level_offsets,
@@ -389,10 +415,11 @@ CSTONE_API cstone_status cstone_sort_variant_info(int variant, int* digit_bits, 
     return CSTONE_OK;
 }
 
-CSTONE_API cstone_status cstone_sort_variant_layout(int variant, int* xcd_group, int* split) {
+CSTONE_API cstone_status cstone_set_lookback_patience(uint32_t waits) { return cs::set_lookback_patience(waits); }
+
+CSTONE_API cstone_status cstone_sort_variant_split(int variant, int* split) {
     if (variant < 0 || variant >= cs::sort_variant_count()) return CSTONE_ERR_INVALID_ARG;
     const cs::SortVariantInfo v = cs::sort_variant_info(variant);
-    if (xcd_group) *xcd_group = v.xcd_group;
     if (split) *split = v.split;
     return CSTONE_OK;
 }

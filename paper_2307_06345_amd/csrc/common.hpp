@@ -69,7 +69,7 @@ template <class T, int BLOCK>
 __device__ __forceinline__ T block_exclusive_sum(T v, T* lds, T* total) {
     constexpr int W = BLOCK / kWave;
     const uint32_t lane = lane_id();
-    const uint32_t wave = threadIdx.x / kWave;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
     T inc = wave_inclusive_sum(v);
     if (lane == kWave - 1) lds[wave] = inc;
     __syncthreads();
@@ -222,22 +222,6 @@ __device__ __forceinline__ uint32_t wave_lower_bound(const uint64_t* a, uint32_t
 // running block (forward progress for the look-back).
 __device__ __forceinline__ uint32_t take_tile(uint32_t* counter, uint32_t* lds_slot) {
     if (threadIdx.x == 0) *lds_slot = atomicAdd(counter, 1u);
-    __syncthreads();
-    uint32_t t = *lds_slot;
-    __syncthreads();
-    return t;
-}
-
-// Grouped dynamic tile index: blocks of group g (block index mod the number
-// of groups) take tiles g, g + groups, g + 2 groups, ... in order from their
-// group's counter (counter + g * stride), so the same-address atomics of one
-// counter are spread over the groups. A tile's predecessor belongs to a group
-// that has a resident block and takes its tiles in order (look-back progress).
-__device__ __forceinline__ uint32_t take_group_tile(uint32_t* counter, uint32_t stride, uint32_t groups,
-                                                    uint32_t* lds_slot) {
-    const uint32_t g_count = min(groups, gridDim.x);
-    const uint32_t g = blockIdx.x % g_count;
-    if (threadIdx.x == 0) *lds_slot = atomicAdd(counter + g * stride, 1u) * g_count + g;
     __syncthreads();
     uint32_t t = *lds_slot;
     __syncthreads();

@@ -96,8 +96,9 @@ cstone_status launch_keys_batch(const double* x, const double* y, const double* 
 // set, set}, never straddling two sets; seg_base[s] = first key of set s.
 // Permutation values are relative to the set's first key.
 struct SortVariantInfo {
-    int bits, block, items, tile, xcd_group, split;
+    int bits, block, items, tile, split;
 };
+cstone_status set_lookback_patience(uint32_t waits);
 int sort_variant_count();
 SortVariantInfo sort_variant_info(int variant);
 int sort_builtin_variant();  // the shape used where the autotune table has no entry
@@ -118,7 +119,7 @@ uint32_t* sort_seg_first_histogram(void* ws, size_t n_total, size_t n_tiles, uin
 cstone_status launch_sort_segmented(const uint64_t* keys_in, uint64_t* keys_out, uint32_t* perm_out,
                                     size_t n_total, const uint4* tiles, uint32_t n_tiles, const uint32_t* seg_base,
                                     uint32_t n_sets, size_t max_set, int sig_bits, int variant, void* ws,
-                                    size_t ws_bytes, hipStream_t stream);
+                                    size_t ws_bytes, hipStream_t stream, uint32_t* err_word = nullptr);
 
 // props.hip — particle counts of every node of a linked octree; gather of
 // particle arrays by the sort permutation (separate passes, or one fused pass
@@ -162,9 +163,9 @@ cstone_status launch_node_counts(const uint64_t* sorted_keys, size_t n, const ui
 size_t rebalance_workspace_bytes(size_t n, uint32_t n_crit, size_t leaf_capacity);
 
 constexpr int kMaxRounds = 64;
-// Tiles of a round are taken from kTileGroups counters (group g = block mod
-// groups takes tiles g, g + groups, ...), each in a 128-byte line of its own.
-constexpr int kTileGroups = 8;
+// Tiles of a round are taken in order from one counter per round (each in a
+// 128-byte line of its own), so that every tile a block waits for in the
+// round's look-back is held by a running block.
 constexpr int kCounterWords = 32;
 
 // Device-side loop state: the part the host reads after a batch of rounds ...
@@ -186,7 +187,7 @@ struct LoopHeader {
 
 // ... and, after it and never copied to the host, the tile counters of every round.
 struct LoopState : LoopHeader {
-    alignas(128) uint32_t counters[kMaxRounds][kTileGroups * kCounterWords];
+    alignas(128) uint32_t counters[kMaxRounds][kCounterWords];
 };
 
 // The rebalance loop, driven from the device: rounds are enqueued ahead of
@@ -240,7 +241,8 @@ size_t batch_rebalance_workspace_bytes(uint32_t n_sets, size_t entry_capacity, s
 cstone_status launch_batch_rebalance(const uint64_t* P, size_t n_total, const BatchSet* sets, uint32_t n_sets,
                                      size_t entry_capacity, size_t split_capacity, uint32_t rounds,
                                      const uint32_t* set_flags, uint64_t* leaves, uint32_t* counts,
-                                     BatchResult* results, void* ws, size_t ws_bytes, hipStream_t stream);
+                                     BatchResult* results, void* ws, size_t ws_bytes, const uint32_t* sort_err,
+                                     hipStream_t stream);
 // The final back-to-back arrays, for the batched link.
 struct BatchTreeView {
     const uint64_t* K[2];

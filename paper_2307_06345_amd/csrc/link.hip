@@ -133,7 +133,7 @@ __global__ __launch_bounds__(kBfBlock) void bf_count_kernel(const uint64_t* __re
     __shared__ uint32_t wtot[kLevels][kBfWaves];
     const size_t nl = nl_dev ? *nl_dev : nl_host;
     const uint32_t tiles = static_cast<uint32_t>((nl + kBfTile - 1) / kBfTile);
-    const uint32_t wave = threadIdx.x / kWave;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
     for (uint32_t tile = blockIdx.x; tile < tiles && tile < stride; tile += gridDim.x) {
         const LeafLevels r = leaf_levels(K, nl, static_cast<size_t>(tile) * kBfTile + threadIdx.x * kBfItems);
 #pragma unroll
@@ -184,7 +184,7 @@ __global__ __launch_bounds__(kBfBlock) void bf_write_kernel(const uint64_t* __re
     const size_t n = nl + (nl - 1) / 7;
     const uint32_t tiles = static_cast<uint32_t>((nl + kBfTile - 1) / kBfTile);
     const uint32_t tid = threadIdx.x;
-    const uint32_t wave = tid / kWave;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid / kWave);  // wave-uniform
     if (tid < kWave) {  // LO: exclusive scan of the level totals
         const uint32_t v = tid < kLevels ? totals[tid] : 0u;
         const uint32_t inc = wave_inclusive_sum(v);
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(kBfBlock) void batch_bf_count_kernel(BatchTreeView 
     __shared__ uint32_t wtot[kLevels][kBfWaves];
     const BatchSrc src = batch_src(view);
     const uint32_t tiles = static_cast<uint32_t>((src.M + kBfTile - 1) / kBfTile);
-    const uint32_t wave = threadIdx.x / kWave;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
     for (uint32_t tile = blockIdx.x; tile < tiles && tile < stride; tile += gridDim.x) {
         const LeafLevels r =
             entry_levels(src.K, src.M, static_cast<size_t>(tile) * kBfTile + threadIdx.x * kBfItems);
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(kBfBlock) void batch_bf_base_kernel(BatchTreeView v
                                                                  uint32_t* __restrict__ rel,
                                                                  uint32_t* __restrict__ level_offsets) {
     const BatchSrc src = batch_src(view);
-    const uint32_t s = blockIdx.x * kBfWaves + threadIdx.x / kWave;
+    const uint32_t s = blockIdx.x * kBfWaves + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     if (s >= n_sets || src.M == 0) return;
     uint32_t g0[kLevels], g1[kLevels];
     running_counts(src, tile_offsets, stride, totals, src.starts[s], g0);
@@ -352,7 +352,7 @@ __global__ __launch_bounds__(kBfBlock) void batch_bf_write_kernel(BatchTreeView 
     const BatchSrc src = batch_src(view);
     const uint32_t tiles = static_cast<uint32_t>((src.M + kBfTile - 1) / kBfTile);
     const uint32_t tid = threadIdx.x;
-    const uint32_t wave = tid / kWave;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid / kWave);  // wave-uniform
     for (uint32_t tile = blockIdx.x; tile < tiles && tile < stride; tile += gridDim.x) {
         const size_t first = static_cast<size_t>(tile) * kBfTile + tid * kBfItems;
         const LeafLevels r = entry_levels(src.K, src.M, first);

@@ -70,7 +70,7 @@ __device__ __forceinline__ void loop_init_part(size_t t, size_t stride, LoopStat
         st->changed[t] = 0;
         st->merged[t] = 0;
         st->over[t] = 0;
-        for (int g = 0; g < kTileGroups; ++g) st->counters[t][g * kCounterWords] = 0;
+        st->counters[t][0] = 0;
         st->nsplit[t] = 0;
     }
     if (t <= kMaxRounds) st->nl[t] = t == 0 ? nl0 : 0;
@@ -112,7 +112,7 @@ constexpr uint32_t kCoarseNodes = 1u << (3 * kStartCoarse);  // 512
 
 __global__ __launch_bounds__(256) void start_coarse_kernel(const uint64_t* __restrict__ P, uint32_t n,
                                                            uint32_t* __restrict__ posc) {
-    const uint32_t w = blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
+    const uint32_t w = blockIdx.x * (256 / kWave) + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     if (w > kCoarseNodes) return;  // whole waves
     const uint64_t key = static_cast<uint64_t>(w) << (3 * (kL - kStartCoarse));  // w = 512: 8^21
     const uint32_t at = wave_lower_bound(P, 0, n, key);
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(kRBlock) void round_kernel(uint32_t n, uint32_t n_c
     }
 
     for (;;) {
-        const uint32_t tile = take_group_tile(st->counters[round], kCounterWords, kTileGroups, &slot);
+        const uint32_t tile = take_tile(st->counters[round], &slot);
         if (tile >= tiles) break;
         const int64_t base = static_cast<int64_t>(tile) * kRTile;
         for (int j = tid; j < kRSpan; j += kRBlock) {  // K and positions of entries base-8 .. base+kRTile+7
@@ -481,7 +481,7 @@ __global__ __launch_bounds__(kSearchBlock) void split_search_kernel(const uint64
     const uint32_t lane = lane_id();
     const uint32_t t = lane & 7u;  // child boundary t (1..7) of the group's split
     const uint32_t waves = gridDim.x * (kSearchBlock / kWave);
-    const uint32_t wave = blockIdx.x * (kSearchBlock / kWave) + threadIdx.x / kWave;
+    const uint32_t wave = blockIdx.x * (kSearchBlock / kWave) + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     if (static_cast<uint64_t>(listed) * 7u <= waves) {  // one search per wave (wave-uniform branch)
         for (uint32_t w = wave; w < listed * 7u; w += waves) {
             const uint64_t e = splits[w / 7u];
@@ -866,7 +866,7 @@ __global__ __launch_bounds__(256) void batch_init_kernel(LoopState* st, const Ba
         st->changed[t] = 0;
         st->merged[t] = 0;
         st->over[t] = 0;
-        for (int g = 0; g < kTileGroups; ++g) st->counters[t][g * kCounterWords] = 0;
+        st->counters[t][0] = 0;
         st->nsplit[t] = 0;
     }
     if (t <= kMaxRounds) st->nl[t] = t == 0 ? 2ull * n_sets : 0ull;
@@ -913,7 +913,7 @@ __global__ __launch_bounds__(kBBlock, 4) void batch_round_kernel(const BatchSet*
     if (tid == 0) any_change = 0;
 
     for (;;) {
-        const uint32_t tile = take_group_tile(st->counters[round], kCounterWords, kTileGroups, &slot);
+        const uint32_t tile = take_tile(st->counters[round], &slot);
         if (tile >= tiles) break;
         const int64_t base = static_cast<int64_t>(tile) * kBTile;
         for (int j = tid; j < kBSpan; j += kBBlock) {  // coalesced: entries base-8 .. base+kBTile+7 that exist
@@ -1082,7 +1082,8 @@ __global__ __launch_bounds__(256) void batch_finalize_kernel(LoopState* st, uint
                                                              const uint32_t* __restrict__ changed_set,
                                                              const uint32_t* __restrict__ set_flags,
                                                              uint64_t* __restrict__ leaves, uint32_t* __restrict__ counts,
-                                                             BatchResult* __restrict__ results) {
+                                                             BatchResult* __restrict__ results,
+                                                             const uint32_t* __restrict__ sort_err) {
     const Outcome o = loop_outcome(st, enqueued, capacity, false);  // batched rounds do not record merges
     const uint64_t M = o.nl <= capacity ? o.nl : 0;
     const bool odd = o.last & 1u;
@@ -1111,7 +1112,11 @@ __global__ __launch_bounds__(256) void batch_finalize_kernel(LoopState* st, uint
                 converged = true;
                 break;
             }
-        if (set_flags[s] & CSTONE_FLAG_NONFINITE)
+        // a device-side wait that gave up (in the sort or a round's look-back)
+        // leaves every set's arrays unreliable
+        if (st->err != 0 || (sort_err && *sort_err != 0))
+            status = CSTONE_ERR_DEVICE;
+        else if (set_flags[s] & CSTONE_FLAG_NONFINITE)
             status = CSTONE_ERR_NONFINITE;
         else if (M == 0 || nl > sets[s].cap)
             status = CSTONE_ERR_CAPACITY;
@@ -1174,7 +1179,7 @@ cstone_status launch_batch_rebalance(const uint64_t* P, size_t n_total, const Ba
                                      size_t C,
                                      size_t split_capacity, uint32_t rounds, const uint32_t* set_flags,
                                      uint64_t* leaves, uint32_t* counts, BatchResult* results, void* ws,
-                                     size_t ws_bytes, hipStream_t stream) {
+                                     size_t ws_bytes, const uint32_t* sort_err, hipStream_t stream) {
     BatchRebalanceWs w = carve_batch_rebalance(ws, n_sets, C, split_capacity);
     if (ws_bytes < w.bytes) return CSTONE_ERR_INVALID_ARG;
     if (n_sets == 0) return CSTONE_OK;
@@ -1199,7 +1204,8 @@ cstone_status launch_batch_rebalance(const uint64_t* P, size_t n_total, const Ba
     }
     hipLaunchKernelGGL(batch_finalize_kernel, dim3(clamp_grid(grid_1d(C + 1, 256))), dim3(256), 0, stream, w.st,
                        rounds, static_cast<uint64_t>(C), sets, n_sets, w.K[0], w.K[1], w.pos[0], w.pos[1], w.sid[0],
-                       w.sid[1], w.starts[0], w.starts[1], w.changed_set, set_flags, leaves, counts, results);
+                       w.sid[1], w.starts[0], w.starts[1], w.changed_set, set_flags, leaves, counts, results,
+                       sort_err);
     CS_HIP(hipGetLastError());
     return CSTONE_OK;
 }

@@ -107,6 +107,11 @@ struct Lb32 {
     __device__ static void store(word* p, word w) {
         __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    // store w if the word still holds `seen`
+    __device__ static void replace(word* p, word seen, word w) {
+        __hip_atomic_compare_exchange_strong(p, &seen, w, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+    }
 };
 struct Lb64 {
     using word = uint64_t;
@@ -120,19 +125,22 @@ struct Lb64 {
     __device__ static uint64_t value(word w) { return w & kValueMask; }
     __device__ static word load(const word* p) { return ld_agent(p); }
     __device__ static void store(word* p, word w) { st_agent(p, w); }
+    __device__ static void replace(word* p, word seen, word w) {
+        __hip_atomic_compare_exchange_strong(p, &seen, w, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+    }
 };
 
-// Exclusive prefix of one digit over the tiles before `tile` (rows of `radix`
-// words). WIN predecessors are read per round trip, nearest first; the walk
-// stops at the first inclusive prefix and waits at the first empty word.
+// Walk of one digit's exclusive prefix back over the tiles before this one
+// (rows of `radix` words): from tile p down to `first`, WIN predecessors per
+// round trip, nearest first, summing aggregates into excl until an inclusive
+// prefix. Returns true when the prefix is complete; false when the word of
+// tile p was still empty after `patience` waits (p and excl keep the progress,
+// so a later call resumes there).
 template <class LB, int WIN>
-__device__ __forceinline__ uint64_t digit_lookback(const typename LB::word* col, uint32_t radix, uint32_t tile,
-                                                   uint32_t first, uint32_t epoch, uint32_t* err) {
-    // tiles first .. tile-1 precede this one in its segment; `first` published an inclusive prefix
-    uint64_t excl = 0;
-    uint32_t spins = 0;
-    const int64_t lo = first;
-    int64_t p = static_cast<int64_t>(tile) - 1;
+__device__ __forceinline__ bool digit_lookback_step(const typename LB::word* col, uint32_t radix, int64_t lo,
+                                                    uint32_t epoch, uint32_t patience, int64_t& p, uint64_t& excl) {
+    uint32_t waits = 0;
     while (p >= lo) {
         typename LB::word w[WIN];
 #pragma unroll
@@ -150,16 +158,13 @@ __device__ __forceinline__ uint64_t digit_lookback(const typename LB::word* col,
             if (f == 2) done = true;
             --p;
         }
-        if (done) break;
+        if (done) return true;
         if (stalled) {
-            if (++spins > kSpinLimit) {
-                atomicOr(err, kErrSpin);
-                break;
-            }
+            if (++waits > patience) return false;
             __builtin_amdgcn_s_sleep(1);
         }
     }
-    return excl;
+    return true;
 }
 
 template <int BITS>
@@ -192,6 +197,30 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid) {
 template <int BLOCK, int ITEMS>
 constexpr int kMinBlocks = (BLOCK <= 512 && BLOCK * ITEMS * 8 <= 72 * 1024 ? 2 : 1) * BLOCK / (4 * kWave);
 
+// Tile of block b. Blocks are dealt to the 8 XCDs in turn; every XCD takes
+// kXcdGroup consecutive tiles of each round of 8 kXcdGroup blocks, so that
+// where one tile's run of a digit ends and the next tile's run begins (a
+// partly written 64-byte segment) both writes meet in the same L2. The last,
+// incomplete round keeps tile = block. A tile may then wait on a tile whose
+// block has not started: each XCD starts its own share of the grid, at its
+// own pace, and kernels on other streams may hold an XCD full. Such a wait
+// does not depend on that block: after a while the waiting block counts the
+// missing tile's digits itself (the look-back's fallback).
+constexpr uint32_t kXcdGroup = 8;
+// Waits (each one look-back round trip and a short sleep) before a block counts
+// a missing predecessor tile's digits itself: by default far longer than a
+// started block takes to publish its counts. Settable per device (0 sends
+// every wait to the fallback, which tests use).
+constexpr uint32_t kLookbackPatience = 256;
+__constant__ uint32_t g_lookback_patience = kLookbackPatience;
+
+__device__ __forceinline__ uint32_t tile_of_block(uint32_t b, uint32_t nblocks) {
+    constexpr uint32_t R = 8u * kXcdGroup;
+    if (b >= nblocks / R * R) return b;
+    const uint32_t r = b / R, q = b % R;
+    return (r * 8u + q % 8u) * kXcdGroup + q / 8u;
+}
+
 struct TileDesc {
     uint32_t tile, base, count, first, seg_base;
 };
@@ -203,7 +232,8 @@ __device__ __forceinline__ void onesweep_tile(const TileDesc td, const uint64_t*
                                               const uint32_t* __restrict__ ghist, uint32_t* __restrict__ ghist_next,
                                               uint32_t shift_next, typename LB::word* lb, uint32_t epoch,
                                               uint32_t* err, uint64_t* stage, uint16_t (*whist)[1 << BITS],
-                                              uint32_t* nhist, uint32_t* ddelta, uint64_t* scan_tmp) {
+                                              uint32_t* nhist, uint32_t* ddelta, uint64_t* scan_tmp,
+                                              const uint4* __restrict__ table) {
     constexpr int RADIX = 1 << BITS;
     constexpr int W = BLOCK / kWave;
     constexpr int TILE = BLOCK * ITEMS;
@@ -285,12 +315,52 @@ __device__ __forceinline__ void onesweep_tile(const TileDesc td, const uint64_t*
             v[i] = FIRST ? idx - td.seg_base : ((FULL || idx < end) ? vals_in[idx] : 0u);
         }
     }
-    if (tid < RADIX) {
-        uint64_t excl = 0;
-        if (tile != td.first) {
-            excl = digit_lookback<LB, WIN>(lb + tid, RADIX, tile, td.first, epoch, err);
-            LB::store(lb + static_cast<size_t>(tile) * RADIX + tid, LB::make(2u, epoch, excl + total));
+    // every digit's exclusive prefix over the tiles before this one (one
+    // digit per thread). A walk that has waited g_lookback_patience times on a
+    // tile gets that tile's digit counts from this block instead (the
+    // fallback): the block counts them from the tile's keys and publishes
+    // them as the tile's aggregates, unless the tile's own block has written
+    // its word by then. The counts are the ones that block would publish, so
+    // the result is the same either way, and no wait depends on another block
+    // having started. Each round settles at least one tile, so the loop ends.
+    __shared__ uint32_t help;
+    uint64_t excl = 0;
+    int64_t p = static_cast<int64_t>(tile) - 1;
+    bool done = tid >= static_cast<uint32_t>(RADIX) || tile == td.first;
+    for (uint32_t round = 0;; ++round) {
+        if (!done)
+            done = digit_lookback_step<LB, WIN>(lb + tid, RADIX, td.first, epoch, g_lookback_patience, p, excl);
+        if (!__syncthreads_or(!done)) break;
+        if (round > tile - td.first) {  // never: every round settles a tile
+            if (tid == 0) atomicOr(err, kErrSpin);
+            break;
         }
+        if (tid == 0) help = 0;
+        for (int i = tid; i < RADIX; i += BLOCK) ddelta[i] = 0;  // the helped tile's digit counts
+        __syncthreads();
+        if (!done) atomicMax(&help, static_cast<uint32_t>(p));  // the nearest tile a walk waits on
+        __syncthreads();
+        const uint32_t q = help;
+        uint32_t q_base, q_count;
+        if (table) {
+            const uint4 t = table[q];
+            q_base = t.x;
+            q_count = t.y;
+        } else {
+            q_base = q * static_cast<uint32_t>(TILE);
+            q_count = min(n - q_base, static_cast<uint32_t>(TILE));
+        }
+        for (uint32_t j = tid; j < q_count; j += BLOCK) atomicAdd(&ddelta[digit_of<BITS>(keys_in[q_base + j], shift)], 1u);
+        __syncthreads();
+        if (tid < RADIX) {
+            typename LB::word* w = lb + static_cast<size_t>(q) * RADIX + tid;
+            const typename LB::word seen = LB::load(w);
+            if (LB::flag(seen, epoch) == 0) LB::replace(w, seen, LB::make(1u, epoch, ddelta[tid]));
+        }
+        __syncthreads();  // help and the counts are reused by the next round
+    }
+    if (tid < RADIX) {
+        if (tile != td.first) LB::store(lb + static_cast<size_t>(tile) * RADIX + tid, LB::make(2u, epoch, excl + total));
         // destination of tile-local position j is j + ddelta (mod 2^32; every index is below 2^32)
         ddelta[tid] = td.seg_base + gbase + static_cast<uint32_t>(excl) - lst;
         if (ghist_next && nhist[tid]) atomicAdd(&ghist_next[tid], nhist[tid]);
@@ -332,24 +402,8 @@ __device__ __forceinline__ void onesweep_tile(const TileDesc td, const uint64_t*
     }
 }
 
-// Tile of block b. Blocks are dealt to the 8 XCDs in turn; with XG > 1 every
-// XCD takes XG consecutive tiles in a row, so that where one tile's run of a
-// digit ends and the next tile's run begins (a partly written 64-byte
-// segment) both writes meet in the same L2. A tile then waits only on tiles
-// whose blocks are at most 8 XG - 1 dispatches later: the look-back progresses
-// whenever 8 XG blocks of the pass can be resident. With XG = 8 that is 64 of
-// the 256-512 a CU-filling pass holds, so even several passes sharing the GPU
-// (sorts on other streams) leave one of them enough to finish and free room.
-// The last, incomplete round of 8 XG blocks keeps tile = block.
-template <int XG>
-__device__ __forceinline__ uint32_t tile_of_block(uint32_t b, uint32_t nblocks) {
-    constexpr uint32_t R = 8u * XG;
-    if (XG == 1 || b >= nblocks / R * R) return b;
-    const uint32_t r = b / R, q = b % R;
-    return (r * 8u + q % 8u) * XG + q / 8u;
-}
 
-template <int BITS, int BLOCK, int ITEMS, int WIN, bool FIRST, bool WITH_VALUES, class LB, int XG>
+template <int BITS, int BLOCK, int ITEMS, int WIN, bool FIRST, bool WITH_VALUES, class LB>
 __global__ __launch_bounds__(BLOCK, (kMinBlocks<BLOCK, ITEMS>)) void onesweep_kernel(const uint64_t* __restrict__ keys_in,
                                                           const uint32_t* __restrict__ vals_in,
                                                           uint64_t* __restrict__ keys_out,
@@ -369,9 +423,7 @@ __global__ __launch_bounds__(BLOCK, (kMinBlocks<BLOCK, ITEMS>)) void onesweep_ke
     __shared__ uint32_t ddelta[RADIX];
     __shared__ uint64_t scan_tmp[W];
     const uint32_t tid = threadIdx.x;
-    // tiles follow the block index: the dispatcher starts lower blocks first,
-    // so every tile a block waits for is running or done
-    const uint32_t tile = tile_of_block<XG>(blockIdx.x, gridDim.x);
+    const uint32_t tile = tile_of_block(blockIdx.x, gridDim.x);
     if (lb_clear && tid < RADIX) lb_clear[static_cast<size_t>(tile) * RADIX + tid] = 0;  // rows of the next pass
     for (int i = tid; i < W * RADIX; i += BLOCK) (&whist[0][0])[i] = 0;
     if (tid < RADIX) nhist[tid] = 0;
@@ -380,18 +432,18 @@ __global__ __launch_bounds__(BLOCK, (kMinBlocks<BLOCK, ITEMS>)) void onesweep_ke
     if (td.count == static_cast<uint32_t>(TILE))
         onesweep_tile<BITS, BLOCK, ITEMS, WIN, FIRST, WITH_VALUES, LB, true>(
             td, keys_in, vals_in, keys_out, vals_out, n, shift, ghist, ghist_next, shift_next, lb, epoch, err, stage,
-            whist, nhist, ddelta, scan_tmp);
+            whist, nhist, ddelta, scan_tmp, nullptr);
     else
         onesweep_tile<BITS, BLOCK, ITEMS, WIN, FIRST, WITH_VALUES, LB, false>(
             td, keys_in, vals_in, keys_out, vals_out, n, shift, ghist, ghist_next, shift_next, lb, epoch, err, stage,
-            whist, nhist, ddelta, scan_tmp);
+            whist, nhist, ddelta, scan_tmp, nullptr);
 }
 
 // Segmented pass: many independent key sets in one launch. Block b sorts
 // tile tiles[b] = {first key, key count, first tile of its set, set}; every
 // set has its own digit histograms (ghist + set * hist_stride) and its own
 // look-back chain, and its permutation values count from the set's start.
-template <int BITS, int BLOCK, int ITEMS, int WIN, bool FIRST, bool WITH_VALUES, class LB, int XG>
+template <int BITS, int BLOCK, int ITEMS, int WIN, bool FIRST, bool WITH_VALUES, class LB>
 __global__ __launch_bounds__(BLOCK, (kMinBlocks<BLOCK, ITEMS>)) void onesweep_seg_kernel(const uint64_t* __restrict__ keys_in,
                                                               const uint32_t* __restrict__ vals_in,
                                                               uint64_t* __restrict__ keys_out,
@@ -413,7 +465,7 @@ __global__ __launch_bounds__(BLOCK, (kMinBlocks<BLOCK, ITEMS>)) void onesweep_se
     __shared__ uint32_t ddelta[RADIX];
     __shared__ uint64_t scan_tmp[W];
     const uint32_t tid = threadIdx.x;
-    const uint32_t tile = tile_of_block<XG>(blockIdx.x, gridDim.x);
+    const uint32_t tile = tile_of_block(blockIdx.x, gridDim.x);
     // a tile table written on the device: blocks past its length have nothing to do
     if (live_tiles && tile >= *live_tiles) return;
     const uint4 t = tiles[tile];
@@ -427,11 +479,11 @@ __global__ __launch_bounds__(BLOCK, (kMinBlocks<BLOCK, ITEMS>)) void onesweep_se
     if (td.count == static_cast<uint32_t>(TILE))
         onesweep_tile<BITS, BLOCK, ITEMS, WIN, FIRST, WITH_VALUES, LB, true>(
             td, keys_in, vals_in, keys_out, vals_out, n, shift, gh, gn, shift_next, lb, epoch, err, stage, whist,
-            nhist, ddelta, scan_tmp);
+            nhist, ddelta, scan_tmp, tiles);
     else
         onesweep_tile<BITS, BLOCK, ITEMS, WIN, FIRST, WITH_VALUES, LB, false>(
             td, keys_in, vals_in, keys_out, vals_out, n, shift, gh, gn, shift_next, lb, epoch, err, stage, whist,
-            nhist, ddelta, scan_tmp);
+            nhist, ddelta, scan_tmp, tiles);
 }
 
 // Pass over a tile table written on the device whose length is known only
@@ -478,11 +530,11 @@ __global__ __launch_bounds__(BLOCK, (kMinBlocks<BLOCK, ITEMS>)) void onesweep_li
         if (td.count == static_cast<uint32_t>(TILE))
             onesweep_tile<BITS, BLOCK, ITEMS, WIN, false, true, LB, true>(
                 td, keys_in, vals_in, keys_out, vals_out, n, shift, gh, gn, shift_next, lb, epoch, err, stage, whist,
-                nhist, ddelta, scan_tmp);
+                nhist, ddelta, scan_tmp, tiles);
         else
             onesweep_tile<BITS, BLOCK, ITEMS, WIN, false, true, LB, false>(
                 td, keys_in, vals_in, keys_out, vals_out, n, shift, gh, gn, shift_next, lb, epoch, err, stage, whist,
-                nhist, ddelta, scan_tmp);
+                nhist, ddelta, scan_tmp, tiles);
         __syncthreads();  // shared state and the slot are reused by the next tile
     }
 }
@@ -998,29 +1050,29 @@ struct PassArgs {
     bool wide;  // 64-bit look-back words (n >= 2^30)
 };
 
-template <int BITS, int BLOCK, int ITEMS, int WIN, bool FIRST, bool VALS, int XG>
+template <int BITS, int BLOCK, int ITEMS, int WIN, bool FIRST, bool VALS>
 void launch_one(const PassArgs& a, hipStream_t stream) {
     constexpr uint32_t tile = BLOCK * ITEMS;
     const dim3 grid((a.n + tile - 1) / tile), block(BLOCK);
     if (a.wide)
-        hipLaunchKernelGGL((onesweep_kernel<BITS, BLOCK, ITEMS, WIN, FIRST, VALS, Lb64, XG>), grid, block, 0, stream,
+        hipLaunchKernelGGL((onesweep_kernel<BITS, BLOCK, ITEMS, WIN, FIRST, VALS, Lb64>), grid, block, 0, stream,
                            a.keys_in, a.vals_in, a.keys_out, a.vals_out, a.n, a.shift, a.ghist, a.ghist_next,
                            a.shift_next, static_cast<uint64_t*>(a.lb), nullptr, a.epoch, a.err);
     else
-        hipLaunchKernelGGL((onesweep_kernel<BITS, BLOCK, ITEMS, WIN, FIRST, VALS, Lb32, XG>), grid, block, 0, stream,
+        hipLaunchKernelGGL((onesweep_kernel<BITS, BLOCK, ITEMS, WIN, FIRST, VALS, Lb32>), grid, block, 0, stream,
                            a.keys_in, a.vals_in, a.keys_out, a.vals_out, a.n, a.shift, a.ghist, a.ghist_next,
                            a.shift_next, static_cast<uint32_t*>(a.lb), static_cast<uint32_t*>(a.lb_clear), a.epoch,
                            a.err);
 }
 
-template <int BITS, int BLOCK, int ITEMS, int WIN, int XG>
+template <int BITS, int BLOCK, int ITEMS, int WIN>
 void launch_pass_t(const PassArgs& a, bool first, bool with_values, hipStream_t stream) {
     if (with_values && first)
-        launch_one<BITS, BLOCK, ITEMS, WIN, true, true, XG>(a, stream);
+        launch_one<BITS, BLOCK, ITEMS, WIN, true, true>(a, stream);
     else if (with_values)
-        launch_one<BITS, BLOCK, ITEMS, WIN, false, true, XG>(a, stream);
+        launch_one<BITS, BLOCK, ITEMS, WIN, false, true>(a, stream);
     else
-        launch_one<BITS, BLOCK, ITEMS, WIN, false, false, XG>(a, stream);
+        launch_one<BITS, BLOCK, ITEMS, WIN, false, false>(a, stream);
 }
 
 struct SegArgs {
@@ -1031,34 +1083,34 @@ struct SegArgs {
     const uint32_t* live_tiles;  // NULL, or the device word holding how many tiles are in use
 };
 
-template <int BITS, int BLOCK, int ITEMS, int WIN, bool FIRST, bool VALS, int XG>
+template <int BITS, int BLOCK, int ITEMS, int WIN, bool FIRST, bool VALS>
 void launch_one_seg(const PassArgs& a, const SegArgs& g, hipStream_t stream) {
     const dim3 grid(g.n_tiles), block(BLOCK);
     if (a.wide)
-        hipLaunchKernelGGL((onesweep_seg_kernel<BITS, BLOCK, ITEMS, WIN, FIRST, VALS, Lb64, XG>), grid, block, 0, stream,
+        hipLaunchKernelGGL((onesweep_seg_kernel<BITS, BLOCK, ITEMS, WIN, FIRST, VALS, Lb64>), grid, block, 0, stream,
                            a.keys_in, a.vals_in, a.keys_out, a.vals_out, a.n, a.shift, a.ghist, a.ghist_next,
                            a.shift_next, g.hist_stride, g.tiles, g.seg_base, static_cast<uint64_t*>(a.lb), nullptr,
                            a.epoch, a.err, g.live_tiles);
     else
-        hipLaunchKernelGGL((onesweep_seg_kernel<BITS, BLOCK, ITEMS, WIN, FIRST, VALS, Lb32, XG>), grid, block, 0, stream,
+        hipLaunchKernelGGL((onesweep_seg_kernel<BITS, BLOCK, ITEMS, WIN, FIRST, VALS, Lb32>), grid, block, 0, stream,
                            a.keys_in, a.vals_in, a.keys_out, a.vals_out, a.n, a.shift, a.ghist, a.ghist_next,
                            a.shift_next, g.hist_stride, g.tiles, g.seg_base, static_cast<uint32_t*>(a.lb),
                            static_cast<uint32_t*>(a.lb_clear), a.epoch, a.err, g.live_tiles);
 }
 
-template <int BITS, int BLOCK, int ITEMS, int WIN, int XG>
+template <int BITS, int BLOCK, int ITEMS, int WIN>
 void launch_seg_t(const PassArgs& a, const SegArgs& g, bool first, bool with_values, hipStream_t stream) {
     if (with_values && first)
-        launch_one_seg<BITS, BLOCK, ITEMS, WIN, true, true, XG>(a, g, stream);
+        launch_one_seg<BITS, BLOCK, ITEMS, WIN, true, true>(a, g, stream);
     else if (with_values)
-        launch_one_seg<BITS, BLOCK, ITEMS, WIN, false, true, XG>(a, g, stream);
+        launch_one_seg<BITS, BLOCK, ITEMS, WIN, false, true>(a, g, stream);
     else
-        launch_one_seg<BITS, BLOCK, ITEMS, WIN, false, false, XG>(a, g, stream);
+        launch_one_seg<BITS, BLOCK, ITEMS, WIN, false, false>(a, g, stream);
 }
 
 constexpr uint32_t kListGrid = 512;  // blocks of a pass over a device-written tile table
 
-template <int BITS, int BLOCK, int ITEMS, int WIN, int XG>
+template <int BITS, int BLOCK, int ITEMS, int WIN>
 void launch_list_t(const PassArgs& a, const SegArgs& g, uint32_t* counter, hipStream_t stream) {
     const dim3 grid(std::min(g.n_tiles, kListGrid)), block(BLOCK);
     if (a.wide)
@@ -1074,34 +1126,31 @@ void launch_list_t(const PassArgs& a, const SegArgs& g, uint32_t* counter, hipSt
 }
 
 struct Variant {
-    int bits, block, items, window, xcd_group;
+    int bits, block, items, window;
     bool split;  // particle keys take the split sort (9-bit digits only), else plain LSD passes
     void (*launch)(const PassArgs&, bool, bool, hipStream_t);
     void (*launch_seg)(const PassArgs&, const SegArgs&, bool, bool, hipStream_t);
     void (*launch_list)(const PassArgs&, const SegArgs&, uint32_t*, hipStream_t);
 };
 
-#define CS_VARIANT(B, BL, IT, WI, XG, SP)                                                                   \
-    {B, BL, IT, WI, XG, SP, launch_pass_t<B, BL, IT, WI, XG>, launch_seg_t<B, BL, IT, WI, XG>, \
-     launch_list_t<B, BL, IT, WI, XG>}
-// Shapes: digit bits, block, keys per thread, look-back window, XCD grouping,
-// split sort for particle keys. A block needs at least one thread per digit,
-// so 256-thread blocks take 8-bit digits; 1024-thread blocks hold one block
-// per CU. The 9-bit shapes without the split run 7 plain LSD passes, which a
+#define CS_VARIANT(B, BL, IT, WI, SP) \
+    {B, BL, IT, WI, SP, launch_pass_t<B, BL, IT, WI>, launch_seg_t<B, BL, IT, WI>, launch_list_t<B, BL, IT, WI>}
+// Shapes: digit bits, block, keys per thread, look-back window, split sort
+// for particle keys. A block needs at least one thread per digit, so
+// 256-thread blocks take 8-bit digits; 1024-thread blocks hold one block per
+// CU. The 9-bit shapes without the split run 7 plain LSD passes, which a
 // strongly clustered set (many level-9 buckets over the bucket kernel's
 // sizes) can favour.
 const Variant kVariants[] = {
-    CS_VARIANT(9, 512, 16, 4, 8, true),   CS_VARIANT(9, 512, 16, 4, 1, true),  CS_VARIANT(8, 512, 16, 4, 8, false),
-    CS_VARIANT(9, 512, 12, 4, 8, true),   CS_VARIANT(9, 512, 32, 4, 8, true),  CS_VARIANT(8, 512, 16, 4, 1, false),
-    CS_VARIANT(9, 512, 12, 4, 1, true),   CS_VARIANT(9, 512, 32, 4, 1, true),  CS_VARIANT(9, 1024, 8, 4, 8, true),
-    CS_VARIANT(9, 1024, 16, 4, 8, true),  CS_VARIANT(8, 256, 16, 4, 8, false), CS_VARIANT(9, 512, 16, 4, 8, false),
-    CS_VARIANT(9, 512, 12, 4, 8, false),
+    CS_VARIANT(9, 512, 16, 4, true),  CS_VARIANT(8, 512, 16, 4, false), CS_VARIANT(9, 512, 12, 4, true),
+    CS_VARIANT(9, 512, 32, 4, true),  CS_VARIANT(9, 1024, 8, 4, true),  CS_VARIANT(9, 1024, 16, 4, true),
+    CS_VARIANT(8, 256, 16, 4, false), CS_VARIANT(9, 512, 16, 4, false), CS_VARIANT(9, 512, 12, 4, false),
 };
 #undef CS_VARIANT
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 // Shape used where the autotune table has no entry: 9-bit digits, 512 x 16
-// tiles, 8 tiles in a row per XCD.
+// tiles, the split sort.
 constexpr int kBuiltinVariant = 0;
 
 // Split sorts of particle keys: 9-bit digits, the top three first (the
@@ -1383,9 +1432,14 @@ cstone_status launch_sort(const uint64_t* keys_in, uint64_t* keys_out, uint32_t*
 
 int sort_variant_count() { return kNumVariants; }
 
+cstone_status set_lookback_patience(uint32_t waits) {
+    CS_HIP(hipMemcpyToSymbol(HIP_SYMBOL(g_lookback_patience), &waits, sizeof waits));
+    return CSTONE_OK;
+}
+
 SortVariantInfo sort_variant_info(int v) {
     const Variant& x = kVariants[(v >= 0 && v < kNumVariants) ? v : 0];
-    return {x.bits, x.block, x.items, x.block * x.items, x.xcd_group, x.split ? 1 : 0};
+    return {x.bits, x.block, x.items, x.block * x.items, x.split ? 1 : 0};
 }
 
 
@@ -1501,7 +1555,7 @@ namespace {
 // listed buckets, as in the split sort of one key set.
 cstone_status launch_split_seg(const uint64_t* keys_in, uint64_t* keys_out, uint32_t* perm_out, size_t n_total,
                                const uint4* tiles, uint32_t n_tiles, const uint32_t* seg_base, uint32_t n_sets,
-                               bool wide, const SegWs& s, const Variant& var, hipStream_t stream) {
+                               bool wide, const SegWs& s, const Variant& var, uint32_t* err, hipStream_t stream) {
     constexpr int radix = 1 << kSplitBits;
     uint32_t* lb32[2] = {static_cast<uint32_t*>(s.lb), static_cast<uint32_t*>(s.lb) + s.rows * kMaxRadix};
     const uint32_t chunks = static_cast<uint32_t>(s.chunks);
@@ -1526,7 +1580,7 @@ cstone_status launch_split_seg(const uint64_t* keys_in, uint64_t* keys_out, uint
         a.lb = wide ? s.lb : static_cast<void*>(lb32[p & 1]);
         a.lb_clear = (!wide && p + 1 < kSplitTop) ? static_cast<void*>(lb32[(p + 1) & 1]) : nullptr;
         a.epoch = static_cast<uint32_t>(p + 1);
-        a.err = s.err;
+        a.err = err;
         var.launch_seg(a, g, p == 0, true, stream);
         src_k = a.keys_out;
         src_v = a.vals_out;
@@ -1546,7 +1600,7 @@ cstone_status launch_split_seg(const uint64_t* keys_in, uint64_t* keys_out, uint
     L.wide = wide ? 1u : 0u;
     hipLaunchKernelGGL((local_sort_kernel<kSplitBits, kLocalBlock, kLocalItems, true>), dim3(chunks),
                        dim3(kLocalBlock), 0, stream, keys_out, perm_out, static_cast<uint32_t>(n_total), kSplitShift,
-                       L, s.err, static_cast<uint32_t*>(nullptr), seg_base, n_sets,
+                       L, err, static_cast<uint32_t*>(nullptr), seg_base, n_sets,
                        static_cast<const uint32_t*>(s.chunk_set));
     if (s.max_buckets > 0) {  // some bucket may be longer than one block sorts
         hipLaunchKernelGGL(large_hist_kernel, dim3(std::min(L.max_tiles, kListGrid)), dim3(512), 0, stream, keys_out,
@@ -1568,7 +1622,7 @@ cstone_status launch_split_seg(const uint64_t* keys_in, uint64_t* keys_out, uint
             a.lb = wide ? s.lb : static_cast<void*>(lb32[p & 1]);
             a.lb_clear = (!wide && p + 1 < kLowPasses) ? static_cast<void*>(lb32[(p + 1) & 1]) : nullptr;
             a.epoch = static_cast<uint32_t>(kSplitTop + 1 + p);
-            a.err = s.err;
+            a.err = err;
             var.launch_list(a, gl, s.large_count + 2 + p, stream);  // a tile counter per pass, cleared at set-up
         }
     }
@@ -1581,7 +1635,7 @@ cstone_status launch_split_seg(const uint64_t* keys_in, uint64_t* keys_out, uint
 cstone_status launch_sort_segmented(const uint64_t* keys_in, uint64_t* keys_out, uint32_t* perm_out,
                                     size_t n_total, const uint4* tiles, uint32_t n_tiles, const uint32_t* seg_base,
                                     uint32_t n_sets, size_t max_set, int sig_bits, int variant, void* ws,
-                                    size_t ws_bytes, hipStream_t stream) {
+                                    size_t ws_bytes, hipStream_t stream, uint32_t* err_word) {
     if (variant < 0 || variant >= kNumVariants) return CSTONE_ERR_INVALID_ARG;
     SegWs s = carve_seg(ws, n_total, n_tiles, n_sets, variant);
     if (ws_bytes < s.bytes) return CSTONE_ERR_INVALID_ARG;
@@ -1592,9 +1646,10 @@ cstone_status launch_sort_segmented(const uint64_t* keys_in, uint64_t* keys_out,
     const int passes = (sig_bits + var.bits - 1) / var.bits;
     if (passes < 1 || static_cast<uint32_t>(passes * radix) > s.stride) return CSTONE_ERR_INVALID_ARG;
     const bool wide = max_set >= (1ull << 30);
+    uint32_t* err = err_word ? err_word : s.err;
     if (s.split && sig_bits == 63)
         return launch_split_seg(keys_in, keys_out, perm_out, n_total, tiles, n_tiles, seg_base, n_sets, wide, s, var,
-                                stream);
+                                err, stream);
     if (s.split) return CSTONE_ERR_INVALID_ARG;  // its first histogram was taken on the top digit
     uint32_t* lb32[2] = {static_cast<uint32_t*>(s.lb), static_cast<uint32_t*>(s.lb) + s.rows * kMaxRadix};
     SegArgs g{tiles, seg_base, n_tiles, s.stride, nullptr};
@@ -1616,7 +1671,7 @@ cstone_status launch_sort_segmented(const uint64_t* keys_in, uint64_t* keys_out,
         a.lb = wide ? s.lb : static_cast<void*>(lb32[p & 1]);
         a.lb_clear = (!wide && p + 1 < passes) ? static_cast<void*>(lb32[(p + 1) & 1]) : nullptr;
         a.epoch = static_cast<uint32_t>(p + 1);
-        a.err = s.err;
+        a.err = err;
         var.launch_seg(a, g, p == 0, true, stream);
         src_k = a.keys_out;
         src_v = a.vals_out;

@@ -133,15 +133,15 @@ CSTONE_API cstone_status cstone_tune_save(const char* path) {
     std::lock_guard<std::mutex> lock(cs::g_mu);
     FILE* f = std::fopen(path, "w");
     if (!f) return CSTONE_ERR_INVALID_ARG;
-    std::fprintf(f, "{\"format\": \"cstone-tune-1\", \"entries\": [\n");
+    std::fprintf(f, "{\"format\": \"cstone-tune-2\", \"entries\": [\n");
     for (size_t i = 0; i < cs::g_entries.size(); ++i) {
         const auto& e = cs::g_entries[i];
         const cs::SortVariantInfo v = cs::sort_variant_info(e.variant);
         std::fprintf(f,
                      "{\"kernel\": \"%s\", \"size_log2\": %d, \"device\": \"%s\", \"variant\": %d, "
-                     "\"digit_bits\": %d, \"block\": %d, \"items\": %d, \"xcd_group\": %d, \"split\": %d}%s\n",
+                     "\"digit_bits\": %d, \"block\": %d, \"items\": %d, \"split\": %d}%s\n",
                      cs::kKernelNames[e.kernel], e.size_class, e.device.c_str(), e.variant, v.bits, v.block, v.items,
-                     v.xcd_group, v.split, i + 1 < cs::g_entries.size() ? "," : "");
+                     v.split, i + 1 < cs::g_entries.size() ? "," : "");
     }
     std::fprintf(f, "]}\n");
     const bool ok = std::fclose(f) == 0;
@@ -156,17 +156,17 @@ CSTONE_API cstone_status cstone_tune_load(const char* path) {
     char line[512];
     bool ok = true, header = false;
     while (std::fgets(line, sizeof line, f)) {
-        if (std::strncmp(line, "{\"format\": \"cstone-tune-1\"", 26) == 0) {
+        if (std::strncmp(line, "{\"format\": \"cstone-tune-2\"", 26) == 0) {
             header = true;
             continue;
         }
         if (line[0] == ']' || line[0] == '\n') continue;
         char kernel[32], device[128];
-        int size_class = 0, variant = 0, bits = 0, block = 0, items = 0, xg = 0, split = 0;
+        int size_class = 0, variant = 0, bits = 0, block = 0, items = 0, split = 0;
         if (std::sscanf(line,
                         "{\"kernel\": \"%31[^\"]\", \"size_log2\": %d, \"device\": \"%127[^\"]\", \"variant\": %d, "
-                        "\"digit_bits\": %d, \"block\": %d, \"items\": %d, \"xcd_group\": %d, \"split\": %d}",
-                        kernel, &size_class, device, &variant, &bits, &block, &items, &xg, &split) != 9) {
+                        "\"digit_bits\": %d, \"block\": %d, \"items\": %d, \"split\": %d}",
+                        kernel, &size_class, device, &variant, &bits, &block, &items, &split) != 8) {
             ok = false;
             break;
         }
@@ -176,7 +176,7 @@ CSTONE_API cstone_status cstone_tune_load(const char* path) {
         // a shape that this library does not have under that index is skipped
         if (k < 0 || variant < 0 || variant >= cs::sort_variant_count()) continue;
         const cs::SortVariantInfo v = cs::sort_variant_info(variant);
-        if (v.bits != bits || v.block != block || v.items != items || v.xcd_group != xg || v.split != split) continue;
+        if (v.bits != bits || v.block != block || v.items != items || v.split != split) continue;
         read.push_back({k, size_class, device, variant});
     }
     std::fclose(f);

@@ -80,9 +80,11 @@ def request_bytes(n: int, cap: int) -> int:
     """HBM reserved for one request: coordinates 24 n, sorted keys and
     permutation 12 n, unsorted keys and sort buffers 28 n (plus look-back rows
     and digit counts), leaves and counts 12 (cap + 1), nodes 12 node slots,
-    rebalance arrays 32 (cap + 1) and split list, and a fixed 64 KiB."""
+    rebalance arrays 32 (cap + 1) and split list, and a fixed 128 KiB (the
+    set's digit counts of every sort pass, its tables and level offsets). A
+    test checks it against the plan's own layout."""
     node_cap = cap + (cap - 1) // 7
-    return 64 * n + 12 * (cap + 1) + 12 * node_cap + 48 * (cap + 1) + 65536
+    return 64 * n + 12 * (cap + 1) + 12 * node_cap + 48 * (cap + 1) + 131072
 
 
 def rounds_for(reqs) -> int:
@@ -217,10 +219,37 @@ class ServingLoop:
         return sorted(done, key=lambda r: r.rid), st
 
 
-class GpuExecutor:
-    """Runs each admitted group as one batched build on its own stream."""
+class _Slot:
+    """A launch slot: a stream and the device buffers its batches reuse."""
 
-    def __init__(self, max_inflight: int = 3, device="cuda", keep=(), reserve=None, sink=None):
+    def __init__(self, stream):
+        self.stream = stream
+        self.arena = None
+        self.coords = None  # x, y, z, each of the capacity below
+        self.coord_cap = 0
+        self.host_results = None  # pinned copy of the last batch's per-set results
+        self.host_stage = None  # pinned staging of the last batch's plan tables
+
+    @property
+    def nbytes(self) -> int:
+        return (self.arena.nbytes if self.arena is not None else 0) + 24 * self.coord_cap
+
+    def drop(self):
+        self.arena, self.coords, self.coord_cap = None, None, 0
+
+
+class GpuExecutor:
+    """Runs each admitted group as one batched build on a slot of its own.
+
+    A slot keeps its device buffers (coordinates, the batch's outputs and
+    workspace) from one group to the next and grows them only when a group
+    needs more, so a launch allocates nothing in the common case; the plan of
+    each group is made on the host. With `budget_bytes`, the slots' buffers
+    together stay within it: before a slot grows, idle slots give theirs
+    back."""
+
+    def __init__(self, max_inflight: int = 3, device="cuda", keep=(), reserve=None, sink=None,
+                 budget_bytes: int | None = None):
         import torch
 
         import workloads
@@ -230,53 +259,123 @@ class GpuExecutor:
         self.torch = torch
         self.wl = workloads
         self.device = torch.device(device)
-        self.free = [torch.cuda.Stream(self.device) for _ in range(max_inflight)]
+        self.free = [_Slot(torch.cuda.Stream(self.device)) for _ in range(max_inflight)]
+        self.slots = list(self.free)
+        self.budget = budget_bytes
+        self.peak_buffer_bytes = 0
+        self.grows = 0
         self.keep = set(keep)
         self.kept = {}  # rid -> dict of host outputs
         self.sink = sink  # sink(rid, outputs): takes the kept outputs instead of self.kept
         # leaf capacity of a request (default: leaf_reservation)
         self.reserve = reserve or (lambda r: leaf_reservation(r.n, r.n_crit, r.full))
 
+    def _buffers(self, slot, need, total):
+        """Make the slot's buffers large enough for a group with these plan
+        needs and particles. Only the buffers that are too small grow, with
+        25% headroom unless that would not fit the budget. Returns the slot's
+        batch buffers."""
+        from . import BatchArena
+
+        if slot.arena is not None and slot.arena.fits(need) and total <= slot.coord_cap:
+            return slot.arena
+        have = slot.arena.cap if slot.arena is not None else (0,) * len(need)
+        exact = tuple(max(int(v), c) for v, c in zip(need, have))
+        roomy = tuple(c if int(v) <= c else max(int(v * 1.25), 1) for v, c in zip(need, have))
+        exact_cap = max(total, slot.coord_cap, 1)
+        roomy_cap = slot.coord_cap if total <= slot.coord_cap else max(int(total * 1.25), 1)
+        grown, cap = roomy, roomy_cap
+        if self.budget is not None:
+            busy = sum(s.nbytes for s in self.slots if s is not slot and s not in self.free)
+            idle = [s for s in self.free if s is not slot]
+            if busy + BatchArena.bytes_of(roomy) + 24 * roomy_cap > self.budget:
+                grown, cap = exact, exact_cap
+            new_bytes = BatchArena.bytes_of(grown) + 24 * cap
+            for s in idle:  # idle slots give their buffers back first
+                if busy + sum(o.nbytes for o in idle) + new_bytes <= self.budget:
+                    break
+                s.drop()
+        # the slot is idle (its last batch has completed), so its buffers can be replaced
+        if slot.arena is None:
+            slot.arena = BatchArena(self.device, grown)
+        else:
+            slot.arena.grow(grown)
+        if cap > slot.coord_cap:
+            slot.coords = None
+            slot.coords = tuple(self.torch.empty(cap, dtype=self.torch.float64, device=self.device) for _ in range(3))
+            slot.coord_cap = cap
+        self.grows += 1
+        self.peak_buffer_bytes = max(self.peak_buffer_bytes, sum(s.nbytes for s in self.slots))
+        return slot.arena
+
+    def _stage(self, slot, nbytes):
+        """The slot's pinned staging buffer for plan tables (grown as needed;
+        its last upload has completed, since the slot is idle)."""
+        if slot.host_stage is None or slot.host_stage.numel() < nbytes:
+            slot.host_stage = None
+            slot.host_stage = self.torch.empty(max(int(nbytes * 1.25), 1 << 16), dtype=self.torch.uint8,
+                                               pin_memory=True)
+        return slot.host_stage
+
     def launch(self, group):
         from . import Batch
 
         torch = self.torch
-        stream = self.free.pop()
-        with torch.cuda.stream(stream):
-            b = Batch([(r.n, r.box, r.curve, r.n_crit, self.reserve(r)) for r in group], device=self.device)
+        slot = self.free.pop()
+        stream = slot.stream
+        sets = [(r.n, r.box, r.curve, r.n_crit, self.reserve(r)) for r in group]
+        total = sum(r.n for r in group)
+        with torch.cuda.stream(stream):  # buffers made and used in the slot's stream order
+            b = Batch(sets, device=self.device, arena=lambda need: self._buffers(slot, need, total),
+                      stage=lambda nbytes: self._stage(slot, nbytes))
             b.set_rounds(rounds_for(group))
-            total = sum(r.n for r in group)
-            x, y, z = (torch.empty(max(total, 1), dtype=torch.float64, device=self.device) for _ in range(3))
+            x, y, z = (c[:max(total, 1)] for c in slot.coords)
             self.wl.device_generate([(r.kind, r.n, r.seed, r.stream) for r in group], x, y, z, stream=stream)
             b.build(x, y, z, stream=stream)
+            # the per-set results come back on the slot's own stream, so that
+            # finishing a group needs no device call (a copy on the default
+            # stream would wait behind whatever shares its hardware queue)
+            k = 4 * len(group)
+            if slot.host_results is None or slot.host_results.numel() < k:
+                slot.host_results = torch.empty(max(k, 4096), dtype=torch.int32, pin_memory=True)
+            slot.host_results[:k].copy_(b.results[:k], non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(stream)
-        return {"stream": stream, "event": ev, "batch": b, "coords": (x, y, z), "group": group}
+        return {"slot": slot, "stream": stream, "event": ev, "batch": b, "coords": (x, y, z), "group": group}
 
     def poll(self, h) -> bool:
         return h["event"].query()
 
     def finish(self, h):
-        from . import STATUS, to_numpy
+        from . import STATUS
 
         b = h["batch"]
-        res = b.set_results()
+        group = h["group"]
+        res = h["slot"].host_results[:4 * len(group)].numpy().view(np.uint32).reshape(len(group), 4)
         out = []
-        for s, r in enumerate(h["group"]):
+        for s, r in enumerate(group):
             status = STATUS.get(int(res[s, 3]), str(int(res[s, 3])))
             out.append((status, int(res[s, 0]), int(res[s, 2])))
             if r.rid in self.keep and status == "OK":
-                v = b.set_view(s, res[s])
-                p0, p1 = int(b.particle_offsets[s]), int(b.particle_offsets[s + 1])
-                rec = {k: to_numpy(v[k]).copy() for k in
-                       ("sorted_keys", "perm", "leaves", "counts", "node_keys", "child", "level_offsets")}
-                rec.update({a: h["coords"][i][p0:p1].cpu().numpy() for i, a in enumerate("xyz")})
+                with self.torch.cuda.stream(h["stream"]):  # the copies below wait on the slot's stream only
+                    rec = self._outputs(b, s, res[s], h["coords"])
                 if self.sink is not None:
                     self.sink(r.rid, rec)
                 else:
                     self.kept[r.rid] = rec
-        self.free.append(h["stream"])
+        self.free.append(h["slot"])
         return out
+
+    @staticmethod
+    def _outputs(b, s, res, coords):
+        from . import to_numpy
+
+        v = b.set_view(s, res)
+        p0, p1 = int(b.particle_offsets[s]), int(b.particle_offsets[s + 1])
+        rec = {k: to_numpy(v[k]).copy() for k in
+               ("sorted_keys", "perm", "leaves", "counts", "node_keys", "child", "level_offsets")}
+        rec.update({a: coords[i][p0:p1].cpu().numpy() for i, a in enumerate("xyz")})
+        return rec
 
 
 def poisson_requests(specs, rate_per_s: float):

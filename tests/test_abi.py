@@ -138,11 +138,11 @@ def test_tune_table_round_trips_through_its_json_file(tmp_path):
         path = str(tmp_path / "tune.json")
         cs.tune_save(path)
         doc = json.load(open(path))
-        assert doc["format"] == "cstone-tune-1" and len(doc["entries"]) == 2
+        assert doc["format"] == "cstone-tune-2" and len(doc["entries"]) == 2
         e = {x["kernel"]: x for x in doc["entries"]}
         assert e["sort"]["size_log2"] == 24 and e["sort"]["variant"] == 2
         assert (e["sort"]["digit_bits"], e["sort"]["block"], e["sort"]["items"]) == cs.sort_variants()[2]
-        assert (e["sort"]["xcd_group"], e["sort"]["split"]) == cs.sort_variant_layouts()[2]
+        assert e["sort"]["split"] == cs.sort_variant_splits()[2]
         assert e["batch_sort"]["size_log2"] == 26
         cs.tune_clear()
         assert cs.tune_entries() == 0 and cs.tune_get(cs.TUNE_SORT, 1 << 24) == -1
@@ -154,7 +154,7 @@ def test_tune_table_round_trips_through_its_json_file(tmp_path):
         # an entry naming a shape this library does not have under that index is skipped
         doc["entries"][0]["block"] = 12345
         with open(path, "w") as f:
-            f.write('{"format": "cstone-tune-1", "entries": [\n')
+            f.write('{"format": "cstone-tune-2", "entries": [\n')
             f.write(",\n".join(json.dumps(x) for x in doc["entries"]) + "\n]}\n")
         cs.tune_clear()
         cs.tune_load(path)

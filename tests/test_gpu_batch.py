@@ -102,6 +102,52 @@ def test_batch_mixed_eager():
     check_against_oracle(b, sets)
 
 
+def test_batch_staged_upload_into_a_reused_arena():
+    """Two batches, one after the other, share one arena and one pinned table
+    stage, with the tables going up asynchronously on a side stream: each
+    matches the oracle, the second (smaller) one included."""
+    sets = mixed_sets()
+    first, second = sets, [sets[i] for i in (7, 3, 0, 9)]
+    side = torch.cuda.Stream()
+    arena = {}
+    stage = {}
+
+    def take_arena(need):
+        if "a" not in arena:
+            arena["a"] = cs.BatchArena("cuda", need)
+        arena["a"].grow(need)
+        return arena["a"]
+
+    def take_stage(nbytes):
+        if "s" not in stage or stage["s"].numel() < nbytes:
+            stage["s"] = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+        return stage["s"]
+
+    for which, group in (("first", first), ("second", second)):
+        say("batch staged upload", which, [s.n for s in group])
+        with torch.cuda.stream(side):
+            b = cs.Batch(specs(group), arena=take_arena, stage=take_stage)
+            b.build(*coords(group), stream=side)
+        side.synchronize()
+        check_against_oracle(b, group)
+
+
+def test_batch_lookback_fallback_matches_the_oracle():
+    """The segmented passes with the look-back patience at 0 (every wait
+    settled by the waiting block counting the predecessor tile itself): every
+    set still matches the oracle."""
+    sets = mixed_sets()
+    try:
+        cs.set_lookback_patience(0)
+        say("batch with look-back fallback", [s.n for s in sets])
+        b = cs.Batch(specs(sets))
+        b.build(*coords(sets))
+        torch.cuda.synchronize()
+        check_against_oracle(b, sets)
+    finally:
+        cs.set_lookback_patience(256)
+
+
 def test_batch_graph_replays_match_eager():
     sets = mixed_sets()
     b = cs.Batch(specs(sets))

@@ -386,6 +386,38 @@ def test_sort_autotune_keeps_the_sort_exact():
 
 
 @pytest.mark.slow
+def test_sort_lookback_fallback_keeps_the_sort_exact():
+    """With the look-back patience at 0, every wait on a predecessor tile is
+    settled by the waiting block counting that tile's digits itself (and
+    publishing them unless the tile's own block got there first): every
+    shape still sorts bit-exactly (uniform keys with a ragged tail; buckets
+    long enough for the listed low passes, whose tiles come from a table),
+    and so does a whole build."""
+    rng = np.random.default_rng(77)
+    nv = len(cs.sort_variants())
+    cs.tune_clear()
+    try:
+        cs.set_lookback_patience(0)
+        for kind, n in (("uniform", (1 << 21) + 7), ("mixed", 300000)):
+            keys = _keys(kind, n, rng)
+            rP, rperm = oracle.sort(keys)
+            for v in range(nv):
+                say("fallback sort", kind, n, "shape", v)
+                cs.tune_set(cs.TUNE_SORT, n, v)
+                P, perm = cs.sort(dev(keys))
+                torch.cuda.synchronize()
+                eq(host(P), rP, f"{kind} shape {v} P")
+                eq(host(perm), rperm, f"{kind} shape {v} perm")
+            cs.tune_clear()
+        s = wl.make_set("plummer", 400000, 43, 0, wl.HILBERT, 16)
+        say("fallback build plummer 400000")
+        r = cs.Builder(s.n, s.n_crit).build(*coords(s), s.box, s.curve, s.n_crit)
+        _check_build(s, r, "fallback build")
+    finally:
+        cs.set_lookback_patience(256)
+        cs.tune_clear()
+
+
 def test_sort_beyond_2_30_uses_wide_lookback_words():
     """n >= 2^30 switches the look-back words to 64 bits (epoch-tagged). At this
     size the sort is checked by its characterisation on the device: sorted,

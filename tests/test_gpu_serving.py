@@ -225,3 +225,87 @@ def test_serving_stratified_sample_equals_alone_and_oracle():
             got = _digest({k: host(v[k]) for k in OUT_NAMES}, OUT_NAMES)
             assert got == {k: mix[k] for k in OUT_NAMES}, f"request {r.rid}: batch of one differs from the mix"
             del b
+
+
+def test_serving_admission_limited_by_the_hbm_budget():
+    """A budget that holds two of these requests at a time: all arrive at
+    once, yet the reserved bytes and the slots' resident buffers never exceed
+    the budget, fewer requests than the slots allow run together, and every
+    result equals the oracle on a sample."""
+    n = 1 << 20
+    specs = [("plummer" if i % 2 else "uniform", n, 16 if i % 3 else 64, 900 + i, 1.0) for i in range(8)]
+    reqs = sv.poisson_requests(specs, rate_per_s=1e12)
+    per = max(sv.request_bytes(r.n, sv.leaf_reservation(r.n, r.n_crit)) for r in reqs)
+    budget = int(2.2 * per)
+    say("serving with budget", budget, "bytes,", per, "per request")
+    keep = {0, 5}
+    ex = sv.GpuExecutor(max_inflight=3, keep=keep, budget_bytes=budget)
+    loop = sv.ServingLoop(ex, budget_bytes=budget, max_inflight=3)
+    done, st = loop.run(reqs)
+    torch.cuda.synchronize()
+    assert all(r.status == "OK" for r in done) and len(done) == len(reqs)
+    assert st.peak_reserved_bytes <= budget
+    assert ex.peak_buffer_bytes <= budget
+    # two requests fit at a time: at least four groups, never three requests in flight
+    assert st.batches >= 4 and st.mean_batch_requests <= 2.0
+    for rid in keep:
+        r = reqs[rid]
+        rec = ex.kept[rid]
+        ref = oracle.build_tree(rec["x"], rec["y"], rec["z"], r.box, cs.HILBERT, r.n_crit)
+        for k, kk in (("sorted_keys", "P"), ("perm", "perm"), ("leaves", "K"), ("counts", "counts"),
+                      ("node_keys", "NK"), ("child", "CO"), ("level_offsets", "LO")):
+            eq(rec[k], ref[kk], f"request {rid} {k}")
+
+
+def test_serving_slots_reuse_their_buffers():
+    """After the first groups the slots' buffers are large enough: later
+    launches allocate nothing (no slot grows), and results stay exact."""
+    specs = wl.serving_specs(count=120, seed=9, log2_min=12.0, log2_max=18.0)
+    reqs = sv.poisson_requests(specs, rate_per_s=2000.0)
+    ex = sv.GpuExecutor(max_inflight=3, keep={7, 100})
+    loop = sv.ServingLoop(ex, budget_bytes=64 * 10**9, max_inflight=3)
+    done, st = loop.run(reqs)
+    torch.cuda.synchronize()
+    say("groups", st.batches, "slot growths", ex.grows)
+    assert all(r.status == "OK" for r in done)
+    assert ex.grows < st.batches / 2  # most launches reuse their slot's buffers
+    for rid in (7, 100):
+        r = reqs[rid]
+        rec = ex.kept[rid]
+        ref = oracle.build_tree(rec["x"], rec["y"], rec["z"], r.box, cs.HILBERT, r.n_crit)
+        eq(rec["leaves"], ref["K"], f"request {rid} leaves")
+        eq(rec["perm"], ref["perm"], f"request {rid} perm")
+
+
+def test_three_large_groups_at_once_equal_each_alone():
+    """Three groups of 40 requests (about 2.4e7 particles each) in flight on
+    three streams at once, so that their look-back passes share the GPU and
+    its XCDs: every request's arrays equal those of its group built alone, and
+    no set reports a device-side wait that gave up."""
+    reqs = sv.poisson_requests(wl.serving_specs(120), rate_per_s=1e12)
+    groups = [reqs[k * 40:(k + 1) * 40] for k in range(3)]
+    keep = {r.rid for r in reqs}
+    together = sv.GpuExecutor(max_inflight=3, keep=keep)
+    say("three groups at once", [sum(r.n for r in g) for g in groups])
+    handles = [together.launch(g) for g in groups]
+    status_together = {}
+    for h in handles:
+        while not together.poll(h):
+            pass
+        for r, (st, nl, rounds) in zip(h["group"], together.finish(h)):
+            status_together[r.rid] = (st, nl, rounds)
+    alone = sv.GpuExecutor(max_inflight=1, keep=keep)
+    status_alone = {}
+    for g in groups:
+        say("group alone", len(g))
+        h = alone.launch(g)
+        torch.cuda.synchronize()
+        for r, res in zip(g, alone.finish(h)):
+            status_alone[r.rid] = res
+    assert status_together == status_alone
+    assert all(st != "DEVICE" for st, _, _ in status_together.values())
+    for rid in sorted(together.kept):
+        a, b = together.kept[rid], alone.kept[rid]
+        assert a.keys() == b.keys()
+        for k in a:
+            eq(a[k], b[k], f"request {rid} {k}")

@@ -159,3 +159,33 @@ def test_reservations_and_rounds():
     assert sv.rounds_for([r]) == 22
     assert sv.request_bytes(100, 1) > 64 * 100
     assert math.isnan(sv.Request(1, 0.0, 5, "uniform", 8, 5, 2).done)
+
+
+def test_request_bytes_cover_the_batch_buffers():
+    """The reservation model is an upper bound of what a group's batched build
+    holds on the device (its workspace and output buffers, from the plan's own
+    layout, plus the coordinates), for single requests over the serving sizes
+    (up to 2^22, both N_crit, the full leaf bound of a retry) and for groups."""
+    cs = pytest.importorskip("paper_2307_06345_amd")
+
+    def actual(reqs, full=False):
+        sets = [(n, sv.BOXES[k], 1, nc, sv.leaf_reservation(n, nc, full)) for k, n, nc in reqs]
+        lay = cs.batch_layout(sets)
+        return cs.BatchArena.bytes_of(cs.BatchArena.need(lay)) + 24 * sum(n for _, n, _ in reqs)
+
+    for n in (1, 4096, 65537, 1 << 20, 3_000_001, 1 << 22):
+        for nc in (16, 64):
+            for full in (False, True):
+                if full and n > (1 << 20):
+                    continue  # the full bound of the largest sizes is plan-only arithmetic, same formula
+                model = sv.request_bytes(n, sv.leaf_reservation(n, nc, full))
+                assert model >= actual([("plummer", n, nc)], full), (n, nc, full)
+    import workloads as wl
+
+    rng = np.random.default_rng(3)
+    specs = wl.serving_specs(count=400, seed=11)
+    for _ in range(20):
+        idx = rng.choice(len(specs), size=int(rng.integers(1, 40)), replace=False)
+        grp = [(specs[i][0], specs[i][1], specs[i][2]) for i in idx]
+        model = sum(sv.request_bytes(n, sv.leaf_reservation(n, nc)) for _, n, nc in grp)
+        assert model >= actual(grp), len(grp)
