@@ -566,13 +566,15 @@ struct Outcome {
     uint32_t buf;      // which of the two arrays holds it (the parity of the rounds that ran)
 };
 
+// settle_last: the last enqueued round may settle too; its check round is then
+// counted without having been enqueued (the caller allows one more round).
 __device__ __forceinline__ Outcome loop_outcome(const LoopState* st, uint32_t enqueued, uint64_t capacity,
-                                                bool settle = true) {
+                                                bool settle = true, bool settle_last = false) {
     for (uint32_t q = 0; q < enqueued; ++q) {
         if (st->nl[q + 1] > capacity) return {q, 2u, st->nl[q], q & 1u};
         if (st->changed[q] == 0) return {q + 1, 1u, st->nl[q + 1], (q + 1) & 1u};  // round q copied every leaf
-        // round q + 1 (enqueued) would copy every leaf: it did not run, and counts
-        if (settle && q + 1 < enqueued && st->merged[q] == 0 && st->over[q] == 0)
+        // round q + 1 would copy every leaf: it does not run, and counts
+        if (settle && (q + 1 < enqueued || settle_last) && st->merged[q] == 0 && st->over[q] == 0)
             return {q + 2, 1u, st->nl[q + 1], (q + 1) & 1u};
     }
     return {enqueued, 0u, st->nl[enqueued], enqueued & 1u};
@@ -584,8 +586,8 @@ __global__ __launch_bounds__(256) void finalize_kernel(LoopState* st, uint32_t e
                                                        uint64_t* __restrict__ K0, const uint64_t* __restrict__ K1,
                                                        const uint32_t* __restrict__ pos0,
                                                        const uint32_t* __restrict__ pos1,
-                                                       uint32_t* __restrict__ counts) {
-    const Outcome o = loop_outcome(st, enqueued, capacity);
+                                                       uint32_t* __restrict__ counts, uint32_t settle_last) {
+    const Outcome o = loop_outcome(st, enqueued, capacity, true, settle_last != 0);
     const uint64_t nl = o.nl <= capacity ? o.nl : 0;
     const bool odd = o.buf != 0;
     const uint32_t* pos = odd ? pos1 : pos0;
@@ -741,13 +743,16 @@ cstone_status RebalanceLoop::enqueue(uint32_t rounds) {
             // when the start may come out a level coarser (the level above it
             // holds under 2 (n_crit + 1) particles per node on average, so
             // some node may not exceed n_crit); a start coarser than that, or
-            // a deeper tree, needs a later batch. The last round, the check,
-            // costs only its launch when the round before it settles the tree.
+            // a deeper tree, needs a later batch. After a safe start the
+            // check round is not enqueued: when the last round settles the
+            // tree, the finalize kernel counts the check round without running
+            // it (and a tree that needs more rounds gets a later batch).
             if (start_top_ > 1) {
                 const double above = static_cast<double>(n_) / (static_cast<double>(n_crit_) + 1.0) /
                                      static_cast<double>(size_t{1} << (3 * (start_top_ - 1)));
-                const uint32_t skip = static_cast<uint32_t>(start_top_) - (above < 2.0 ? 1u : 0u);
-                rounds = std::max<uint32_t>(2, rounds - skip);
+                const bool safe = above >= 2.0;
+                const uint32_t skip = static_cast<uint32_t>(start_top_) - (safe ? 0u : 1u);
+                rounds = safe ? std::max<uint32_t>(1, rounds - skip - 1) : std::max<uint32_t>(2, rounds - skip);
             }
         }
     }
@@ -770,7 +775,8 @@ cstone_status RebalanceLoop::enqueue(uint32_t rounds) {
     }
     enqueued_ += rounds;
     hipLaunchKernelGGL(finalize_kernel, dim3(clamp_grid(grid_1d(cap_ + 1, 256))), dim3(256), 0, stream_, w.st,
-                       enqueued_, static_cast<uint64_t>(cap_), leaves_, w.K_alt, w.pos[0], w.pos[1], counts_);
+                       enqueued_, static_cast<uint64_t>(cap_), leaves_, w.K_alt, w.pos[0], w.pos[1], counts_,
+                       enqueued_ < max_iters_ ? 1u : 0u);
     CS_HIP(hipGetLastError());
     return CSTONE_OK;
 }
