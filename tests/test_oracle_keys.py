@@ -138,6 +138,31 @@ def test_hilbert_small_curve_invariants(bits):
         assert oracle.hilbert_decode(k, bits) == p
 
 
+@pytest.mark.parametrize("bits", [5, 6, 7])
+def test_hilbert_coarse_curve_of_the_full_keys(bits):
+    # Exhaustive over the cells of a 2^bits grid (2^21 cells at 7 bits): the
+    # top 3 bits digits of the full 21-bit keys of the cell centres order the
+    # cells along a Hilbert curve of order `bits` -- a bijection onto
+    # [0, 8^bits), starting at the origin, consecutive cells sharing a face,
+    # and every aligned run of 8^m cells an aligned 2^m cube (Sec. 3: the
+    # curve refines the octree level by level).
+    n = 1 << bits
+    ix, iy, iz = (a.ravel() for a in np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij"))
+    keys, _ = oracle.compute_keys((ix + 0.5) / n, (iy + 0.5) / n, (iz + 0.5) / n, ((0, 0, 0), (1, 1, 1)),
+                                  oracle.HILBERT)
+    cell = keys.astype(np.uint64) >> np.uint64(3 * (L - bits))
+    order = np.argsort(cell, kind="stable")
+    assert np.array_equal(cell[order], np.arange(n ** 3, dtype=np.uint64))
+    pts = np.stack([ix[order], iy[order], iz[order]], axis=1).astype(np.int64)
+    assert tuple(pts[0]) == (0, 0, 0)
+    assert np.all(np.abs(np.diff(pts, axis=0)).sum(axis=1) == 1)
+    for m in range(1, bits + 1):
+        blocks = pts.reshape(-1, 8 ** m, 3)
+        lo, hi = blocks.min(axis=1), blocks.max(axis=1)
+        assert np.all(hi - lo == (1 << m) - 1)
+        assert np.all(lo % (1 << m) == 0)
+
+
 def test_hilbert_21bit_roundtrip_and_steps():
     rng = np.random.default_rng(15)
     for _ in range(3000):
