@@ -555,7 +555,7 @@ constexpr int kLocalBlock = 512;
 constexpr int kLocalItems = 4;
 constexpr int kLocalBlocksPerCU = 4;                        // LDS of a block stays below 40 KB
 constexpr uint32_t kLocalCap = kLocalBlock * kLocalItems;  // keys one block holds and sorts in LDS
-constexpr uint32_t kLocalLook = 256;                        // look-ahead past the chunk for its last bucket's end
+constexpr uint32_t kLocalLook = 64;                         // look-ahead past the chunk for its last bucket's end
 constexpr uint32_t kLocalChunk = kLocalCap - kLocalLook;    // a block owns the buckets starting in its chunk
 constexpr uint32_t kErrLarge = 1u << 9;                     // bucket list overflow (not reachable by the sizing)
 constexpr uint32_t kCountMax = 160;  // buckets up to this size are ranked by counting, larger ones by LDS passes
