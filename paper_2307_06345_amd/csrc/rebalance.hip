@@ -313,6 +313,7 @@ __global__ __launch_bounds__(kRBlock) void round_kernel(uint32_t n, uint32_t n_c
     const uint64_t nl = st->nl[round];
     if (nl == 0 || nl > capacity) return;  // an earlier round overflowed
     const uint32_t tiles = static_cast<uint32_t>((nl + kRTile - 1) / kRTile);
+    if (blockIdx.x >= tiles) return;  // more blocks than tiles: the rest stay off the counter
     const uint32_t tid = threadIdx.x;
     const uint32_t epoch = static_cast<uint32_t>(round + 1);
     if (tid == 0) {
@@ -914,6 +915,7 @@ __global__ __launch_bounds__(kBBlock, 4) void batch_round_kernel(const BatchSet*
     const uint64_t M = st->nl[round];
     if (M == 0 || M > capacity) return;  // an earlier round overflowed
     const uint32_t tiles = static_cast<uint32_t>((M + kBTile - 1) / kBTile);
+    if (blockIdx.x >= tiles) return;  // more blocks than tiles: the rest stay off the counter
     const uint32_t tid = threadIdx.x;
     const uint32_t epoch = static_cast<uint32_t>(round + 1);
     if (tid == 0) any_change = 0;
