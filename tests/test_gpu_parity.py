@@ -144,6 +144,30 @@ def test_sort_buckets_past_the_lookahead_repeatedly():
         eq(host(perm), rperm, "perm")
 
 
+@pytest.mark.parametrize("lo,hi", [(40, 300), (150, 170), (1900, 2100)])
+def test_sort_bucket_sizes_around_the_bucket_kernel_limits(lo, hi):
+    """Level-9 buckets whose sizes straddle the bucket kernel's limits: the
+    64-key look-ahead and the chunk ends (40-300 keys), the size up to which
+    a window's buckets are ranked by counting (150-170), and the size one
+    block sorts in LDS (1900-2100; larger buckets are listed for the low
+    passes). Low bits with many repeats, so ties are checked too; three
+    repeated sorts of the same keys."""
+    rng = np.random.default_rng(lo * 7 + hi)
+    n = (1 << 21) + 33
+    sizes = rng.integers(lo, hi + 1, n // lo + 2)
+    pre = np.sort(rng.choice(1 << 27, sizes.size, replace=False)).astype(np.uint64)
+    low = rng.integers(0, 1 << 12, n, dtype=np.uint64) << np.uint64(rng.integers(0, 24))
+    keys = (np.repeat(pre, sizes)[:n] << np.uint64(36)) | (low & np.uint64((1 << 36) - 1))
+    keys = keys[rng.permutation(n)]
+    rP, rperm = oracle.sort(keys)
+    d = dev(keys)
+    for rep in range(3):
+        say("sort, bucket sizes", lo, hi, "rep", rep)
+        P, perm = cs.sort(d)
+        eq(host(P), rP, "sorted keys")
+        eq(host(perm), rperm, "perm")
+
+
 def test_sort_twice_identical():
     rng = np.random.default_rng(5)
     keys = dev(_keys("dups", 500000, rng))
