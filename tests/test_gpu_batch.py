@@ -273,11 +273,11 @@ def test_batch_nonfinite_set_reported_alone():
     check_against_oracle(b, sets, which=[s for s in range(len(sets)) if s != bad])
 
 
-def test_batch_config4_full_size():
+def test_batch_512_sets_full_size():
     """512 sets, sizes log-uniform in [2^10, 2^20]: captured graph, every set
     bit-exact against the oracle (run on host threads) in every output."""
     sets = wl.batched_sets()
-    say("config 4: 512 sets, total", sum(s.n for s in sets))
+    say("512 sets, total", sum(s.n for s in sets))
     b = cs.Batch(specs(sets))
     x, y, z = coords(sets)
     side = torch.cuda.Stream()

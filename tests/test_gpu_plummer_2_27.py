@@ -71,8 +71,8 @@ def check_against_oracle(r, ref_keys):
     assert not msgs, msgs
 
 
-def test_config3_plummer_2_27_and_incremental_rebuilds():
-    say("config 3: generate 2^27 Plummer particles on the device")
+def test_plummer_2_27_and_incremental_rebuilds():
+    say("2^27 Plummer particles, generated on the device")
     x, y, z, _ = wl.device_sets([("plummer", N, SEED, 0)])
     cap = 8 * N // (N_CRIT + 1) + 64
     b = cs.Builder(N, N_CRIT, leaf_capacity=cap)
