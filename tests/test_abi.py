@@ -107,6 +107,34 @@ def test_batch_plan_layout_on_the_host():
         cs._lib.cstone_batch_destroy(plan)
 
 
+def test_batch_staged_upload_checks_its_stage_on_the_host():
+    """The tables' size is a host query, and a staged upload with no stage, or
+    one smaller than the tables, is refused before any device call."""
+    import numpy as np
+
+    import paper_2307_06345_amd as cs
+    unit = ((0, 0, 0), (1, 1, 1))
+    specs = [(1000, unit, 0, 8, 0), (8192, unit, 1, 64, 0), (3, unit, 1, 1, 0)]
+    st, plan = _plan(cs, specs)
+    assert st == 0
+    try:
+        need = int(cs._lib.cstone_batch_table_bytes(plan))
+        assert need >= 3 * 4  # at least the sets' bases
+        lay = cs.BatchLayout()
+        assert cs._lib.cstone_batch_get_layout(plan, ctypes.byref(lay), None, None, None) == 0
+        assert need <= lay.workspace_bytes
+        small = np.zeros(max(need - 1, 1), dtype=np.uint8)
+        fake_ws = ctypes.c_void_p(1 << 40)  # never touched: the checks come first
+        assert cs._lib.cstone_batch_upload_staged(plan, fake_ws, lay.workspace_bytes, None, need, None) == 1
+        assert cs._lib.cstone_batch_upload_staged(plan, fake_ws, lay.workspace_bytes,
+                                                  small.ctypes.data_as(ctypes.c_void_p), small.size, None) == 1
+        assert cs._lib.cstone_batch_upload_staged(plan, fake_ws, lay.workspace_bytes - 1,
+                                                  small.ctypes.data_as(ctypes.c_void_p), need, None) == 1
+        assert cs._lib.cstone_batch_table_bytes(None) == 0
+    finally:
+        cs._lib.cstone_batch_destroy(plan)
+
+
 def test_batch_plan_rejects_bad_sets():
     import paper_2307_06345_amd as cs
     unit = ((0, 0, 0), (1, 1, 1))
