@@ -850,6 +850,10 @@ namespace {
 // ids, 512-thread blocks at 4 waves per SIMD would spill).
 constexpr int kBBlock = 256;
 constexpr int kBTile = kBBlock * kRItems;
+// Blocks of a batched round: as many as stay resident (4 per CU), each taking
+// tiles until none are left, so the one tile counter sees about one ticket per
+// tile, not one more per block of a larger grid.
+constexpr uint32_t kBRoundGrid = 1024;
 constexpr int kBSpan = kBTile + 2 * kRHalo;
 
 __global__ __launch_bounds__(256) void batch_init_kernel(LoopState* st, const BatchSet* __restrict__ sets,
@@ -1201,7 +1205,8 @@ cstone_status launch_batch_rebalance(const uint64_t* P, size_t n_total, const Ba
     const uint32_t cap_u = static_cast<uint32_t>(split_capacity);
     for (uint32_t q = 0; q < rounds; ++q) {
         const int a = q & 1, b = (q + 1) & 1;
-        hipLaunchKernelGGL(batch_round_kernel, dim3(clamp_grid(grid_1d(C + 1, kBTile))), dim3(kBBlock), 0, stream,
+        hipLaunchKernelGGL(batch_round_kernel, dim3(std::min<uint32_t>(clamp_grid(grid_1d(C + 1, kBTile)), kBRoundGrid)),
+                           dim3(kBBlock), 0, stream,
                            sets, w.K[a], w.pos[a], w.sid[a], w.K[b], w.pos[b], w.sid[b], w.starts[b], n_sets,
                            w.changed_set + static_cast<size_t>(q) * n_sets, w.splits, cap_u, w.st,
                            static_cast<int>(q), static_cast<uint64_t>(C), w.lb);
