@@ -249,16 +249,25 @@ __device__ __forceinline__ void onesweep_tile(const TileDesc td, const uint64_t*
 
     // this pass's digit counts of the whole set, for the global digit offsets
     const uint32_t gcount = tid < RADIX ? ghist[tid] : 0u;
+    // item i of this lane sits at wave_base + lane + i * kWave: one base pointer
+    // and constant offsets (a 32-bit index per item would keep 16 widened
+    // indices live from the key loads to the value loads)
+    const uint64_t* kp = keys_in + (wave_base + lane);
     uint64_t k[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t idx = wave_base + i * kWave + lane;
-        k[i] = (FULL || idx < end) ? keys_in[idx] : 0ull;
+        k[i] = (FULL || idx < end) ? kp[i * kWave] : 0ull;
     }
     __syncthreads();  // counters cleared
 
     // stable rank of every key among the keys of its wave with the same digit
-    uint32_t rank[ITEMS];
+    // (below TILE <= 2^16: two ranks per register, which keeps the keys out of
+    // scratch)
+    static_assert(TILE <= 65536, "ranks and tile positions are packed in 16 bits");
+    uint32_t rank2[(ITEMS + 1) / 2];
+#pragma unroll
+    for (int i = 0; i < (ITEMS + 1) / 2; ++i) rank2[i] = 0;
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t idx = wave_base + i * kWave + lane;
@@ -269,7 +278,7 @@ __device__ __forceinline__ void onesweep_tile(const TileDesc td, const uint64_t*
         const uint32_t below = lanes_below(peers);
         const uint32_t base = whist[wave][d];
         if (ok && below == 0) whist[wave][d] = static_cast<uint16_t>(base + static_cast<uint32_t>(__popcll(peers)));
-        rank[i] = base + below;
+        rank2[i / 2] |= ((base + below) & 0xffffu) << ((i & 1) * 16);
     }
     __syncthreads();
 
@@ -297,22 +306,29 @@ __device__ __forceinline__ void onesweep_tile(const TileDesc td, const uint64_t*
     __syncthreads();
 
     // reorder the tile by digit in LDS before waiting on the other tiles
-    uint32_t lpos[ITEMS];
+    uint32_t lpos2[(ITEMS + 1) / 2];  // tile positions, two per register
+#pragma unroll
+    for (int i = 0; i < (ITEMS + 1) / 2; ++i) lpos2[i] = 0;
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t idx = wave_base + i * kWave + lane;
-        lpos[i] = whist[wave][digit_of<BITS>(k[i], shift)] + rank[i];
-        if (FULL || idx < end) stage[lpos[i]] = k[i];
+        const uint32_t lp = (whist[wave][digit_of<BITS>(k[i], shift)] + ((rank2[i / 2] >> ((i & 1) * 16)) & 0xffffu)) & 0xffffu;
+        lpos2[i / 2] |= lp << ((i & 1) * 16);
+        if (FULL || idx < end) stage[lp] = k[i];
     }
     // the permutation values are only needed for the scatter: start loading them
     // (not earlier: the keys must be dead by then to keep the registers in budget)
     __builtin_amdgcn_sched_barrier(0);
     uint32_t v[ITEMS];
-    if (WITH_VALUES) {
+    if constexpr (WITH_VALUES && FIRST) {
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) v[i] = wave_base + i * kWave + lane - td.seg_base;
+    } else if constexpr (WITH_VALUES) {
+        const uint32_t* vp = vals_in + (wave_base + lane);
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             const uint32_t idx = wave_base + i * kWave + lane;
-            v[i] = FIRST ? idx - td.seg_base : ((FULL || idx < end) ? vals_in[idx] : 0u);
+            v[i] = (FULL || idx < end) ? vp[i * kWave] : 0u;
         }
     }
     // every digit's exclusive prefix over the tiles before this one (one
@@ -388,7 +404,7 @@ __device__ __forceinline__ void onesweep_tile(const TileDesc td, const uint64_t*
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             const uint32_t idx = wave_base + i * kWave + lane;
-            if (FULL || idx < end) stage32[lpos[i]] = v[i];
+            if (FULL || idx < end) stage32[(lpos2[i / 2] >> ((i & 1) * 16)) & 0xffffu] = v[i];
         }
         __syncthreads();
 #pragma unroll
