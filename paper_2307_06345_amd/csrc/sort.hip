@@ -206,7 +206,7 @@ constexpr int kMinBlocks = (BLOCK <= 512 && BLOCK * ITEMS * 8 <= 72 * 1024 ? 2 :
 // own pace, and kernels on other streams may hold an XCD full. Such a wait
 // does not depend on that block: after a while the waiting block counts the
 // missing tile's digits itself (the look-back's fallback).
-constexpr uint32_t kXcdGroup = 8;
+constexpr uint32_t kXcdGroup = 16;
 // Waits (each one look-back round trip and a short sleep) before a block counts
 // a missing predecessor tile's digits itself: by default far longer than a
 // started block takes to publish its counts. Settable per device (0 sends
