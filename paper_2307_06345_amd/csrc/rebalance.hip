@@ -291,7 +291,7 @@ __global__ __launch_bounds__(256) void start_write_kernel(const uint32_t* __rest
 constexpr int kRHalo = 8;
 constexpr int kRSpan = kRTile + 2 * kRHalo;
 
-__global__ __launch_bounds__(kRBlock) void round_kernel(uint32_t n, uint32_t n_crit, const uint64_t* __restrict__ K,
+__global__ __launch_bounds__(kRBlock, 4) void round_kernel(uint32_t n, uint32_t n_crit, const uint64_t* __restrict__ K,
                                                          const uint32_t* __restrict__ pos,
                                                          uint64_t* __restrict__ K_out, uint32_t* __restrict__ pos_out,
                                                          uint64_t* __restrict__ splits, uint32_t split_capacity,
@@ -325,11 +325,30 @@ __global__ __launch_bounds__(kRBlock) void round_kernel(uint32_t n, uint32_t n_c
         const uint32_t tile = take_tile(st->counters[round], &slot);
         if (tile >= tiles) break;
         const int64_t base = static_cast<int64_t>(tile) * kRTile;
-        for (int j = tid; j < kRSpan; j += kRBlock) {  // K and positions of entries base-8 .. base+kRTile+7
-            const int64_t g = base - kRHalo + j;
-            if (g >= 0 && g <= static_cast<int64_t>(nl)) {
-                sK[j] = K[g];
-                sP[j] = pos[g];
+        {  // K and positions of entries base-8 .. base+kRTile+7: all loads in flight at once (an index
+           // outside 0 .. nl reads entry 0 or nl instead, and is not stored)
+            constexpr int kLoads = (kRSpan + kRBlock - 1) / kRBlock;
+            constexpr int kHalf = (kLoads + 1) / 2;  // two batches of loads keep the registers in budget
+#pragma unroll
+            for (int h = 0; h < kLoads; h += kHalf) {
+                uint64_t lk[kHalf];
+                uint32_t lp[kHalf];
+#pragma unroll
+                for (int q = 0; q < kHalf; ++q) {
+                    const int64_t g = base - kRHalo + static_cast<int64_t>(tid) + (h + q) * kRBlock;
+                    const int64_t c = min(max(g, int64_t{0}), static_cast<int64_t>(nl));
+                    lk[q] = K[c];
+                    lp[q] = pos[c];
+                }
+#pragma unroll
+                for (int q = 0; q < kHalf; ++q) {
+                    const int j = static_cast<int>(tid) + (h + q) * kRBlock;
+                    const int64_t g = base - kRHalo + j;
+                    if (h + q < kLoads && j < kRSpan && g >= 0 && g <= static_cast<int64_t>(nl)) {
+                        sK[j] = lk[q];
+                        sP[j] = lp[q];
+                    }
+                }
             }
         }
         __syncthreads();
