@@ -939,12 +939,39 @@ __global__ __launch_bounds__(BLOCK, kLocalBlocksPerCU * BLOCK / (4 * kWave)) voi
         s0 = chunk_set[blockIdx.x];
         first_at = chunk_set[gridDim.x + 1 + blockIdx.x];
     }
+    // every load of the window in flight at once (a load under a per-item
+    // branch would wait before the next one is issued)
+    if (wn == CAP) {  // block-uniform: a whole window, one base pointer and constant offsets
+        const uint64_t* kb = kin + (lo + tid);
+        const uint32_t* vb = vin + (lo + tid);
+        uint64_t wk[ITEMS];
+        uint32_t wv[ITEMS];
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t j = static_cast<uint32_t>(i) * BLOCK + tid;
-        if (j < wn) {
-            sm.keys[j] = kin[lo + j];
-            sm.vals[j] = vin[lo + j];
+        for (int i = 0; i < ITEMS; ++i) {
+            wk[i] = kb[i * BLOCK];
+            wv[i] = vb[i * BLOCK];
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            sm.keys[i * BLOCK + tid] = wk[i];
+            sm.vals[i * BLOCK + tid] = wv[i];
+        }
+    } else {  // the last windows: a position past the window reads its last entry (wn >= 1), not stored
+        uint64_t wk[ITEMS];
+        uint32_t wv[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t j = min(static_cast<uint32_t>(i) * BLOCK + tid, wn - 1u);
+            wk[i] = kin[lo + j];
+            wv[i] = vin[lo + j];
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t j = static_cast<uint32_t>(i) * BLOCK + tid;
+            if (j < wn) {
+                sm.keys[j] = wk[i];
+                sm.vals[j] = wv[i];
+            }
         }
     }
     const uint64_t before = lo ? kin[lo - 1] >> pshift : ~0ull;  // the same word in every lane
