@@ -100,19 +100,29 @@ constexpr int kBfWaves = kBfBlock / kWave;
 struct LeafLevels {
     int a[kBfItems];
     int lam[kBfItems];
+    uint64_t k[kBfItems];  // the keys themselves
 };
 
 __device__ __forceinline__ LeafLevels leaf_levels(const uint64_t* __restrict__ K, size_t nl, size_t first) {
+    // K[first - 1 .. first + kBfItems] (K holds nl + 1 keys), every load in flight at once; an
+    // index outside 0 .. nl reads a key that is not used
+    uint64_t kv[kBfItems + 2];
+#pragma unroll
+    for (int t = 0; t < kBfItems + 2; ++t) {
+        const size_t raw = first + t;  // key raw - 1
+        kv[t] = K[raw == 0 ? 0 : min(raw - 1, nl)];
+    }
     LeafLevels r;
 #pragma unroll
     for (int it = 0; it < kBfItems; ++it) {
         const size_t j = first + it;
         r.a[it] = 0;
         r.lam[it] = -1;  // no levels for padding items
+        r.k[it] = kv[it + 1];
         if (j < nl) {
-            const uint64_t kj = K[j];
-            r.lam[it] = span_level(K[j + 1] - kj);
-            r.a[it] = j ? (clz64(K[j - 1] ^ kj) - 1) / 3 : -1;
+            const uint64_t kj = kv[it + 1];
+            r.lam[it] = span_level(kv[it + 2] - kj);
+            r.a[it] = j ? (clz64(kv[it] ^ kj) - 1) / 3 : -1;
         }
     }
     return r;
@@ -172,7 +182,7 @@ __global__ __launch_bounds__(kBfBlock) void bf_scan_kernel(uint32_t* __restrict_
     if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
-__global__ __launch_bounds__(kBfBlock) void bf_write_kernel(const uint64_t* __restrict__ K, const uint64_t* nl_dev,
+__global__ __launch_bounds__(kBfBlock, 5) void bf_write_kernel(const uint64_t* __restrict__ K, const uint64_t* nl_dev,
                                                             size_t nl_host, const uint32_t* __restrict__ tile_offsets,
                                                             uint32_t stride, const uint32_t* __restrict__ totals,
                                                             uint64_t* __restrict__ nk, uint32_t* __restrict__ co,
@@ -214,7 +224,7 @@ __global__ __launch_bounds__(kBfBlock) void bf_write_kernel(const uint64_t* __re
         for (int it = 0; it < kBfItems; ++it) {
             const size_t j = first + it;
             if (j >= nl) continue;
-            const uint64_t kj = K[j];
+            const uint64_t kj = r.k[it];
             for (int l = r.a[it] + 1; l <= r.lam[it]; ++l) {
                 const uint32_t p = run[l][tid]++;
                 if (p >= n) continue;  // always in range for a cornerstone array; guards memory
@@ -235,17 +245,26 @@ __global__ __launch_bounds__(kBfBlock) void bf_write_kernel(const uint64_t* __re
 // at the set's first entry makes them relative to the set.
 
 __device__ __forceinline__ LeafLevels entry_levels(const uint64_t* __restrict__ K, size_t M, size_t first) {
+    // K[first - 1 .. first + kBfItems], every load in flight at once; an index outside
+    // 0 .. M - 1 reads a key that is not used (M >= 1 whenever a thread has an entry)
+    uint64_t kv[kBfItems + 2];
+#pragma unroll
+    for (int t = 0; t < kBfItems + 2; ++t) {
+        const size_t raw = first + t;  // entry raw - 1
+        kv[t] = M ? K[raw == 0 ? 0 : min(raw - 1, M - 1)] : 0ull;
+    }
     LeafLevels r;
 #pragma unroll
     for (int it = 0; it < kBfItems; ++it) {
         const size_t j = first + it;
         r.a[it] = 0;
         r.lam[it] = -1;
+        r.k[it] = kv[it + 1];
         if (j < M) {
-            const uint64_t kj = K[j];
+            const uint64_t kj = kv[it + 1];
             if (kj != kKeyEnd) {
-                r.lam[it] = span_level(K[j + 1] - kj);
-                r.a[it] = kj == 0 ? -1 : (clz64(K[j - 1] ^ kj) - 1) / 3;
+                r.lam[it] = span_level(kv[it + 2] - kj);
+                r.a[it] = kj == 0 ? -1 : (clz64(kv[it] ^ kj) - 1) / 3;
             }
         }
     }
@@ -380,7 +399,7 @@ __global__ __launch_bounds__(kBfBlock) void batch_bf_write_kernel(BatchTreeView 
         for (int it = 0; it < kBfItems; ++it) {
             const size_t j = first + it;
             if (j >= src.M || r.lam[it] < 0) continue;
-            const uint64_t kj = src.K[j];
+            const uint64_t kj = r.k[it];
             const uint32_t s = src.sid[j];
             if (s != cur) {
                 cur = s;
