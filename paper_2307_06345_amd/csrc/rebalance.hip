@@ -947,12 +947,44 @@ __global__ __launch_bounds__(kBBlock, 4) void batch_round_kernel(const BatchSet*
         const uint32_t tile = take_tile(st->counters[round], &slot);
         if (tile >= tiles) break;
         const int64_t base = static_cast<int64_t>(tile) * kBTile;
-        for (int j = tid; j < kBSpan; j += kBBlock) {  // coalesced: entries base-8 .. base+kBTile+7 that exist
-            const int64_t g = base - kRHalo + j;
-            if (g >= 0 && g < static_cast<int64_t>(M)) {
-                sK[j] = K[g];
-                sP[j] = pos[g];
-                sS[j] = sid[g];
+        if (base >= kRHalo && base + kBSpan - kRHalo <= static_cast<int64_t>(M)) {
+            // block-uniform: the whole span exists; its keys, then its positions and set ids, each
+            // batch of loads in flight at once (one base pointer, constant offsets)
+            constexpr int kFull = kBSpan / kBBlock;  // whole rows of the span; the rest below
+            const size_t g0 = static_cast<size_t>(base - kRHalo) + tid;
+            {
+                uint64_t lk[kFull];
+#pragma unroll
+                for (int q = 0; q < kFull; ++q) lk[q] = K[g0 + q * kBBlock];
+#pragma unroll
+                for (int q = 0; q < kFull; ++q) sK[tid + q * kBBlock] = lk[q];
+            }
+            {
+                uint32_t lp[kFull], ls[kFull];
+#pragma unroll
+                for (int q = 0; q < kFull; ++q) {
+                    lp[q] = pos[g0 + q * kBBlock];
+                    ls[q] = sid[g0 + q * kBBlock];
+                }
+#pragma unroll
+                for (int q = 0; q < kFull; ++q) {
+                    sP[tid + q * kBBlock] = lp[q];
+                    sS[tid + q * kBBlock] = ls[q];
+                }
+            }
+            for (int j = kFull * kBBlock + tid; j < kBSpan; j += kBBlock) {
+                sK[j] = K[g0 + (j - tid)];
+                sP[j] = pos[g0 + (j - tid)];
+                sS[j] = sid[g0 + (j - tid)];
+            }
+        } else {
+            for (int j = tid; j < kBSpan; j += kBBlock) {  // coalesced: entries base-8 .. base+kBTile+7 that exist
+                const int64_t g = base - kRHalo + j;
+                if (g >= 0 && g < static_cast<int64_t>(M)) {
+                    sK[j] = K[g];
+                    sP[j] = pos[g];
+                    sS[j] = sid[g];
+                }
             }
         }
         for (uint32_t j = tid; j < kSetFlags; j += kBBlock) sflag[j] = 0;
