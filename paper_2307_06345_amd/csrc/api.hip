@@ -209,13 +209,16 @@ cstone_status cstone_build(const double* x, const double* y, const double* z, si
         if (mark(0) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
         // The key kernel goes first (a long launch, so the host's later
         // launches overlap it) and stores per-block counts of the sort's first
-        // digit and per-block non-finite flags; the sort's set-up launch sums
-        // them, writes the flag word and clears what the passes need cleared.
+        // digit (of all three top digits for the split sort) and per-block
+        // non-finite flags; the sort's set-up launch sums them, writes the
+        // flag word and clears what the passes need cleared.
         if (n) {
-            uint32_t *hist_parts = nullptr, *bad_parts = nullptr, hist_mask = 0, hist_shift = 0, parts = 0;
-            sort_key_parts(stage_ws, n, true, 63, variant, &hist_parts, &bad_parts, &hist_mask, &hist_shift);
+            uint32_t *hist_parts = nullptr, *bad_parts = nullptr, hist_mask = 0, hist_shift = 0, parts = 0,
+                     hist_digits = 1;
+            sort_key_parts(stage_ws, n, true, 63, variant, &hist_parts, &bad_parts, &hist_mask, &hist_shift,
+                           &hist_digits);
             s = launch_keys(x, y, z, n, *box, curve, keys, nullptr, stream, hist_parts, hist_mask, hist_shift,
-                            bad_parts, &parts);
+                            bad_parts, &parts, hist_digits);
             if (s != CSTONE_OK) break;
             if (mark(1) != hipSuccess) { s = CSTONE_ERR_DEVICE; break; }
             if ((s = sort_setup_from_keys(stage_ws, n, true, variant, parts, flag, level6, stream)) != CSTONE_OK) break;

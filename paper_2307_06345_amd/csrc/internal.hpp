@@ -7,19 +7,22 @@ namespace cs {
 
 // keys.hip
 constexpr uint32_t kKeyBlocksMax = 512;  // blocks of the plain key kernel (grid-stride beyond)
+constexpr uint32_t kKeyDigitsMax = 3;    // digits the key kernel counts at most (the split sort's top digits)
 
 // First positions of the level-6 nodes, handed from the sort to the loop's start
 constexpr uint32_t kLevel6Cells = 1u << 18;
 constexpr uint32_t kCellEmpty = 0xffffffffu;
 // flags: NULL, or a word into which CSTONE_FLAG_NONFINITE is OR-ed.
-// hist_parts: NULL, or kKeyBlocksMax rows of 512 words; block b stores the
-// count of every key's ((key >> hist_shift) & hist_mask) into row b.
+// hist_parts: NULL, or kKeyDigitsMax x 512 columns of kKeyBlocksMax words;
+// block b stores, for d < hist_digits and every value v, the count of keys with
+// ((key >> (hist_shift + d * hist_bits)) & hist_mask) == v at
+// [(d * 512 + v) * kKeyBlocksMax + b] (hist_mask = 2^hist_bits - 1).
 // bad_parts: NULL, or kKeyBlocksMax words; block b stores CSTONE_FLAG_NONFINITE
 // or 0. *blocks_used (if not NULL): the rows and words written.
 cstone_status launch_keys(const double* x, const double* y, const double* z, size_t n, const cstone_box& box,
                           cstone_curve curve, uint64_t* keys, uint32_t* flags, hipStream_t stream,
                           uint32_t* hist_parts = nullptr, uint32_t hist_mask = 0, uint32_t hist_shift = 0,
-                          uint32_t* bad_parts = nullptr, uint32_t* blocks_used = nullptr);
+                          uint32_t* bad_parts = nullptr, uint32_t* blocks_used = nullptr, uint32_t hist_digits = 1);
 
 // sort.hip — stable radix sort of 64-bit keys (63 or 64 significant bits)
 // with an optional uint32 permutation; sig_bits selects how many low bits are
@@ -28,9 +31,10 @@ cstone_status launch_keys(const double* x, const double* y, const double* z, siz
 size_t sort_workspace_bytes(size_t n, bool with_perm);
 // pass_events: NULL, or sort_passes() + 1 events recorded before the first
 // pass and after every pass (split path: after the first top pass, after the
-// last one, after the bucket sort and after the low passes). prepared: sort_prepare() already ran on this
-// workspace, or the key kernel stored its per-block counts of the first digit
-// and sort_setup_from_keys() ran, so neither step is repeated.
+// last one, after the bucket sort and after the low passes). prepared: the key
+// kernel stored its per-block digit counts (sort_key_parts) and
+// sort_setup_from_keys() ran, so no set-up or first histogram is repeated, and
+// the split sort's top passes count no digits for the pass after them.
 // err_word: NULL, or a caller word (cleared beforehand) into which the sort's
 // kernels OR their error bits (a look-back wait that gave up, a bucket-list
 // overflow), all above the public CSTONE_FLAG_* bits.
@@ -49,13 +53,16 @@ bool sort_uses_split(size_t n, int sig_bits, bool with_perm, int variant);
 // sort shape the passes will use
 cstone_status sort_prepare(void* ws, size_t n, bool with_perm, hipStream_t stream, uint32_t* clear_word,
                            int variant);
-// Per-block first-digit counts and non-finite flags of the key kernel, in the
-// sort workspace: where to store them and which digit to count.
+// Per-block digit counts and non-finite flags of the key kernel, in the sort
+// workspace: where to store them and which digits to count (the first pass's
+// digit, or for the split sort its three top digits: a histogram does not
+// depend on the order of the keys, so the unsorted keys give every pass's).
 void sort_key_parts(void* ws, size_t n, bool with_perm, int sig_bits, int variant, uint32_t** hist_parts,
-                    uint32_t** bad_parts, uint32_t* mask, uint32_t* shift);
+                    uint32_t** bad_parts, uint32_t* mask, uint32_t* shift, uint32_t* digits);
 // Set-up after the key kernel stored its parts (replaces sort_prepare in a
-// build): the first digit's counts are the sum of the `parts` rows, *flag the
-// OR of the blocks' flags, and everything sort_prepare clears is cleared.
+// build): the counts of the digits sort_key_parts named are the sums of the
+// `parts` rows, *flag the OR of the blocks' flags, and everything sort_prepare
+// clears is cleared.
 cstone_status sort_setup_from_keys(void* ws, size_t n, bool with_perm, int variant, uint32_t parts, uint32_t* flag,
                                    uint32_t* level6, hipStream_t stream);
 int sort_passes(size_t n, int sig_bits, bool with_perm, int variant);

@@ -79,17 +79,21 @@ __global__ __launch_bounds__(kKeysBlockPlain) void keys_kernel(const double* __r
                                                           double lo1, double lo2, double s0, double s1, double s2,
                                                           uint64_t* __restrict__ keys, uint32_t* flags,
                                                           uint32_t* hist_parts, uint32_t hmask, uint32_t hshift,
-                                                          uint32_t* bad_parts) {
+                                                          uint32_t* bad_parts, uint32_t hdigits, uint32_t hbits) {
     __shared__ uint16_t two[kStates * 64];
     __shared__ uint16_t first[8];
-    __shared__ uint32_t h[512];
+    __shared__ uint32_t h[kKeyDigitsMax * 512];
     if (CURVE == CSTONE_HILBERT) {
         for (int i = threadIdx.x; i < kStates * 64; i += kKeysBlockPlain) two[i] = d_hilbert.two[i];
         if (threadIdx.x < 8) first[threadIdx.x] = d_hilbert.first[threadIdx.x];
     }
     if (hist_parts)
-        for (int i = threadIdx.x; i < 512; i += kKeysBlockPlain) h[i] = 0;
+        for (uint32_t i = threadIdx.x; i < hdigits * 512; i += kKeysBlockPlain) h[i] = 0;
     __syncthreads();
+    // counts of digit d (d < hdigits) of a key, part d of the block's row
+    auto count = [&](uint64_t k) {
+        for (uint32_t d = 0; d < hdigits; ++d) atomicAdd(&h[d * 512 + ((k >> (hshift + d * hbits)) & hmask)], 1u);
+    };
     bool bad = false;
     const size_t stride = static_cast<size_t>(gridDim.x) * kKeysBlockPlain;
     const size_t t0 = static_cast<size_t>(blockIdx.x) * kKeysBlockPlain + threadIdx.x;
@@ -107,8 +111,8 @@ __global__ __launch_bounds__(kKeysBlockPlain) void keys_kernel(const double* __r
             k.y = key_of<CURVE>(cx.y, cy.y, cz.y, lo0, lo1, lo2, s0, s1, s2, two, first);
             k2[p] = k;
             if (hist_parts) {
-                atomicAdd(&h[(k.x >> hshift) & hmask], 1u);
-                atomicAdd(&h[(k.y >> hshift) & hmask], 1u);
+                count(k.x);
+                count(k.y);
             }
         }
         if ((n & 1) && t0 == 0) {
@@ -116,7 +120,7 @@ __global__ __launch_bounds__(kKeysBlockPlain) void keys_kernel(const double* __r
             bad |= !finite3(x[p], y[p], z[p]);
             const uint64_t k = key_of<CURVE>(x[p], y[p], z[p], lo0, lo1, lo2, s0, s1, s2, two, first);
             keys[p] = k;
-            if (hist_parts) atomicAdd(&h[(k >> hshift) & hmask], 1u);
+            if (hist_parts) count(k);
         }
     } else {
         for (size_t p = t0; p < n; p += stride) {
@@ -124,7 +128,7 @@ __global__ __launch_bounds__(kKeysBlockPlain) void keys_kernel(const double* __r
             bad |= !finite3(cx, cy, cz);
             const uint64_t k = key_of<CURVE>(cx, cy, cz, lo0, lo1, lo2, s0, s1, s2, two, first);
             keys[p] = k;
-            if (hist_parts) atomicAdd(&h[(k >> hshift) & hmask], 1u);
+            if (hist_parts) count(k);
         }
     }
     if (flags && __ballot(bad) != 0ull && lane_id() == 0) atomicOr(flags, CSTONE_FLAG_NONFINITE);
@@ -136,18 +140,20 @@ __global__ __launch_bounds__(kKeysBlockPlain) void keys_kernel(const double* __r
     }
     if (hist_parts) {
         __syncthreads();
-        uint32_t* mine = hist_parts + static_cast<size_t>(blockIdx.x) * 512;
-        for (uint32_t i = threadIdx.x; i <= hmask; i += kKeysBlockPlain) mine[i] = h[i];
+        // column-major (block fastest), so the set-up reads every column in one piece
+        for (uint32_t d = 0; d < hdigits; ++d)
+            for (uint32_t i = threadIdx.x; i <= hmask; i += kKeysBlockPlain)
+                hist_parts[static_cast<size_t>(d * 512 + i) * kKeyBlocksMax + blockIdx.x] = h[d * 512 + i];
     }
 }
 
 template <int CURVE, bool PAIRED>
 void launch_keys_t(size_t blocks, hipStream_t stream, const double* x, const double* y, const double* z, size_t n,
                    const cstone_box& box, const double* s, uint64_t* keys, uint32_t* flags, uint32_t* hist_parts,
-                   uint32_t hmask, uint32_t hshift, uint32_t* bad_parts) {
+                   uint32_t hmask, uint32_t hshift, uint32_t* bad_parts, uint32_t hdigits, uint32_t hbits) {
     hipLaunchKernelGGL((keys_kernel<CURVE, PAIRED>), dim3(blocks), dim3(kKeysBlockPlain), 0, stream, x, y, z, n,
                        box.lo[0], box.lo[1], box.lo[2], s[0], s[1], s[2], keys, flags, hist_parts, hmask, hshift,
-                       bad_parts);
+                       bad_parts, hdigits, hbits);
 }
 
 // Batched keys: block b encodes tile tiles[b] = {first particle, count, -, set}
@@ -209,10 +215,13 @@ cstone_status launch_keys_batch(const double* x, const double* y, const double* 
 cstone_status launch_keys(const double* x, const double* y, const double* z, size_t n, const cstone_box& box,
                           cstone_curve curve, uint64_t* keys, uint32_t* flags, hipStream_t stream,
                           uint32_t* hist_parts, uint32_t hist_mask, uint32_t hist_shift, uint32_t* bad_parts,
-                          uint32_t* blocks_used) {
+                          uint32_t* blocks_used, uint32_t hist_digits) {
     if (blocks_used) *blocks_used = 0;
     if (n == 0) return CSTONE_OK;
-    if (hist_parts && (hist_mask >= 512 || hist_shift >= 64)) return CSTONE_ERR_INVALID_ARG;
+    const uint32_t hist_bits = static_cast<uint32_t>(__builtin_popcount(hist_mask));
+    if (hist_parts && (hist_mask >= 512 || ((hist_mask + 1) & hist_mask) != 0 || hist_digits < 1 ||
+                       hist_digits > kKeyDigitsMax || hist_shift + hist_digits * hist_bits > 64))
+        return CSTONE_ERR_INVALID_ARG;
     double s[3];
     for (int d = 0; d < 3; ++d) s[d] = 2097152.0 / (box.hi[d] - box.lo[d]);
     auto aligned = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; };
@@ -224,17 +233,17 @@ cstone_status launch_keys(const double* x, const double* y, const double* z, siz
     if (curve == CSTONE_HILBERT) {
         if (paired)
             launch_keys_t<CSTONE_HILBERT, true>(blocks, stream, x, y, z, n, box, s, keys, flags, hist_parts, hist_mask,
-                                                   hist_shift, bad_parts);
+                                                   hist_shift, bad_parts, hist_digits, hist_bits);
         else
             launch_keys_t<CSTONE_HILBERT, false>(blocks, stream, x, y, z, n, box, s, keys, flags, hist_parts, hist_mask,
-                                                   hist_shift, bad_parts);
+                                                   hist_shift, bad_parts, hist_digits, hist_bits);
     } else {
         if (paired)
             launch_keys_t<CSTONE_MORTON, true>(blocks, stream, x, y, z, n, box, s, keys, flags, hist_parts, hist_mask,
-                                                   hist_shift, bad_parts);
+                                                   hist_shift, bad_parts, hist_digits, hist_bits);
         else
             launch_keys_t<CSTONE_MORTON, false>(blocks, stream, x, y, z, n, box, s, keys, flags, hist_parts, hist_mask,
-                                                   hist_shift, bad_parts);
+                                                   hist_shift, bad_parts, hist_digits, hist_bits);
     }
     CS_HIP(hipGetLastError());
     return CSTONE_OK;

@@ -35,13 +35,15 @@ __global__ __launch_bounds__(256) void sort_init_kernel(uint32_t* ghist, size_t 
     }
 }
 
-// Set-up of a build's sort from the key kernel's per-block parts: block d < radix
-// sums digit d over the parts, block radix ORs the blocks' flags into *flag;
-// all blocks clear what sort_init_kernel clears (but the first digit's counts).
+// Set-up of a build's sort from the key kernel's per-block parts: block
+// p * radix + d (p < digits, d < radix) sums digit value d of pass p over the
+// parts, block digits * radix ORs the blocks' flags into *flag; all blocks
+// clear what sort_init_kernel clears (but the counts summed here).
 __global__ __launch_bounds__(kKeyBlocksMax) void sort_setup_kernel(uint32_t* ghist, size_t ghist_words, uint32_t* err,
                                                                   uint64_t* lb, size_t lb_words,
                                                                   const uint32_t* __restrict__ parts, uint32_t nparts,
-                                                                  uint32_t radix, const uint32_t* __restrict__ bad,
+                                                                  uint32_t radix, uint32_t digits,
+                                                                  const uint32_t* __restrict__ bad,
                                                                   uint32_t* flag, uint32_t* level6) {
     __shared__ uint32_t red[kKeyBlocksMax / kWave];
     const uint32_t tid = threadIdx.x;
@@ -50,12 +52,15 @@ __global__ __launch_bounds__(kKeyBlocksMax) void sort_setup_kernel(uint32_t* ghi
     for (size_t i = t; i < lb_words; i += stride) lb[i] = 0;
     if (level6)
         for (size_t i = t; i < kLevel6Cells; i += stride) level6[i] = kCellEmpty;
-    for (size_t i = radix + t; i < ghist_words; i += stride) ghist[i] = 0;
+    const uint32_t counted = digits * radix;
+    for (size_t i = counted + t; i < ghist_words; i += stride) ghist[i] = 0;
     const uint32_t d = blockIdx.x;
-    if (d <= radix) {  // block-uniform
+    if (d <= counted) {  // block-uniform
         uint32_t v = 0;
-        if (tid < nparts) v = d < radix ? parts[static_cast<size_t>(tid) * kMaxRadix + d] : bad[tid];
-        if (d < radix) {
+        if (tid < nparts)
+            v = d < counted ? parts[static_cast<size_t>((d / radix) * kMaxRadix + d % radix) * kKeyBlocksMax + tid]
+                            : bad[tid];
+        if (d < counted) {
             v = wave_inclusive_sum(v);
             if (lane_id() == kWave - 1) red[tid / kWave] = v;
         } else {
@@ -65,9 +70,9 @@ __global__ __launch_bounds__(kKeyBlocksMax) void sort_setup_kernel(uint32_t* ghi
         __syncthreads();
         if (tid == 0) {
             uint32_t acc = 0;
-            for (uint32_t w = 0; w < kKeyBlocksMax / kWave; ++w) acc = d < radix ? acc + red[w] : (acc | red[w]);
-            if (d < radix) {
-                ghist[d] = acc;
+            for (uint32_t w = 0; w < kKeyBlocksMax / kWave; ++w) acc = d < counted ? acc + red[w] : (acc | red[w]);
+            if (d < counted) {
+                ghist[d] = acc;  // pass d / radix, digit value d % radix
             } else {
                 *flag = acc;
                 *err = 0;
@@ -1246,7 +1251,7 @@ SortWs carve_sort(void* ws, size_t n, bool with_perm) {
         s.large_tiles = c.take<uint4>(s.max_tiles_any);
         s.large_start = c.take<uint32_t>(s.max_buckets + 1);
         s.large_hist = c.take<uint32_t>((s.max_buckets + 1) * kLowPasses * kMaxRadix);
-        s.key_parts = c.take<uint32_t>(static_cast<size_t>(kKeyBlocksMax) * kMaxRadix);
+        s.key_parts = c.take<uint32_t>(static_cast<size_t>(kKeyBlocksMax) * kKeyDigitsMax * kMaxRadix);
         s.key_bad = c.take<uint32_t>(kKeyBlocksMax);
     }
     s.bytes = c.off;
@@ -1292,10 +1297,12 @@ cstone_status sort_prepare(void* ws, size_t n, bool with_perm, hipStream_t strea
 }
 
 void sort_key_parts(void* ws, size_t n, bool with_perm, int sig_bits, int variant, uint32_t** hist_parts,
-                    uint32_t** bad_parts, uint32_t* mask, uint32_t* shift) {
+                    uint32_t** bad_parts, uint32_t* mask, uint32_t* shift, uint32_t* digits) {
     const Variant& var = variant_or_builtin(variant);
+    const bool split = use_split(n, sig_bits, with_perm, var);
     *mask = (1u << var.bits) - 1u;
-    *shift = use_split(n, sig_bits, with_perm, var) ? kSplitShift : 0u;
+    *shift = split ? kSplitShift : 0u;
+    *digits = split ? static_cast<uint32_t>(kSplitTop) : 1u;
     const SortWs s = carve_sort(ws, n, with_perm);
     *hist_parts = s.key_parts;
     *bad_parts = s.key_bad;
@@ -1312,9 +1319,10 @@ cstone_status sort_setup_from_keys(void* ws, size_t n, bool with_perm, int varia
     const bool wide = n >= (1ull << 30);
     const size_t lb_words = std::min(s.lb_bytes / 8, wide ? words : (words + 1) / 2);
     const uint32_t radix = 1u << var.bits;
-    hipLaunchKernelGGL(sort_setup_kernel, dim3(radix + 1), dim3(kKeyBlocksMax), 0, stream, s.ghist,
+    const uint32_t digits = use_split(n, 63, with_perm, var) ? static_cast<uint32_t>(kSplitTop) : 1u;
+    hipLaunchKernelGGL(sort_setup_kernel, dim3(digits * radix + 1), dim3(kKeyBlocksMax), 0, stream, s.ghist,
                        static_cast<size_t>(kGhistWords), s.err, static_cast<uint64_t*>(s.lb), lb_words, s.key_parts,
-                       parts, radix, s.key_bad, flag, level6);
+                       parts, radix, digits, s.key_bad, flag, level6);
     CS_HIP(hipGetLastError());
     return CSTONE_OK;
 }
@@ -1330,7 +1338,7 @@ namespace {
 // listed buckets keys_out -> alt -> ... -> keys_out.
 cstone_status launch_split(const uint64_t* keys_in, uint64_t* keys_out, uint32_t* perm_out, size_t n,
                            const SortWs& s, const Variant& var, bool wide, hipStream_t stream,
-                           hipEvent_t* pass_events, uint32_t* err, uint32_t* level6) {
+                           hipEvent_t* pass_events, uint32_t* err, uint32_t* level6, bool top_counted) {
     constexpr int radix = 1 << kSplitBits;
     uint32_t* lb32[2] = {static_cast<uint32_t*>(s.lb), static_cast<uint32_t*>(s.lb) + s.rows * kMaxRadix};
     if (pass_events) CS_HIP(hipEventRecord(pass_events[0], stream));
@@ -1346,7 +1354,9 @@ cstone_status launch_split(const uint64_t* keys_in, uint64_t* keys_out, uint32_t
         a.n = static_cast<uint32_t>(n);
         a.shift = kSplitShift + p * kSplitBits;
         a.ghist = s.ghist + p * radix;
-        a.ghist_next = p + 1 < kSplitTop ? s.ghist + (p + 1) * radix : nullptr;
+        // every top digit's counts came from the key kernel (top_counted), else
+        // each top pass counts the next one's
+        a.ghist_next = p + 1 < kSplitTop && !top_counted ? s.ghist + (p + 1) * radix : nullptr;
         a.shift_next = kSplitShift + (p + 1) * kSplitBits;
         a.wide = wide;
         a.lb = wide ? s.lb : static_cast<void*>(lb32[p & 1]);
@@ -1438,7 +1448,8 @@ cstone_status launch_sort(const uint64_t* keys_in, uint64_t* keys_out, uint32_t*
                            s.ghist);
     }
     uint32_t* err = err_word ? err_word : s.err;
-    if (split) return launch_split(keys_in, keys_out, perm_out, n, s, var, wide, stream, pass_events, err, level6);
+    if (split)
+        return launch_split(keys_in, keys_out, perm_out, n, s, var, wide, stream, pass_events, err, level6, prepared);
 
     uint32_t* lb32[2] = {static_cast<uint32_t*>(s.lb), static_cast<uint32_t*>(s.lb) + s.rows * kMaxRadix};
     if (pass_events) CS_HIP(hipEventRecord(pass_events[0], stream));
