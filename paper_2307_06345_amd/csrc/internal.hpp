@@ -13,10 +13,10 @@ constexpr uint32_t kKeyDigitsMax = 3;    // digits the key kernel counts at most
 constexpr uint32_t kLevel6Cells = 1u << 18;
 constexpr uint32_t kCellEmpty = 0xffffffffu;
 // flags: NULL, or a word into which CSTONE_FLAG_NONFINITE is OR-ed.
-// hist_parts: NULL, or kKeyDigitsMax x 512 columns of kKeyBlocksMax words;
-// block b stores, for d < hist_digits and every value v, the count of keys with
+// hist_parts: NULL, or kKeyBlocksMax rows of kKeyDigitsMax x 512 words; block b
+// stores, for d < hist_digits and every value v, the count of keys with
 // ((key >> (hist_shift + d * hist_bits)) & hist_mask) == v at
-// [(d * 512 + v) * kKeyBlocksMax + b] (hist_mask = 2^hist_bits - 1).
+// [b * kKeyDigitsMax * 512 + d * 512 + v] (hist_mask = 2^hist_bits - 1).
 // bad_parts: NULL, or kKeyBlocksMax words; block b stores CSTONE_FLAG_NONFINITE
 // or 0. *blocks_used (if not NULL): the rows and words written.
 cstone_status launch_keys(const double* x, const double* y, const double* z, size_t n, const cstone_box& box,

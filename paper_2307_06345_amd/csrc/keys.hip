@@ -140,10 +140,9 @@ __global__ __launch_bounds__(kKeysBlockPlain) void keys_kernel(const double* __r
     }
     if (hist_parts) {
         __syncthreads();
-        // column-major (block fastest), so the set-up reads every column in one piece
+        uint32_t* mine = hist_parts + static_cast<size_t>(blockIdx.x) * (kKeyDigitsMax * 512);
         for (uint32_t d = 0; d < hdigits; ++d)
-            for (uint32_t i = threadIdx.x; i <= hmask; i += kKeysBlockPlain)
-                hist_parts[static_cast<size_t>(d * 512 + i) * kKeyBlocksMax + blockIdx.x] = h[d * 512 + i];
+            for (uint32_t i = threadIdx.x; i <= hmask; i += kKeysBlockPlain) mine[d * 512 + i] = h[d * 512 + i];
     }
 }
 

@@ -35,48 +35,58 @@ __global__ __launch_bounds__(256) void sort_init_kernel(uint32_t* ghist, size_t 
     }
 }
 
-// Set-up of a build's sort from the key kernel's per-block parts: block
-// p * radix + d (p < digits, d < radix) sums digit value d of pass p over the
-// parts, block digits * radix ORs the blocks' flags into *flag; all blocks
-// clear what sort_init_kernel clears (but the counts summed here).
+// Set-up of a build's sort from the key kernel's per-block parts (rows of
+// kKeyDigitsMax x kMaxRadix words, one per key block): block j < digits *
+// kMaxRadix / kSetupCols sums columns [j * kSetupCols, (j + 1) * kSetupCols)
+// over the parts' rows (column p * kMaxRadix + v: digit value v of pass p),
+// reading whole row segments; the last block ORs the blocks' flags into *flag;
+// all blocks clear what sort_init_kernel clears (but the counts summed here).
+constexpr uint32_t kSetupCols = kWave;
+constexpr uint32_t kSetupGroups = kKeyBlocksMax / kSetupCols;  // row groups of a summing block
 __global__ __launch_bounds__(kKeyBlocksMax) void sort_setup_kernel(uint32_t* ghist, size_t ghist_words, uint32_t* err,
                                                                   uint64_t* lb, size_t lb_words,
                                                                   const uint32_t* __restrict__ parts, uint32_t nparts,
                                                                   uint32_t radix, uint32_t digits,
                                                                   const uint32_t* __restrict__ bad,
                                                                   uint32_t* flag, uint32_t* level6) {
-    __shared__ uint32_t red[kKeyBlocksMax / kWave];
+    __shared__ uint32_t red[kKeyBlocksMax];
     const uint32_t tid = threadIdx.x;
     const size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + tid;
     const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
     for (size_t i = t; i < lb_words; i += stride) lb[i] = 0;
     if (level6)
         for (size_t i = t; i < kLevel6Cells; i += stride) level6[i] = kCellEmpty;
-    const uint32_t counted = digits * radix;
-    for (size_t i = counted + t; i < ghist_words; i += stride) ghist[i] = 0;
-    const uint32_t d = blockIdx.x;
-    if (d <= counted) {  // block-uniform
-        uint32_t v = 0;
-        if (tid < nparts)
-            v = d < counted ? parts[static_cast<size_t>((d / radix) * kMaxRadix + d % radix) * kKeyBlocksMax + tid]
-                            : bad[tid];
-        if (d < counted) {
-            v = wave_inclusive_sum(v);
-            if (lane_id() == kWave - 1) red[tid / kWave] = v;
-        } else {
-            v = __ballot(v != 0) ? CSTONE_FLAG_NONFINITE : 0u;
-            if (lane_id() == 0) red[tid / kWave] = v;
+    for (size_t i = digits * radix + t; i < ghist_words; i += stride) ghist[i] = 0;
+    const uint32_t sums = digits * kMaxRadix / kSetupCols;
+    const uint32_t j = blockIdx.x;
+    if (j < sums) {  // block-uniform
+        constexpr uint32_t kRows = kKeyBlocksMax / kSetupGroups;  // rows per thread at most
+        const uint32_t col = j * kSetupCols + tid % kSetupCols, g = tid / kSetupCols;
+        uint32_t acc = 0;
+        // rows g, g + kSetupGroups, ...: every load in flight (a row past nparts
+        // reads row 0, not counted)
+        uint32_t v[kRows];
+#pragma unroll
+        for (uint32_t q = 0; q < kRows; ++q) {
+            const uint32_t r = g + q * kSetupGroups;
+            v[q] = parts[static_cast<size_t>(r < nparts ? r : 0u) * (kKeyDigitsMax * kMaxRadix) + col];
         }
+#pragma unroll
+        for (uint32_t q = 0; q < kRows; ++q) acc += g + q * kSetupGroups < nparts ? v[q] : 0u;
+        red[tid] = acc;
         __syncthreads();
+        if (tid < kSetupCols) {
+            uint32_t total = 0;
+            for (uint32_t w = 0; w < kSetupGroups; ++w) total += red[w * kSetupCols + tid];
+            const uint32_t p = col / kMaxRadix, d = col % kMaxRadix;
+            if (d < radix) ghist[p * radix + d] = total;
+        }
+    } else if (j == sums) {  // block-uniform: the flags
+        const uint32_t f = tid < nparts ? bad[tid] : 0u;
+        const uint32_t any = __syncthreads_or(f != 0);
         if (tid == 0) {
-            uint32_t acc = 0;
-            for (uint32_t w = 0; w < kKeyBlocksMax / kWave; ++w) acc = d < counted ? acc + red[w] : (acc | red[w]);
-            if (d < counted) {
-                ghist[d] = acc;  // pass d / radix, digit value d % radix
-            } else {
-                *flag = acc;
-                *err = 0;
-            }
+            *flag = any ? CSTONE_FLAG_NONFINITE : 0u;
+            *err = 0;
         }
     }
 }
@@ -1320,7 +1330,9 @@ cstone_status sort_setup_from_keys(void* ws, size_t n, bool with_perm, int varia
     const size_t lb_words = std::min(s.lb_bytes / 8, wide ? words : (words + 1) / 2);
     const uint32_t radix = 1u << var.bits;
     const uint32_t digits = use_split(n, 63, with_perm, var) ? static_cast<uint32_t>(kSplitTop) : 1u;
-    hipLaunchKernelGGL(sort_setup_kernel, dim3(digits * radix + 1), dim3(kKeyBlocksMax), 0, stream, s.ghist,
+    // the summing blocks and the flag block, and enough blocks besides for the clearing
+    const uint32_t grid = std::max<uint32_t>(digits * kMaxRadix / kSetupCols + 1, kMaxRadix + 1);
+    hipLaunchKernelGGL(sort_setup_kernel, dim3(grid), dim3(kKeyBlocksMax), 0, stream, s.ghist,
                        static_cast<size_t>(kGhistWords), s.err, static_cast<uint64_t*>(s.lb), lb_words, s.key_parts,
                        parts, radix, digits, s.key_bad, flag, level6);
     CS_HIP(hipGetLastError());
