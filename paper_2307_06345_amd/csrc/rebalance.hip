@@ -1156,25 +1156,58 @@ __global__ __launch_bounds__(256) void batch_finalize_kernel(LoopState* st, uint
     const uint32_t* starts = odd ? starts1 : starts0;
     const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
     const size_t t0 = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    for (size_t e = t0; e < M; e += stride) {
-        const uint32_t s = sid[e];
-        const BatchSet& S = sets[s];
-        const uint64_t i = e - starts[s];
-        const uint64_t nl = starts[s + 1] - starts[s] - 1;
-        if (nl > S.cap) continue;  // this set outgrew its region
-        leaves[S.leaf_off + i] = K[e];
-        if (i < nl) counts[S.leaf_off + i] = pos[e + 1] - pos[e];
+    // kFinItems entries per thread, blockDim.x apart (coalesced): their keys,
+    // positions and set ids loaded together (indices clamped to the array),
+    // then their sets' records, then the stores
+    constexpr int kFinItems = 4;
+    const size_t span = static_cast<size_t>(blockDim.x) * kFinItems;
+    for (size_t b0 = static_cast<size_t>(blockIdx.x) * span; b0 < M; b0 += static_cast<size_t>(gridDim.x) * span) {
+        uint64_t kk[kFinItems];
+        uint32_t ss[kFinItems], p0[kFinItems], p1[kFinItems];
+#pragma unroll
+        for (int q = 0; q < kFinItems; ++q) {
+            const size_t e = min(b0 + q * blockDim.x + threadIdx.x, static_cast<size_t>(M - 1));
+            kk[q] = K[e];
+            ss[q] = sid[e];
+            p0[q] = pos[e];
+            p1[q] = pos[min(e + 1, static_cast<size_t>(M - 1))];
+        }
+        uint64_t off[kFinItems], cap[kFinItems];
+        uint32_t first[kFinItems], next[kFinItems];
+#pragma unroll
+        for (int q = 0; q < kFinItems; ++q) {
+            off[q] = sets[ss[q]].leaf_off;
+            cap[q] = sets[ss[q]].cap;
+            first[q] = starts[ss[q]];
+            next[q] = starts[ss[q] + 1];
+        }
+#pragma unroll
+        for (int q = 0; q < kFinItems; ++q) {
+            const size_t e = b0 + q * blockDim.x + threadIdx.x;
+            const uint64_t nl = next[q] - first[q] - 1;
+            if (e >= M || nl > cap[q]) continue;  // past the array, or this set outgrew its region
+            const uint64_t i = e - first[q];
+            leaves[off[q] + i] = kk[q];
+            if (i < nl) counts[off[q] + i] = p1[q] - p0[q];  // entry e + 1 is in the same set
+        }
     }
     for (size_t s = t0; s < n_sets; s += stride) {
         const uint64_t nl = M ? starts[s + 1] - starts[s] - 1 : 0;
         uint32_t rounds = o.last, status;
         bool converged = false;
-        for (uint32_t q = 0; q < o.last; ++q)
-            if (changed_set[static_cast<size_t>(q) * n_sets + s] == 0) {
-                rounds = q + 1;
-                converged = true;
-                break;
-            }
+        // the first round in which the set changed nothing: flags read 8 rounds at a time
+        for (uint32_t q0 = 0; q0 < o.last && !converged; q0 += 8) {
+            uint32_t c[8];
+#pragma unroll
+            for (uint32_t q = 0; q < 8; ++q)
+                c[q] = changed_set[static_cast<size_t>(min(q0 + q, o.last - 1)) * n_sets + s];
+#pragma unroll
+            for (uint32_t q = 0; q < 8; ++q)
+                if (!converged && q0 + q < o.last && c[q] == 0) {
+                    rounds = q0 + q + 1;
+                    converged = true;
+                }
+        }
         // a device-side wait that gave up (in the sort or a round's look-back)
         // leaves every set's arrays unreliable
         if (st->err != 0 || (sort_err && *sort_err != 0))
