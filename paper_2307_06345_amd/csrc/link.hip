@@ -128,6 +128,21 @@ __device__ __forceinline__ LeafLevels leaf_levels(const uint64_t* __restrict__ K
     return r;
 }
 
+// Wave total of a per-lane count v < 8, and this lane's exclusive prefix of
+// it, from its three bit planes: three ballots and bit counts instead of a
+// chain of cross-lane shuffles.
+static_assert(kBfItems < 8, "a lane's count of one level fits in three bits");
+__device__ __forceinline__ uint32_t wave_count_total(uint32_t v) {
+    return static_cast<uint32_t>(__popcll(__ballot(v & 1u))) + 2u * static_cast<uint32_t>(__popcll(__ballot(v & 2u))) +
+           4u * static_cast<uint32_t>(__popcll(__ballot(v & 4u)));
+}
+__device__ __forceinline__ uint32_t wave_count_prefix(uint32_t v, uint32_t* total) {
+    const uint64_t b0 = __ballot(v & 1u), b1 = __ballot(v & 2u), b2 = __ballot(v & 4u);
+    *total = static_cast<uint32_t>(__popcll(b0)) + 2u * static_cast<uint32_t>(__popcll(b1)) +
+             4u * static_cast<uint32_t>(__popcll(b2));
+    return lanes_below(b0) + 2u * lanes_below(b1) + 4u * lanes_below(b2);
+}
+
 __device__ __forceinline__ uint32_t level_count(const LeafLevels& r, int l) {
     uint32_t c = 0;
 #pragma unroll
@@ -148,7 +163,7 @@ __global__ __launch_bounds__(kBfBlock) void bf_count_kernel(const uint64_t* __re
         const LeafLevels r = leaf_levels(K, nl, static_cast<size_t>(tile) * kBfTile + threadIdx.x * kBfItems);
 #pragma unroll
         for (int l = 0; l < kLevels; ++l) {
-            const uint32_t s = wave_sum<uint32_t>(level_count(r, l));
+            const uint32_t s = wave_count_total(level_count(r, l));
             if (lane_id() == 0) wtot[l][wave] = s;
         }
         __syncthreads();
@@ -204,12 +219,12 @@ __global__ __launch_bounds__(kBfBlock, 5) void bf_write_kernel(const uint64_t* _
     for (uint32_t tile = blockIdx.x; tile < tiles && tile < stride; tile += gridDim.x) {
         const size_t first = static_cast<size_t>(tile) * kBfTile + tid * kBfItems;
         const LeafLevels r = leaf_levels(K, nl, first);
-        uint32_t c[kLevels], inc[kLevels];
+        uint32_t ex[kLevels];  // this lane's exclusive prefix in its wave, per level
 #pragma unroll
         for (int l = 0; l < kLevels; ++l) {
-            c[l] = level_count(r, l);
-            inc[l] = wave_inclusive_sum(c[l]);
-            if (lane_id() == kWave - 1) wtot[l][wave] = inc[l];
+            uint32_t total;
+            ex[l] = wave_count_prefix(level_count(r, l), &total);
+            if (lane_id() == 0) wtot[l][wave] = total;
         }
         __syncthreads();
 #pragma unroll
@@ -217,7 +232,7 @@ __global__ __launch_bounds__(kBfBlock, 5) void bf_write_kernel(const uint64_t* _
             uint32_t before = 0;
 #pragma unroll
             for (int w = 0; w < kBfWaves; ++w) before += w < static_cast<int>(wave) ? wtot[l][w] : 0u;
-            run[l][tid] = lo[l] + tile_offsets[static_cast<size_t>(l) * stride + tile] + before + inc[l] - c[l];
+            run[l][tid] = lo[l] + tile_offsets[static_cast<size_t>(l) * stride + tile] + before + ex[l];
         }
         // each thread only touches its own column of run[][]
 #pragma unroll
@@ -295,7 +310,7 @@ __global__ __launch_bounds__(kBfBlock) void batch_bf_count_kernel(BatchTreeView 
             entry_levels(src.K, src.M, static_cast<size_t>(tile) * kBfTile + threadIdx.x * kBfItems);
 #pragma unroll
         for (int l = 0; l < kLevels; ++l) {
-            const uint32_t sum = wave_sum<uint32_t>(level_count(r, l));
+            const uint32_t sum = wave_count_total(level_count(r, l));
             if (lane_id() == 0) wtot[l][wave] = sum;
         }
         __syncthreads();
@@ -375,12 +390,12 @@ __global__ __launch_bounds__(kBfBlock) void batch_bf_write_kernel(BatchTreeView 
     for (uint32_t tile = blockIdx.x; tile < tiles && tile < stride; tile += gridDim.x) {
         const size_t first = static_cast<size_t>(tile) * kBfTile + tid * kBfItems;
         const LeafLevels r = entry_levels(src.K, src.M, first);
-        uint32_t c[kLevels], inc[kLevels];
+        uint32_t ex[kLevels];  // this lane's exclusive prefix in its wave, per level
 #pragma unroll
         for (int l = 0; l < kLevels; ++l) {
-            c[l] = level_count(r, l);
-            inc[l] = wave_inclusive_sum(c[l]);
-            if (lane_id() == kWave - 1) wtot[l][wave] = inc[l];
+            uint32_t total;
+            ex[l] = wave_count_prefix(level_count(r, l), &total);
+            if (lane_id() == 0) wtot[l][wave] = total;
         }
         __syncthreads();
 #pragma unroll
@@ -388,7 +403,7 @@ __global__ __launch_bounds__(kBfBlock) void batch_bf_write_kernel(BatchTreeView 
             uint32_t before = 0;
 #pragma unroll
             for (int w = 0; w < kBfWaves; ++w) before += w < static_cast<int>(wave) ? wtot[l][w] : 0u;
-            run[l][tid] = tile_offsets[static_cast<size_t>(l) * stride + tile] + before + inc[l] - c[l];
+            run[l][tid] = tile_offsets[static_cast<size_t>(l) * stride + tile] + before + ex[l];
         }
         // a thread's entries nearly always share one set: its node region is
         // read once per set, not per entry
