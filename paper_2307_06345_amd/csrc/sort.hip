@@ -1007,32 +1007,32 @@ __global__ __launch_bounds__(BLOCK, kLocalBlocksPerCU * BLOCK / (4 * kWave)) voi
         }
     }
     __syncthreads();
-    // bucket starts: the first and last in the chunk, the first after it
-    uint32_t first = 0xffffffffu, last = 0u, after = 0xffffffffu;
+    // bucket starts: the first and last in the chunk, the first after it; the
+    // wave's are read off ballots (item i of lane l sits at i * BLOCK + the
+    // wave's first thread + l, so the lowest and highest set lane give them)
+    uint32_t first = 0xffffffffu, last = 0u, after = 0xffffffffu;  // wave-uniform
+    const uint32_t wave0 = tid - lane_id();
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t j = static_cast<uint32_t>(i) * BLOCK + tid;
+        bool st = false;
         if (j < wn) {
             const uint64_t pj = sm.keys[j] >> pshift;
             const uint64_t pp = j ? sm.keys[j - 1] >> pshift : before;
-            bool st = pj != pp;
+            st = pj != pp;
             if constexpr (SEG) st = st || ((sm.setbits[j >> 5] >> (j & 31u)) & 1u);
-            if (st) {
-                if (j < own) {
-                    first = min(first, j);
-                    last = max(last, j);
-                    // a level-6 node starts here too if the key's top 18 bits changed
-                    const uint32_t up = 45u - pshift;
-                    if (level6 && (pj >> up) != (pp >> up)) level6[pj >> up] = lo + j;
-                } else {
-                    after = min(after, j);
-                }
-            }
+            // a level-6 node starts here too if the key's top 18 bits changed
+            const uint32_t up = 45u - pshift;
+            if (st && j < own && level6 && (pj >> up) != (pp >> up)) level6[pj >> up] = lo + j;
         }
+        const uint64_t in_chunk = __ballot(st && j < own), past = __ballot(st && j >= own);
+        const uint32_t base = static_cast<uint32_t>(i) * BLOCK + wave0;
+        if (in_chunk) {
+            first = min(first, base + static_cast<uint32_t>(__builtin_ctzll(in_chunk)));
+            last = max(last, base + 63u - static_cast<uint32_t>(__builtin_clzll(in_chunk)));
+        }
+        if (past) after = min(after, base + static_cast<uint32_t>(__builtin_ctzll(past)));
     }
-    first = wave_min_u32(first);
-    last = wave_max_u32(last);
-    after = wave_min_u32(after);
     if (lane_id() == 0) {
         if (first != 0xffffffffu) {
             atomicMin(&sm.first, first);
