@@ -235,25 +235,45 @@ __global__ __launch_bounds__(kFineBlock) void start_fine_kernel(const uint64_t* 
 // coarse check found every level-3 node over n_crit.
 __global__ __launch_bounds__(256) void start_mins_kernel(const uint32_t* __restrict__ posf, int lf, LoopState* st,
                                                          int all) {
-    __shared__ uint32_t red[256 / kWave];
+    __shared__ uint32_t red[kStartFine][256 / kWave];
     if (!all && !st->start_fine) return;
     if (all && blockIdx.x == 0 && threadIdx.x == 0) st->start_fine = 1;
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (int k = all ? 0 : kStartCoarse + 1; k < lf; ++k) {
-        const uint32_t nodes = 1u << (3 * k);
-        const uint32_t span = 1u << (3 * (lf - k));
-        uint32_t c = 0xffffffffu;
-        for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < nodes; u += stride)
-            c = min(c, posf[(u + 1) * span] - posf[u * span]);
-        for (int d = 1; d < kWave; d <<= 1) c = min(c, static_cast<uint32_t>(__shfl_xor(static_cast<int>(c), d, kWave)));
-        if (lane_id() == 0) red[threadIdx.x / kWave] = c;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t m = 0xffffffffu;
-            for (int w = 0; w < 256 / kWave; ++w) m = min(m, red[w]);
-            if (m != 0xffffffffu) atomicMin(&st->mins[k], m);
-        }
-        __syncthreads();
+    const int k0 = all ? 0 : kStartCoarse + 1;
+    const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+    uint32_t c[kStartFine];
+    // this thread's first node of every level, all loads in flight at once (a
+    // level outside k0 .. lf - 1, or a node past the level, reads entry 0 and
+    // is not counted); lf <= kStartFine
+#pragma unroll
+    for (int k = 0; k < kStartFine; ++k) {
+        const bool lv = k >= k0 && k < lf;
+        const uint32_t nodes = lv ? 1u << (3 * k) : 0u;
+        const uint32_t span = lv ? 1u << (3 * (lf - k)) : 0u;
+        const uint32_t u = gtid < nodes ? gtid : 0u;
+        const uint32_t hi = posf[(u + 1) * span], lo = posf[u * span];
+        c[k] = gtid < nodes ? hi - lo : 0xffffffffu;
+    }
+    // further nodes, when the grid is smaller than a level
+#pragma unroll
+    for (int k = 0; k < kStartFine; ++k) {
+        if (k < k0 || k >= lf) continue;
+        const uint32_t nodes = 1u << (3 * k), span = 1u << (3 * (lf - k));
+        for (uint32_t u = gtid + stride; u < nodes; u += stride) c[k] = min(c[k], posf[(u + 1) * span] - posf[u * span]);
+    }
+    // wave minima of all levels together, then one barrier and one atomic per level and block
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1)
+#pragma unroll
+        for (int k = 0; k < kStartFine; ++k) c[k] = min(c[k], static_cast<uint32_t>(__shfl_xor(static_cast<int>(c[k]), d, kWave)));
+    if (lane_id() == 0)
+#pragma unroll
+        for (int k = 0; k < kStartFine; ++k) red[k][threadIdx.x / kWave] = c[k];
+    __syncthreads();
+    if (threadIdx.x < static_cast<uint32_t>(kStartFine)) {
+        const int k = static_cast<int>(threadIdx.x);
+        uint32_t m = 0xffffffffu;
+        for (int w = 0; w < 256 / kWave; ++w) m = min(m, red[k][w]);
+        if (k >= k0 && k < lf && m != 0xffffffffu) atomicMin(&st->mins[k], m);
     }
 }
 
